@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of the blaz hot path on one MI355X.
+
+Workload: two 8192x8192 binary64 smooth fields (16 seeded sinusoids of at
+most 8 cycles per side, amplitude U[0.5, 2], + N(0, 1e-3) noise), resident in
+HBM.  One step = compress both, add the compressed matrices (Algorithm 1),
+scale the sum by 1.7 (Algorithm 2, out of place), decompress the result.
+
+value = FP64-equivalent bytes of the step / step time: the bytes the same
+operations move on dense binary64 matrices (compress and decompress 8 n^2
+each, add 3 * 8 n^2, scale 2 * 8 n^2; 64 n^2 per step).
+
+The JSON line also carries, per operation, the time and the actual and
+FP64-equivalent GB/s; the same operations on dense FP64 on this GPU ("plain");
+the roofline of the dominant kernel (compress) from HIP events on its stream;
+a matmul leg (compressed 4096^2 field times dense U[-1, 1]); and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
+RECORD = 45                    # compressed bytes per block
+BLOCK = 512                    # dense bytes per block
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=8192, help="matrix side (default: the 8192 workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-matmul", action="store_true", help="skip the matmul leg")
+    ap.add_argument("--cpu-rows", type=int, default=512, help="rows of each field the oracle times")
+    return ap.parse_args()
+
+
+def elapsed_ms(pairs):
+    return [a.elapsed_time(b) for a, b in pairs]
+
+
+def traffic_for(kernel_src: str, kernel: str):
+    """HBM bytes per launch measured with rocprofv3 counters, if the kernel's
+    source is unchanged since the measurement."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(kernel)
+    if not rec:
+        return None
+    with open(os.path.join(ROOT, kernel_src), "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(A, B, rows):
+    import oracle
+
+    a = A[:rows].copy()
+    b = B[:rows].copy()
+    t0 = time.perf_counter()
+    x = oracle.compress(a)
+    y = oracle.compress(b)
+    z = oracle.add(x, y)
+    w = oracle.scale(z, 1.7)
+    oracle.decompress(w)
+    dt = time.perf_counter() - t0
+    n2 = a.shape[0] * a.shape[1]
+    return {
+        "value": round(64.0 * n2 / dt / 1e9, 4),
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"first {rows} rows of both fields ({a.shape[0]}x{a.shape[1]}, {n2 // 64} blocks each): "
+                  f"same step (compress x2, add, scale, decompress), single-threaded C, {dt:.1f} s",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the per-GPU shard is the measured unit; see the sharding notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2202_13007_amd as blaz
+    from paper_2202_13007_amd import _lib
+    from synth import workload_inputs
+
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    torch.cuda.set_device(0)
+    n = args.n
+    t_gen = time.time()
+    A, B = workload_inputs("plain-8192", n=n)
+    print(f"# inputs generated in {time.time() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    dA = torch.from_numpy(A).cuda()
+    dB = torch.from_numpy(B).cuda()
+    x = blaz.BlazMatrix.empty(n, n)
+    y = blaz.BlazMatrix.empty(n, n)
+    z = blaz.BlazMatrix.empty(n, n)
+    w = blaz.BlazMatrix.empty(n, n)
+    D = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    nblk = x.nblk
+    n2 = n * n
+
+    ops = ("compress_x", "compress_y", "add", "scale", "decompress")
+    ev = {k: [] for k in ops}
+
+    def step(record):
+        def timed(name, fn):
+            if record:
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                fn()
+                b.record()
+                ev[name].append((a, b))
+            else:
+                fn()
+        timed("compress_x", lambda: blaz.compress(dA, out=x))
+        timed("compress_y", lambda: blaz.compress(dB, out=y))
+        timed("add", lambda: blaz.add(x, y, out=z))
+        timed("scale", lambda: blaz.scale(z, 1.7, out=w))
+        timed("decompress", lambda: blaz.decompress(w, out=D))
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        step(True)
+    t1.record()
+    torch.cuda.synchronize()
+    ms_step = t0.elapsed_time(t1) / args.steps
+
+    per = {k: float(np.mean(elapsed_ms(v))) for k, v in ev.items()}
+    bytes_actual = {"compress": (BLOCK + RECORD) * nblk, "add": 3 * RECORD * nblk,
+                    "scale": 2 * RECORD * nblk, "decompress": (RECORD + BLOCK) * nblk}
+    bytes_equiv = {"compress": 8 * n2, "add": 24 * n2, "scale": 16 * n2, "decompress": 8 * n2}
+    op_report = {}
+    for k, ms in per.items():
+        base = k.split("_")[0]
+        op_report[k] = {"ms": round(ms, 5),
+                        "GBps_actual": round(bytes_actual[base] / ms / 1e6, 1),
+                        "GBps_fp64_equiv": round(bytes_equiv[base] / ms / 1e6, 1),
+                        "hbm_frac": round(bytes_actual[base] / ms / 1e6 / HBM_PEAK_GBS, 4)}
+
+    # The same operations on dense binary64 on this GPU (harness only).
+    C = torch.empty_like(dA)
+    plain = {}
+    for name, fn, nbytes in (("add", lambda: torch.add(dA, dB, out=C), 24 * n2),
+                             ("scale", lambda: torch.mul(dA, 1.7, out=C), 16 * n2)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(20):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 20
+        plain[name] = {"ms": round(ms, 5), "GBps": round(nbytes / ms / 1e6, 1),
+                       "blaz_speedup": round(ms / per[name], 2)}
+    del C
+
+    # Roofline of the dominant kernel: compress, 557 algorithmic bytes per block.
+    comp_ms = (per["compress_x"] + per["compress_y"]) / 2
+    achieved = (BLOCK + RECORD) * nblk / comp_ms / 1e6
+    traffic = traffic_for("paper_2202_13007_amd/csrc/codec.hip", "compress_f64_kernel")
+    roofline = {"kernel": "compress_f64_kernel", "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic}
+
+    result = {
+        "metric": "blaz compress+add GB/s (FP64-equiv) vs plain; matmul TFLOP/s; p99 latency",
+        "value": round(64.0 * n2 / ms_step / 1e6, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"plain-{n}: two {n}x{n} binary64 smooth fields (16 sinusoids, <= 8 cycles/side, "
+                               "N(0,1e-3) noise); step = compress x2 + add + scale(1.7) + decompress",
+                   "n": n, "blocks_per_matrix": nblk},
+        "roofline": roofline,
+        "ops": op_report,
+        "plain_dense_fp64": plain,
+    }
+    del dA, dB, D
+
+    if not args.no_matmul:
+        Am, Bm, _ = workload_inputs("linalg-4096")
+        g = blaz.compress(torch.from_numpy(Am).cuda())
+        dBm = torch.from_numpy(Bm).cuda()
+        Cm = torch.empty((4096, 4096), dtype=torch.float64, device="cuda")
+        ws = torch.empty(blaz.matmul_workspace_bytes(4096, 4096, 4096, False), dtype=torch.uint8, device="cuda")
+        Ad = blaz.decompress(g)
+        legs = {}
+        for name, fn in (("blaz_fp64", lambda: blaz.matmul(g, dBm, out=Cm, workspace=ws)),
+                         ("plain_dense_fp64_torch", lambda: torch.matmul(Ad, dBm, out=Cm))):
+            fn()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(5):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / 5
+            tf = 2 * 4096 ** 3 / ms / 1e9
+            legs[name] = {"ms": round(ms, 4), "TFLOPs": round(tf, 2),
+                          "mfma_frac": round(tf / FP64_MFMA_PEAK_TFLOPS, 4)}
+        result["matmul_4096"] = legs
+        del g, dBm, Cm, ws, Ad
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(A, B, min(args.cpu_rows, n))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

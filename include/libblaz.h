@@ -1,0 +1,179 @@
+/*
+ * libblaz.h -- C ABI of the blaz compressed-matrix library for MI355X (gfx950).
+ *
+ * The method is M. Martel, "Compressed Matrix Computations" (arXiv
+ * 2202.13007): a lossy, fixed-rate codec for 8x8 blocks of binary64 (block
+ * splitting, normalization, prediction, DCT-II, quantization; Section
+ * "Compression Scheme") and the operations that run on the compressed form
+ * (addition, Algorithm 1; multiplication by a constant, Algorithm 2) or on
+ * partly decompressed blocks (dot product, Algorithm 3 with Eqs. eqbbb0 and
+ * eqbbb; matrix multiplication, last paragraph of Section "Basic Linear
+ * Algebra Algorithms").
+ *
+ * Conventions for every entry point:
+ *  - Data pointers (matrices, compressed arrays, index and output arrays,
+ *    workspaces) are DEVICE pointers.  The blaz_matrix descriptor itself is
+ *    host memory and is read during the call only.
+ *  - A call validates its arguments synchronously and returns a non-zero
+ *    blaz_status before anything is enqueued; on success the work is
+ *    enqueued on `stream` (0 = the null stream) and the call returns without
+ *    synchronizing.  No call allocates device memory, and none keeps a
+ *    pointer after it returns.
+ *  - A launch failure reported by the HIP runtime returns BLAZ_ERR_HIP.
+ *  - Data conditions are not errors: saturated codes in an addition, phi
+ *    clamps, constant blocks.  Non-finite inputs give unspecified contents
+ *    in the affected blocks.
+ *  - Matrices are row-major binary64 with a leading dimension (elements)
+ *    >= cols.  rows and cols must be multiples of 8 (the paper splits into
+ *    8x8 blocks and gives no padding rule); 0 is allowed and gives an empty
+ *    matrix on which every call is a successful no-op.
+ */
+#ifndef LIBBLAZ_H
+#define LIBBLAZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BLAZ_OK = 0,
+    BLAZ_ERR_NULL = -1,        /* a required pointer is NULL                          */
+    BLAZ_ERR_SHAPE = -2,       /* rows/cols negative or not a multiple of 8, or ld < cols */
+    BLAZ_ERR_MISMATCH = -3,    /* operand shapes do not agree                         */
+    BLAZ_ERR_ALIGN = -4,       /* a pointer is not aligned to its element type         */
+    BLAZ_ERR_ARG = -5,         /* another invalid argument (count < 0, bad enum, overlap) */
+    BLAZ_ERR_UNSUPPORTED = -6, /* a valid request this build does not implement        */
+    BLAZ_ERR_WORKSPACE = -7,   /* workspace missing or smaller than required           */
+    BLAZ_ERR_HIP = -8          /* the HIP runtime reported an error                    */
+} blaz_status;
+
+/* Arithmetic of the DCT stage in blaz_compress and of the contraction in
+ * blaz_matmul.  BLAZ_PREC_FP64 is the plain method and the default. */
+typedef enum {
+    BLAZ_PREC_FP64 = 0,
+    BLAZ_PREC_FP32 = 1,   /* FP32 operands on MFMA, FP32 accumulation               */
+    BLAZ_PREC_BF16X3 = 2  /* operands split into BF16 hi + lo, three MFMA products,  */
+                          /* FP32 accumulation                                       */
+} blaz_precision;
+
+/* A compressed rows x cols matrix: one record per 8x8 block, 45 bytes =
+ * the paper's 360 bits (Section "Compression Scheme", last paragraph), kept
+ * as four arrays.  Block (I, J) -- rows 8I..8I+7, columns 8J..8J+7 -- has
+ * index b = I*(cols/8) + J.
+ *   f[b]        first element M_00 of the block (binary64)
+ *   s[b]        mean slope s, Eq. eqslope (binary64)
+ *   phi[b]      re-scaling factor phi, Eq. eqphi (8-bit unsigned, >= 1)
+ *   codes[28*b + t], t = 0..27
+ *               the kept DCT coefficients trunc(phi * D_ij), int8, for the
+ *               positions of the first two lines and first two columns in
+ *               row-major order: (0,0..7), (1,0..7), (2,0), (2,1), ...,
+ *               (7,0), (7,1).
+ * The caller owns the four arrays (device memory): f and s 8-byte aligned,
+ * codes 4-byte aligned. */
+typedef struct blaz_matrix {
+    int64_t rows;
+    int64_t cols;
+    double *f;
+    double *s;
+    uint8_t *phi;
+    int8_t *codes;
+} blaz_matrix;
+
+/* Number of 8x8 blocks of a rows x cols matrix, or a negative blaz_status
+ * if the shape is invalid. */
+int64_t blaz_block_count(int64_t rows, int64_t cols);
+
+/* Bytes of the compressed form (45 per block), 0 for an invalid shape. */
+size_t blaz_compressed_bytes(int64_t rows, int64_t cols);
+
+/* Compression (Section "Compression Scheme"): block splitting, normalization
+ * (Eq. eqnorm), mean slope (Eqs. eqslope, eqslope2), prediction (Eq.
+ * eqpredict), DCT-II (Eq. eqdct) and quantization (Eq. eqphi) of every
+ * 8x8 block of A (out->rows x out->cols, leading dimension lda >= cols,
+ * 8-byte aligned) into *out.
+ * psi: optional ([nblk][64] uint8, row-major within the block) receives the
+ *   prediction indexes Psi of Eq. eqpredict.  They are not part of the stored
+ *   stream: the transform is applied to the normalized block (the reading
+ *   under which Example 5 is reproduced), so Psi is a side output.  NULL
+ *   skips it.
+ * prec: BLAZ_PREC_FP64 runs every stage in binary64.  BLAZ_PREC_FP32 and
+ *   BLAZ_PREC_BF16X3 run the 63 non-DC DCT coefficients in that arithmetic on
+ *   MFMA; normalization, slope, DC term, phi and truncation stay binary64.
+ * A and the output arrays must not overlap. */
+blaz_status blaz_compress(const double *A, int64_t lda, const blaz_matrix *out, blaz_precision prec,
+                          uint8_t *psi, hipStream_t stream);
+
+/* Decompression: dequantize (C/phi at the kept positions, zero elsewhere;
+ * Section "Dot product"), inverse DCT, and the inverse of the normalization
+ * (Eq. eqbbb read as the exact inverse of Eq. eqnorm) of every block of *in
+ * into A (in->rows x in->cols, leading dimension lda >= cols, 8-byte
+ * aligned).  A must not overlap the compressed arrays. */
+blaz_status blaz_decompress(const blaz_matrix *in, double *A, int64_t lda, hipStream_t stream);
+
+/* Addition of compressed matrices, Algorithm 1, blockwise: z = x + y.
+ * f = f1 + f2; s = s1 + s2; phi = max(1, floor(phi1 phi2 / (phi1 + phi2)));
+ * alpha_k = s_k / s; beta_k = (alpha_k / phi_k) * phi;
+ * C = trunc(beta1 C1 + beta2 C2) saturated to [-127, 127]; C = 0 when s = 0.
+ * All three descriptors must have the same shape; z may be x or y (in
+ * place), otherwise it must not overlap them. */
+blaz_status blaz_add(const blaz_matrix *x, const blaz_matrix *y, const blaz_matrix *z, hipStream_t stream);
+
+/* Subtraction z = x - y, which the paper says works like the addition:
+ * Algorithm 1 applied to x and (-1) * y (Algorithm 2), fused in one pass.
+ * Same shape and aliasing rules as blaz_add. */
+blaz_status blaz_sub(const blaz_matrix *x, const blaz_matrix *y, const blaz_matrix *z, hipStream_t stream);
+
+/* Multiplication by a constant, Algorithm 2, blockwise: z = c x.
+ * f and s are multiplied by c; phi and the codes are copied (not touched
+ * when z == x, the in-place form). */
+blaz_status blaz_scale(const blaz_matrix *x, double c, const blaz_matrix *z, hipStream_t stream);
+
+/* Dot products, Algorithm 3 with Eqs. eqbbb0 and eqbbb applied blockwise:
+ * out[q] = sum_k X[xrow[q], k] * Y[k, ycol[q]] over the decompressed values,
+ * for q = 0..count-1.  Only the lines 0..(xrow mod 8) of the blocks of X and
+ * the columns 0..(ycol mod 8) of the blocks of Y that the product needs are
+ * rebuilt.  x->cols must equal y->rows.  xrow and ycol are device arrays of
+ * count int64; an index outside its matrix yields out[q] = NaN. */
+blaz_status blaz_dot(const blaz_matrix *x, const int64_t *xrow, const blaz_matrix *y, const int64_t *ycol,
+                     int64_t count, double *out, hipStream_t stream);
+
+/* Dot products of lines of a compressed matrix with dense vectors:
+ * out[q] = sum_k X[xrow[q], k] * v[q*ldv + k].  ldv = 0 uses one vector for
+ * every q; otherwise ldv >= x->cols.  v is 16-byte aligned and, when
+ * ldv != 0, ldv is even.  An index outside X yields NaN. */
+blaz_status blaz_dot_dense(const blaz_matrix *x, const int64_t *xrow, const double *v, int64_t ldv,
+                           int64_t count, double *out, hipStream_t stream);
+
+/* Bytes of workspace blaz_matmul needs for an m x k times k x n product
+ * (b_compressed != 0: B is compressed too). */
+size_t blaz_matmul_workspace_bytes(int64_t m, int64_t n, int64_t k, int b_compressed, blaz_precision prec);
+
+/* Matrix multiplication on partly decompressed operands (last paragraph of
+ * Section "Basic Linear Algebra Algorithms"): every block of A (and of B when
+ * it is compressed) is decompressed once into the workspace, then the
+ * product C = A B (m x n, leading dimension ldc >= n) is formed on the
+ * matrix cores; m = a->rows, k = a->cols.  B is either compressed
+ * (b != NULL with b->rows == k and b->cols == n, bdense == NULL) or dense
+ * binary64 (b == NULL, bdense k x n with leading dimension ldb >= n, ldb
+ * even, 16-byte aligned).  k == 0 writes zeros to C.
+ * prec selects the contraction arithmetic (FP64, FP32, or BF16x3 with FP32
+ * accumulation); the output is binary64 in every case.  workspace must hold
+ * blaz_matmul_workspace_bytes() bytes, 256-byte aligned.  C must not overlap
+ * the inputs or the workspace. */
+blaz_status blaz_matmul(const blaz_matrix *a, const blaz_matrix *b, const double *bdense, int64_t n,
+                        int64_t ldb, double *c, int64_t ldc, blaz_precision prec, void *workspace,
+                        size_t ws_bytes, hipStream_t stream);
+
+/* A static description of a status code. */
+const char *blaz_status_string(blaz_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBBLAZ_H */

@@ -1,0 +1,9 @@
+"""libblaz for MI355X: the blaz compressed-matrix method (arXiv 2202.13007) on gfx950.
+
+The library itself is the C ABI in include/libblaz.h, implemented by the HIP
+kernels under csrc/ and built into libblaz.so.  This package is its thin
+Python binding (``api``) and the build script (``_build``).
+"""
+from .api import (BlazMatrix, add, compress, decompress, dot, dot_dense, matmul,  # noqa: F401
+                  matmul_workspace_bytes, scale, sub)
+from ._lib import BlazError, EXPORTS, LIB_PATH  # noqa: F401

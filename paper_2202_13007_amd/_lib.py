@@ -1,0 +1,93 @@
+"""ctypes loader for libblaz.so (the C ABI declared in include/libblaz.h).
+
+The library is built in-tree by ``paper_2202_13007_amd._build``.  Loading
+fails loudly when it is missing: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libblaz.so")
+
+BLAZ_OK = 0
+STATUS_NAMES = {
+    0: "BLAZ_OK", -1: "BLAZ_ERR_NULL", -2: "BLAZ_ERR_SHAPE", -3: "BLAZ_ERR_MISMATCH",
+    -4: "BLAZ_ERR_ALIGN", -5: "BLAZ_ERR_ARG", -6: "BLAZ_ERR_UNSUPPORTED",
+    -7: "BLAZ_ERR_WORKSPACE", -8: "BLAZ_ERR_HIP",
+}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+# Every symbol include/libblaz.h declares.
+EXPORTS = (
+    "blaz_block_count", "blaz_compressed_bytes", "blaz_compress", "blaz_decompress", "blaz_add",
+    "blaz_sub", "blaz_scale", "blaz_dot", "blaz_dot_dense", "blaz_matmul_workspace_bytes",
+    "blaz_matmul", "blaz_status_string",
+)
+
+
+class BlazMatrixC(ctypes.Structure):
+    """Mirror of ``blaz_matrix``: shape plus four device pointers."""
+    _fields_ = [
+        ("rows", ctypes.c_int64),
+        ("cols", ctypes.c_int64),
+        ("f", ctypes.c_void_p),
+        ("s", ctypes.c_void_p),
+        ("phi", ctypes.c_void_p),
+        ("codes", ctypes.c_void_p),
+    ]
+
+
+class BlazError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)} ({_status_string(status)})")
+
+
+_lib = None
+
+
+def _status_string(status: int) -> str:
+    try:
+        return lib().blaz_status_string(status).decode()
+    except Exception:  # pragma: no cover - only used while formatting an error
+        return "?"
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libblaz.so not found at {LIB_PATH}: build it with "
+                           "`python -m paper_2202_13007_amd._build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, D, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    M = ctypes.POINTER(BlazMatrixC)
+    sig = {
+        "blaz_block_count": ([I64, I64], I64),
+        "blaz_compressed_bytes": ([I64, I64], ctypes.c_size_t),
+        "blaz_compress": ([P, I64, M, I, P, P], I),
+        "blaz_decompress": ([M, P, I64, P], I),
+        "blaz_add": ([M, M, M, P], I),
+        "blaz_sub": ([M, M, M, P], I),
+        "blaz_scale": ([M, D, M, P], I),
+        "blaz_dot": ([M, P, M, P, I64, P, P], I),
+        "blaz_dot_dense": ([M, P, P, I64, I64, P, P], I),
+        "blaz_matmul_workspace_bytes": ([I64, I64, I64, I, I], ctypes.c_size_t),
+        "blaz_matmul": ([M, M, P, I64, I64, P, I64, I, P, ctypes.c_size_t, P], I),
+        "blaz_status_string": ([I], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def check(status: int, what: str) -> None:
+    if status != BLAZ_OK:
+        raise BlazError(status, what)

@@ -1,0 +1,184 @@
+"""Python face of libblaz: argument marshalling only.
+
+torch provides device memory and the current stream; every step runs in the
+HIP kernels behind the C ABI.  All functions take and return tensors on the
+current HIP device and enqueue on ``torch.cuda.current_stream()`` without
+synchronizing.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import BlazMatrixC, check
+
+NKEPT = 28
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class BlazMatrix:
+    """A compressed rows x cols matrix on the device (45 bytes per 8x8 block).
+
+    f, s: float64 [nblk]; phi: uint8 [nblk]; codes: int8 [nblk, 28].
+    Block (I, J) is entry I*(cols/8) + J.
+    """
+    rows: int
+    cols: int
+    f: torch.Tensor
+    s: torch.Tensor
+    phi: torch.Tensor
+    codes: torch.Tensor
+
+    @property
+    def nblk(self) -> int:
+        return (self.rows // 8) * (self.cols // 8)
+
+    @property
+    def nbytes(self) -> int:
+        return self.f.nbytes + self.s.nbytes + self.phi.nbytes + self.codes.nbytes
+
+    @staticmethod
+    def empty(rows: int, cols: int, device=None) -> "BlazMatrix":
+        n = _lib.lib().blaz_block_count(rows, cols)
+        if n < 0:
+            raise _lib.BlazError(int(n), f"BlazMatrix.empty({rows}, {cols})")
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        return BlazMatrix(rows, cols,
+                          torch.empty(n, dtype=torch.float64, device=dev),
+                          torch.empty(n, dtype=torch.float64, device=dev),
+                          torch.empty(n, dtype=torch.uint8, device=dev),
+                          torch.empty((n, NKEPT), dtype=torch.int8, device=dev))
+
+    def c(self) -> BlazMatrixC:
+        return BlazMatrixC(self.rows, self.cols, self.f.data_ptr(), self.s.data_ptr(),
+                           self.phi.data_ptr(), self.codes.data_ptr())
+
+    def to_host(self):
+        """(f, s, phi, codes) as numpy arrays (synchronizes)."""
+        return (self.f.cpu().numpy(), self.s.cpu().numpy(), self.phi.cpu().numpy(),
+                self.codes.cpu().numpy())
+
+    @staticmethod
+    def from_host(rows, cols, f, s, phi, codes, device=None) -> "BlazMatrix":
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        return BlazMatrix(rows, cols,
+                          torch.as_tensor(f, dtype=torch.float64).to(dev).contiguous(),
+                          torch.as_tensor(s, dtype=torch.float64).to(dev).contiguous(),
+                          torch.as_tensor(phi, dtype=torch.uint8).to(dev).contiguous(),
+                          torch.as_tensor(codes, dtype=torch.int8).reshape(-1, NKEPT).to(dev).contiguous())
+
+
+def _check_dense(A: torch.Tensor, what: str):
+    if A.dtype != torch.float64 or A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
+        raise ValueError(f"{what}: expected a 2-D float64 CUDA tensor with unit column stride")
+
+
+def compress(A: torch.Tensor, out: BlazMatrix | None = None, prec: str = "fp64",
+             psi: torch.Tensor | None = None) -> BlazMatrix:
+    """Compress a float64 matrix (rows, cols multiples of 8)."""
+    _check_dense(A, "compress")
+    rows, cols = A.shape
+    if out is None:
+        out = BlazMatrix.empty(rows, cols, A.device)
+    m = out.c()
+    check(_lib.lib().blaz_compress(_ptr(A), A.stride(0), ctypes.byref(m), _lib.PREC[prec], _ptr(psi),
+                                   _stream()), "blaz_compress")
+    return out
+
+
+def decompress(x: BlazMatrix, out: torch.Tensor | None = None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty((x.rows, x.cols), dtype=torch.float64, device=x.f.device)
+    _check_dense(out, "decompress")
+    m = x.c()
+    check(_lib.lib().blaz_decompress(ctypes.byref(m), _ptr(out), out.stride(0), _stream()), "blaz_decompress")
+    return out
+
+
+def add(x: BlazMatrix, y: BlazMatrix, out: BlazMatrix | None = None) -> BlazMatrix:
+    out = BlazMatrix.empty(x.rows, x.cols, x.f.device) if out is None else out
+    mx, my, mz = x.c(), y.c(), out.c()
+    check(_lib.lib().blaz_add(ctypes.byref(mx), ctypes.byref(my), ctypes.byref(mz), _stream()), "blaz_add")
+    return out
+
+
+def sub(x: BlazMatrix, y: BlazMatrix, out: BlazMatrix | None = None) -> BlazMatrix:
+    out = BlazMatrix.empty(x.rows, x.cols, x.f.device) if out is None else out
+    mx, my, mz = x.c(), y.c(), out.c()
+    check(_lib.lib().blaz_sub(ctypes.byref(mx), ctypes.byref(my), ctypes.byref(mz), _stream()), "blaz_sub")
+    return out
+
+
+def scale(x: BlazMatrix, c: float, out: BlazMatrix | None = None) -> BlazMatrix:
+    """out = c * x; pass out=x for the in-place form."""
+    out = BlazMatrix.empty(x.rows, x.cols, x.f.device) if out is None else out
+    mx, mz = x.c(), out.c()
+    check(_lib.lib().blaz_scale(ctypes.byref(mx), float(c), ctypes.byref(mz), _stream()), "blaz_scale")
+    return out
+
+
+def dot(x: BlazMatrix, xrow: torch.Tensor, y: BlazMatrix, ycol: torch.Tensor,
+        out: torch.Tensor | None = None) -> torch.Tensor:
+    """out[q] = <line xrow[q] of x, column ycol[q] of y> (int64 device index tensors)."""
+    count = xrow.numel()
+    if ycol.numel() != count or xrow.dtype != torch.int64 or ycol.dtype != torch.int64:
+        raise ValueError("dot: xrow and ycol must be int64 tensors of one length")
+    out = torch.empty(count, dtype=torch.float64, device=x.f.device) if out is None else out
+    mx, my = x.c(), y.c()
+    check(_lib.lib().blaz_dot(ctypes.byref(mx), _ptr(xrow.contiguous()), ctypes.byref(my),
+                              _ptr(ycol.contiguous()), count, _ptr(out), _stream()), "blaz_dot")
+    return out
+
+
+def dot_dense(x: BlazMatrix, xrow: torch.Tensor, v: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """out[q] = <line xrow[q] of x, v[q]> (v 2-D [count, >= cols]) or with one shared 1-D v."""
+    count = xrow.numel()
+    if xrow.dtype != torch.int64:
+        raise ValueError("dot_dense: xrow must be int64")
+    if v.dim() == 1:
+        ldv = 0
+    else:
+        if v.stride(1) != 1 or v.shape[0] != count:
+            raise ValueError("dot_dense: v must be [count, >= cols] with unit column stride")
+        ldv = v.stride(0)
+    out = torch.empty(count, dtype=torch.float64, device=x.f.device) if out is None else out
+    mx = x.c()
+    check(_lib.lib().blaz_dot_dense(ctypes.byref(mx), _ptr(xrow.contiguous()), _ptr(v), ldv, count, _ptr(out),
+                                    _stream()), "blaz_dot_dense")
+    return out
+
+
+def matmul_workspace_bytes(m: int, n: int, k: int, b_compressed: bool, prec: str = "fp64") -> int:
+    return int(_lib.lib().blaz_matmul_workspace_bytes(m, n, k, int(b_compressed), _lib.PREC[prec]))
+
+
+def matmul(a: BlazMatrix, b: BlazMatrix | torch.Tensor, out: torch.Tensor | None = None, prec: str = "fp64",
+           workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """C = A B with A compressed and B compressed or dense float64; C dense float64."""
+    compressed_b = isinstance(b, BlazMatrix)
+    n = b.cols if compressed_b else b.shape[1]
+    if not compressed_b:
+        _check_dense(b, "matmul B")
+    if out is None:
+        out = torch.empty((a.rows, n), dtype=torch.float64, device=a.f.device)
+    need = matmul_workspace_bytes(a.rows, n, a.cols, compressed_b, prec)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=a.f.device)
+    ma = a.c()
+    mb = b.c() if compressed_b else None
+    check(_lib.lib().blaz_matmul(ctypes.byref(ma), ctypes.byref(mb) if compressed_b else None,
+                                 None if compressed_b else _ptr(b), n, 0 if compressed_b else b.stride(0),
+                                 _ptr(out), out.stride(0), _lib.PREC[prec], _ptr(workspace),
+                                 workspace.numel(), _stream()), "blaz_matmul")
+    return out

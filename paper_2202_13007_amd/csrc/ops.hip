@@ -1,0 +1,135 @@
+// Operations on compressed blocks: addition (Algorithm 1), subtraction (the
+// addition applied to x and -y) and multiplication by a constant
+// (Algorithm 2).
+//
+// Mapping: one lane per block.  The per-block work is a handful of binary64
+// divisions and 28 multiply-adds, so a lane can own a whole record; a wave
+// then reads 64 consecutive records, i.e. contiguous runs of f, s, phi and
+// codes, and the kernels stay bound by HBM rather than by instruction issue.
+#include <hip/hip_runtime.h>
+
+#include "blaz_device.hpp"
+#include "blaz_internal.hpp"
+
+namespace blaz {
+
+template <bool kNegY>
+__global__ __launch_bounds__(256) void add_kernel(const double* f1, const double* s1,
+                                                  const uint8_t* phi1,
+                                                  const uint32_t* c1, const double* f2,
+                                                  const double* s2, const uint8_t* phi2,
+                                                  const uint32_t* c2, int64_t nblk, double* fo,
+                                                  double* so, uint8_t* phio, uint32_t* co)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblk) return;
+    // z may alias x or y: every input of block b is read before it is written.
+    // Algorithm 1, line 1: f = f1 + f2, s = s1 + s2 (y negated for subtraction,
+    // which is exact).
+    const double fy = kNegY ? -f2[b] : f2[b];
+    const double sy = kNegY ? -s2[b] : s2[b];
+    const double sx = s1[b];
+    const double f = f1[b] + fy;
+    const double s = sx + sy;
+    // Line 2 and Eq. eq55: phi = phi1 phi2 / (phi1 + phi2), integer division,
+    // kept >= 1 so that the block can be decompressed.
+    const int p1 = phi1[b], p2 = phi2[b];
+    int p = p1 + p2 > 0 ? (p1 * p2) / (p1 + p2) : 1;
+    p = p < 1 ? 1 : p;
+
+    uint32_t wx[kCodeWords], wy[kCodeWords], wo[kCodeWords];
+#pragma unroll
+    for (int q = 0; q < kCodeWords; ++q) {
+        wx[q] = c1[b * kCodeWords + q];
+        wy[q] = c2[b * kCodeWords + q];
+        wo[q] = 0;
+    }
+    if (s != 0.0) {
+        // Lines 3-4: alpha_k = s_k / s, beta_k = (alpha_k / phi_k) * phi.
+        const double a1 = sx / s;
+        const double a2 = sy / s;
+        const double b1 = a1 / (double)p1 * (double)p;
+        const double b2 = a2 / (double)p2 * (double)p;
+        // Lines 5-7: C = trunc(beta1 C1 + beta2 C2), saturated to +-127.
+        // Two products then one sum, never fused (the library is built with
+        // -ffp-contract=off), so the result is reproducible bit for bit.
+#pragma unroll
+        for (int t = 0; t < kKept; ++t) {
+            const int32_t cx = (int32_t)(wx[t / 4] << (24 - 8 * (t % 4))) >> 24;
+            const int32_t cy = (int32_t)(wy[t / 4] << (24 - 8 * (t % 4))) >> 24;
+            const double v = b1 * (double)cx + b2 * (double)cy;
+            const double tv = fmin(fmax(trunc(v), -127.0), 127.0);
+            wo[t / 4] |= ((uint32_t)(int32_t)tv & 0xffu) << (8 * (t % 4));
+        }
+    }
+    fo[b] = f;
+    so[b] = s;
+    phio[b] = (uint8_t)p;
+#pragma unroll
+    for (int q = 0; q < kCodeWords; ++q) co[b * kCodeWords + q] = wo[q];
+}
+
+// Algorithm 2 in place: only f and s change.
+__global__ __launch_bounds__(256) void scale_inplace_kernel(double* f, double* s, double c, int64_t nblk)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblk) return;
+    f[b] = f[b] * c;
+    s[b] = s[b] * c;
+}
+
+// Algorithm 2 out of place: f and s times c, phi and the codes copied.
+__global__ __launch_bounds__(256) void scale_kernel(const double* __restrict__ f1, const double* __restrict__ s1,
+                                                    const uint8_t* phi1,
+                                                    const uint32_t* __restrict__ c1, double c, int64_t nblk,
+                                                    double* __restrict__ fo, double* __restrict__ so,
+                                                    uint8_t* __restrict__ phio, uint32_t* __restrict__ co)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nblk) {
+        fo[b] = f1[b] * c;
+        so[b] = s1[b] * c;
+        phio[b] = phi1[b];
+    }
+    // The codes are copied as one flat dword stream (7 dwords per block) so
+    // that consecutive lanes touch consecutive dwords.
+    const int64_t total = nblk * kCodeWords;
+    const int64_t base = (int64_t)blockIdx.x * blockDim.x * kCodeWords + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < kCodeWords; ++q) {
+        const int64_t i = base + (int64_t)q * blockDim.x;
+        if (i < total) co[i] = c1[i];
+    }
+}
+
+namespace detail {
+
+hipError_t launch_add(const blaz_matrix& x, const blaz_matrix& y, const blaz_matrix& z, bool negate_y,
+                      hipStream_t st)
+{
+    const int64_t nblk = (x.rows / 8) * (x.cols / 8);
+    const unsigned grid = (unsigned)((nblk + 255) / 256);
+    auto cw = [](const blaz_matrix& m) { return reinterpret_cast<uint32_t*>(m.codes); };
+    if (negate_y)
+        add_kernel<true><<<grid, 256, 0, st>>>(x.f, x.s, x.phi, cw(x), y.f, y.s, y.phi, cw(y), nblk, z.f, z.s,
+                                               z.phi, cw(z));
+    else
+        add_kernel<false><<<grid, 256, 0, st>>>(x.f, x.s, x.phi, cw(x), y.f, y.s, y.phi, cw(y), nblk, z.f, z.s,
+                                                z.phi, cw(z));
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(const blaz_matrix& x, double c, const blaz_matrix& z, hipStream_t st)
+{
+    const int64_t nblk = (x.rows / 8) * (x.cols / 8);
+    const unsigned grid = (unsigned)((nblk + 255) / 256);
+    if (z.f == x.f && z.s == x.s && z.phi == x.phi && z.codes == x.codes)
+        scale_inplace_kernel<<<grid, 256, 0, st>>>(z.f, z.s, c, nblk);
+    else
+        scale_kernel<<<grid, 256, 0, st>>>(x.f, x.s, x.phi, reinterpret_cast<const uint32_t*>(x.codes), c, nblk,
+                                           z.f, z.s, z.phi, reinterpret_cast<uint32_t*>(z.codes));
+    return hipGetLastError();
+}
+
+}  // namespace detail
+}  // namespace blaz

@@ -1,0 +1,416 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Every case feeds the same seeded arrays to both sides.  Rules in parity.py.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2202_13007_amd as blaz
+from synth import smooth_field, uniform_matrix, workload_inputs
+
+from parity import (TIE_RATE_MAX, assert_blocks_close, assert_dots_close, assert_same_compressed,
+                    compare_compressed, near_integer)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    blaz._lib.lib()  # fails loudly if libblaz.so is missing
+    yield
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_compress(A, psi=False, lda_pad=0, misalign=False):
+    """Compress with the library; A is uploaded inside a wider buffer when
+    lda_pad > 0 and at an 8-byte (not 16-byte) offset when misalign."""
+    rows, cols = A.shape
+    off = 1 if misalign else 0
+    big = np.zeros((rows, cols + lda_pad + off))
+    big[:, off:off + cols] = A
+    t = dev(big)[:, off:off + cols]
+    p = torch.empty((max(1, (rows // 8) * (cols // 8)), 64), dtype=torch.uint8, device="cuda") if psi else None
+    m = blaz.compress(t, psi=p)
+    torch.cuda.synchronize()
+    return (m, p.cpu().numpy() if psi else None)
+
+
+def host(m):
+    return m.to_host()
+
+
+def upload(c: oracle.Compressed):
+    return blaz.BlazMatrix.from_host(c.rows, c.cols, c.f, c.s, c.phi, c.codes)
+
+
+def oracle_tuple(c):
+    return (c.f, c.s, c.phi, c.codes)
+
+
+# --------------------------------------------------------------------------
+# Compression
+# --------------------------------------------------------------------------
+
+def check_compress(A, what, max_ties=0, **kw):
+    g, _ = gpu_compress(A, **kw)
+    o, (_, code_x, phi_x) = oracle.compress(A, with_debug=True)
+    ties = compare_compressed(host(g), oracle_tuple(o), code_x, phi_x, what)
+    assert ties <= max_ties, f"{what}: {ties} boundary ties"
+    return ties
+
+
+def test_compress_plain_64_workload():
+    """Two 64x64 smooth fields (4 sinusoids, <= 2 cycles/side, N(0, 1e-3))."""
+    A, B = workload_inputs("plain-64")
+    check_compress(A, "A")
+    check_compress(B, "B")
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (8, 24), (24, 8), (64, 64), (264, 520), (1032, 528)])
+def test_compress_shapes(shape):
+    """Single block, one block row/column, and grids with ragged workgroup tails."""
+    r, c = shape
+    A = smooth_field(r, 8, 4.0, 1e-3, 1000 + r + c, cols=c) * 3.0 - 1.0
+    check_compress(A, f"compress {shape}")
+
+
+@pytest.mark.parametrize("lda_pad,misalign", [(8, False), (3, False), (0, True), (5, True)])
+def test_compress_leading_dimension(lda_pad, misalign):
+    A = smooth_field(72, 6, 3.0, 1e-3, 77, cols=136)
+    check_compress(A, f"compress lda+{lda_pad} misalign={misalign}", lda_pad=lda_pad, misalign=misalign)
+
+
+def special_blocks():
+    """One block row of designed blocks."""
+    u = np.arange(8.0)
+    blocks = [
+        np.full((8, 8), 2.5),                                   # constant: K = 0
+        np.zeros((8, 8)),                                       # all zero
+        0.01 * np.outer(u, u),                                  # Example 1
+        np.outer(0.1 * u, 0.1 * u),                             # Example 1, other rounding
+        1.25 + 0.3 * u[:, None] - 0.7 * u[None, :],             # affine
+        np.cumsum(np.cumsum(np.full((8, 8), 0.37), 0), 1),      # sign-consistent (K = 63)
+        np.where((u[:, None] + u[None, :]) % 2 == 0, 1.0, -1.0),  # checkerboard
+        np.eye(8) * 1e-3,                                       # sparse
+        np.pad(np.array([[1e-3]]), ((7, 0), (7, 0))),           # one non-zero Delta: phi clamps
+        1e300 * np.sin(u[:, None] + 2 * u[None, :]),            # huge magnitudes
+        1e-300 * np.cos(u[:, None] - u[None, :]),               # tiny magnitudes
+        -np.exp(0.1 * (u[:, None] + u[None, :])),               # negative, smooth
+    ]
+    return np.hstack(blocks)
+
+
+def test_compress_special_blocks():
+    A = special_blocks()
+    ties = check_compress(A, "special blocks", max_ties=8)
+    print(f"special blocks: {ties} boundary ties")
+
+
+def test_compress_prediction_side_output():
+    """Eq. eqpredict: Psi equals the oracle's brute-force argmin except at
+    half-way ties."""
+    A = np.vstack([smooth_field(64, 4, 2.0, 1e-3, 5), special_blocks()[:, :64]])
+    g, psi = gpu_compress(A, psi=True)
+    o, (opsi, _, _) = oracle.compress(A, with_debug=True)
+    diff = psi.astype(int) - opsi.astype(int)
+    for b, e in zip(*np.nonzero(diff)):
+        I, J = divmod(b, A.shape[1] // 8)
+        tr = oracle.compress_block(A[8 * I:8 * I + 8, 8 * J:8 * J + 8])
+        dp = tr.arr("dprime").ravel()[e]
+        smax = np.max(np.abs(tr.arr("dprime")))
+        q = (dp - (tr.s - smax)) / (2 * smax / 256)
+        assert abs(diff[b, e]) == 1 and abs(q - np.floor(q) - 0.5) < 1e-9, f"psi block {b} elt {e}"
+
+
+def test_compress_full_size_8192_sampled():
+    """8192x8192 field (16 sinusoids, <= 8 cycles/side): every block on the GPU,
+    a sample of blocks on the oracle, properties on all blocks."""
+    A, _ = workload_inputs("plain-8192")
+    g, _ = gpu_compress(A)
+    gf, gs, gphi, gcodes = host(g)
+    nbc = A.shape[1] // 8
+    rng = np.random.default_rng(0)
+    sample = np.unique(np.concatenate([[0, 1, nbc - 1, nbc, len(gf) - 1],
+                                       rng.integers(0, len(gf), 3000)]))
+    of, os_, ophi, ocodes, code_x, phi_x = oracle.compress_blocks(A, sample)
+    ties = compare_compressed((gf[sample], gs[sample], gphi[sample], gcodes[sample]),
+                              (of, os_, ophi, ocodes), code_x, phi_x, "8192 sampled")
+    assert ties <= 1
+    # properties on every block
+    np.testing.assert_array_equal(gf, A[::8, ::8].ravel())
+    assert np.all(gs > 0) and np.all(gphi >= 1)
+    assert np.all(np.abs(gcodes.astype(int)) <= 127)
+
+
+# --------------------------------------------------------------------------
+# Decompression
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(64, 64), (8, 8), (24, 8), (264, 520)])
+def test_decompress(shape):
+    r, c = shape
+    A = smooth_field(r, 6, 3.0, 1e-3, 300 + r, cols=c)
+    o = oracle.compress(A)
+    got = blaz.decompress(upload(o)).cpu().numpy()
+    assert_blocks_close(got, oracle.decompress(o))
+
+
+def test_decompress_special_blocks_and_leading_dimension():
+    o = oracle.compress(special_blocks())
+    want = oracle.decompress(o)
+    x = upload(o)
+    big = torch.zeros((8, want.shape[1] + 5), dtype=torch.float64, device="cuda")
+    blaz.decompress(x, out=big[:, 1:1 + want.shape[1]])
+    got = big.cpu().numpy()
+    assert_blocks_close(got[:, 1:1 + want.shape[1]], want)
+    assert np.all(got[:, 0] == 0) and np.all(got[:, 1 + want.shape[1]:] == 0)
+    # a constant block comes back bit-exact
+    np.testing.assert_array_equal(got[:, 1:9], np.full((8, 8), 2.5))
+
+
+def test_decompress_random_records():
+    """Any valid record (phi >= 1, codes in [-127, 127]) decodes like the oracle."""
+    rng = np.random.default_rng(9)
+    nb = 4 * 9
+    c = oracle.Compressed(32, 72, rng.standard_normal(nb), rng.standard_normal(nb) * 0.1,
+                          rng.integers(1, 256, nb).astype(np.uint8),
+                          rng.integers(-127, 128, (nb, 28)).astype(np.int8))
+    assert_blocks_close(blaz.decompress(upload(c)).cpu().numpy(), oracle.decompress(c))
+
+
+def test_compress_then_decompress_full_size_sampled():
+    """8192x8192: GPU round trip equals the oracle's decompression of the
+    GPU's own codes (sampled blocks), and the method's error is a few percent."""
+    A, _ = workload_inputs("plain-8192")
+    g, _ = gpu_compress(A)
+    back = blaz.decompress(g).cpu().numpy()
+    gf, gs, gphi, gcodes = host(g)
+    rng = np.random.default_rng(1)
+    nbc = A.shape[1] // 8
+    for b in np.unique(np.concatenate([[0, len(gf) - 1], rng.integers(0, len(gf), 400)])):
+        I, J = divmod(int(b), nbc)
+        want = oracle.decompress_block(gf[b], gs[b], gphi[b], gcodes[b])
+        blk = back[8 * I:8 * I + 8, 8 * J:8 * J + 8]
+        assert np.max(np.abs(blk - want)) <= 1e-12 * np.max(np.abs(want)), f"block {b}"
+    rel = np.linalg.norm(back - A) / np.linalg.norm(A)
+    assert rel < 0.05
+
+
+# --------------------------------------------------------------------------
+# Add, subtract, scale (Algorithms 1 and 2): bit-exact
+# --------------------------------------------------------------------------
+
+def random_records(rows, cols, seed, phi_lo=1):
+    rng = np.random.default_rng(seed)
+    nb = (rows // 8) * (cols // 8)
+    return oracle.Compressed(rows, cols, rng.standard_normal(nb) * 10, rng.standard_normal(nb),
+                             rng.integers(phi_lo, 256, nb).astype(np.uint8),
+                             rng.integers(-127, 128, (nb, 28)).astype(np.int8))
+
+
+def add_cases():
+    A, B = workload_inputs("plain-64")
+    x, y = oracle.compress(A), oracle.compress(B)
+    yield "fields", x, y
+    yield "self", x, x
+    yield "opposite slopes cancel", x, oracle.scale(x, -1.0)
+    yield "near cancellation saturates", x, oracle.scale(y, -0.97)
+    r1, r2 = random_records(72, 520, 3), random_records(72, 520, 4)
+    yield "random records", r1, r2
+    r3 = random_records(72, 520, 5)
+    r3.phi[:] = 1
+    yield "phi = 1", r1, r3
+    r4 = r2.copy()
+    r4.s[::3] = 0.0
+    yield "zero slopes", r1, r4
+
+
+@pytest.mark.parametrize("case", range(7))
+def test_add_bit_exact(case):
+    name, x, y = list(add_cases())[case]
+    got = host(blaz.add(upload(x), upload(y)))
+    assert_same_compressed(got, oracle_tuple(oracle.add(x, y)), f"add {name}")
+
+
+@pytest.mark.parametrize("case", range(7))
+def test_sub_bit_exact(case):
+    """Subtraction = Algorithm 1 on x and (-1) y."""
+    name, x, y = list(add_cases())[case]
+    got = host(blaz.sub(upload(x), upload(y)))
+    assert_same_compressed(got, oracle_tuple(oracle.add(x, oracle.scale(y, -1.0))), f"sub {name}")
+
+
+def test_add_in_place():
+    x, y = random_records(16, 1032, 6), random_records(16, 1032, 7)
+    gx, gy = upload(x), upload(y)
+    blaz.add(gx, gy, out=gx)
+    assert_same_compressed(host(gx), oracle_tuple(oracle.add(x, y)), "add in place (z = x)")
+    gx2, gy2 = upload(x), upload(y)
+    blaz.add(gx2, gy2, out=gy2)
+    assert_same_compressed(host(gy2), oracle_tuple(oracle.add(x, y)), "add in place (z = y)")
+
+
+@pytest.mark.parametrize("c", [1.7, -2.0, 0.0, 1e-300])
+def test_scale_bit_exact(c):
+    x = random_records(40, 264, 8)
+    want = oracle_tuple(oracle.scale(x, c))
+    assert_same_compressed(host(blaz.scale(upload(x), c)), want, f"scale {c}")
+    gx = upload(x)
+    blaz.scale(gx, c, out=gx)
+    assert_same_compressed(host(gx), want, f"scale {c} in place")
+
+
+def test_add_scale_full_size_8192_sampled():
+    """8192x8192 compressed add and scale, sampled blocks against the oracle."""
+    A, B = workload_inputs("plain-8192")
+    gx, _ = gpu_compress(A)
+    gy, _ = gpu_compress(B)
+    gz = blaz.add(gx, gy)
+    gw = blaz.scale(gz, 1.7)
+    xh, yh, zh, wh = host(gx), host(gy), host(gz), host(gw)
+    rng = np.random.default_rng(2)
+    smp = np.unique(np.concatenate([[0, len(xh[0]) - 1], rng.integers(0, len(xh[0]), 5000)]))
+    pick = lambda t: oracle.Compressed(8, 8 * len(smp), t[0][smp], t[1][smp], t[2][smp], t[3][smp])
+    oz = oracle.add(pick(xh), pick(yh))
+    assert_same_compressed(tuple(a[smp] for a in zh), oracle_tuple(oz), "add 8192 sampled")
+    assert_same_compressed(tuple(a[smp] for a in wh), oracle_tuple(oracle.scale(oz, 1.7)), "scale 8192 sampled")
+
+
+# --------------------------------------------------------------------------
+# Dot products and matrix multiplication
+# --------------------------------------------------------------------------
+
+def test_dot_compressed():
+    """Algorithm 3 blockwise: line i of X times column j of Y."""
+    X = smooth_field(24, 4, 2.0, 1e-3, 400, cols=1040)
+    Y = smooth_field(1040, 4, 2.0, 1e-3, 401, cols=40)
+    ox, oy = oracle.compress(X), oracle.compress(Y)
+    rng = np.random.default_rng(3)
+    rows = np.concatenate([np.arange(24), rng.integers(0, 24, 40)])
+    cols = np.concatenate([np.arange(24) % 40, rng.integers(0, 40, 40)])
+    got = blaz.dot(upload(ox), dev(rows), upload(oy), dev(cols)).cpu().numpy()
+    want = oracle.dot(ox, rows, oy, cols)
+    Xd, Yd = oracle.decompress(ox), oracle.decompress(oy)
+    mag = np.array([np.abs(Xd[i]) @ np.abs(Yd[:, j]) for i, j in zip(rows, cols)])
+    assert_dots_close(got, want, mag, what="dot")
+
+
+def test_dot_invalid_index_gives_nan():
+    ox = oracle.compress(smooth_field(16, 2, 1.0, 0, 1))
+    got = blaz.dot(upload(ox), dev(np.array([0, 16, -1, 3])), upload(ox), dev(np.array([0, 0, 1, 99]))).cpu().numpy()
+    assert np.isfinite(got[0]) and np.isnan(got[1]) and np.isnan(got[2]) and np.isnan(got[3])
+
+
+@pytest.mark.parametrize("shared", [False, True])
+def test_dot_dense(shared):
+    X = smooth_field(48, 4, 2.0, 1e-3, 410, cols=1096)
+    ox = oracle.compress(X)
+    rows = np.arange(48)[::-1].copy()
+    V = uniform_matrix(1 if shared else 48, 1096, 411)
+    v = V[0] if shared else V
+    got = blaz.dot_dense(upload(ox), dev(rows), dev(v)).cpu().numpy()
+    want = oracle.dot_dense(ox, rows, v, 0 if shared else 1096)
+    Xd = oracle.decompress(ox)
+    mag = np.array([np.abs(Xd[i]) @ np.abs(V[0 if shared else q]) for q, i in enumerate(rows)])
+    assert_dots_close(got, want, mag, what="dot_dense")
+
+
+def band_rows(og: oracle.Compressed, i: int) -> np.ndarray:
+    """Line i of a compressed matrix, decompressed by the oracle (its block row only)."""
+    nbc = og.cols // 8
+    I = i // 8
+    sl = slice(I * nbc, (I + 1) * nbc)
+    band = oracle.Compressed(8, og.cols, og.f[sl], og.s[sl], og.phi[sl], og.codes[sl])
+    return oracle.decompress(band)[i % 8]
+
+
+def test_dot_dense_full_size_4096_sampled():
+    """4096 dot products of compressed lines with their own dense vectors."""
+    A, _, V = workload_inputs("linalg-4096")
+    g, _ = gpu_compress(A)
+    rows = np.arange(4096)
+    got = blaz.dot_dense(g, dev(rows), dev(V)).cpu().numpy()
+    og = oracle.Compressed(4096, 4096, *host(g))
+    smp = np.array([0, 7, 8, 2047, 4095] + list(np.random.default_rng(4).integers(0, 4096, 15)))
+    want = oracle.dot_dense(og, rows[smp], V[smp], 4096)
+    mag = np.array([np.abs(band_rows(og, int(i))) @ np.abs(V[i]) for i in smp])
+    assert_dots_close(got[smp], want, mag, what="dot_dense 4096")
+
+
+def test_dot_equals_matmul_element():
+    """Section "Accuracy Measurements": dot(i, j) is element (i, j) of the product."""
+    X = smooth_field(64, 4, 2.0, 1e-3, 420)
+    Y = smooth_field(64, 4, 2.0, 1e-3, 421)
+    gx, gy = upload(oracle.compress(X)), upload(oracle.compress(Y))
+    P = blaz.matmul(gx, gy).cpu().numpy()
+    rows = np.repeat(np.arange(64), 64)
+    cols = np.tile(np.arange(64), 64)
+    d = blaz.dot(gx, dev(rows), gy, dev(cols)).cpu().numpy().reshape(64, 64)
+    Xd, Yd = oracle.decompress(oracle.compress(X)), oracle.decompress(oracle.compress(Y))
+    mag = np.abs(Xd) @ np.abs(Yd)
+    assert np.all(np.abs(d - P) <= 2e-12 * mag)
+
+
+def test_matmul_plain_64_workload():
+    """64x64 partly-decompressed product of the two compressed fields."""
+    A, B = workload_inputs("plain-64")
+    ox, oy = oracle.compress(A), oracle.compress(B)
+    got = blaz.matmul(upload(ox), upload(oy)).cpu().numpy()
+    Xd, Yd = oracle.decompress(ox), oracle.decompress(oy)
+    want = oracle.gemm(Xd, Yd)
+    assert_dots_close(got, want, np.abs(Xd) @ np.abs(Yd), what="matmul 64")
+
+
+@pytest.mark.parametrize("m,k,n", [(136, 200, 72), (8, 8, 8), (256, 64, 392), (392, 136, 264)])
+def test_matmul_dense_b_ragged(m, k, n):
+    A = smooth_field(m, 4, 2.0, 1e-3, 430 + m, cols=k)
+    B = uniform_matrix(k, n, 431)
+    ox = oracle.compress(A)
+    got = blaz.matmul(upload(ox), dev(B)).cpu().numpy()
+    Xd = oracle.decompress(ox)
+    want = oracle.gemm(Xd, B)
+    assert_dots_close(got, want, np.abs(Xd) @ np.abs(B), what=f"matmul {m}x{k}x{n}")
+
+
+def test_matmul_leading_dimensions():
+    A = smooth_field(64, 4, 2.0, 1e-3, 440, cols=128)
+    B = uniform_matrix(128, 72, 441)
+    ox = oracle.compress(A)
+    Bbig = np.zeros((128, 80))
+    Bbig[:, :72] = B
+    Cbig = torch.full((64, 90), 7.0, dtype=torch.float64, device="cuda")
+    blaz.matmul(upload(ox), dev(Bbig)[:, :72], out=Cbig[:, 4:76])
+    got = Cbig.cpu().numpy()
+    Xd = oracle.decompress(ox)
+    assert_dots_close(got[:, 4:76], oracle.gemm(Xd, B), np.abs(Xd) @ np.abs(B), what="matmul ld")
+    assert np.all(got[:, :4] == 7.0) and np.all(got[:, 76:] == 7.0)
+
+
+def test_matmul_full_size_4096_sampled():
+    """Compressed 4096x4096 field times dense U[-1, 1]: sampled entries, each
+    computed by the oracle as a line of the decompressed A times a column of B."""
+    A, B, _ = workload_inputs("linalg-4096")
+    g, _ = gpu_compress(A)
+    C = blaz.matmul(g, dev(B)).cpu().numpy()
+    og = oracle.Compressed(4096, 4096, *host(g))
+    rng = np.random.default_rng(5)
+    ij = [(0, 0), (4095, 4095), (127, 128), (128, 127)] + [tuple(rng.integers(0, 4096, 2)) for _ in range(12)]
+    for i, j in ij:
+        bj = np.ascontiguousarray(B[:, j])
+        want = oracle.dot_dense(og, [i], bj, 0)[0]
+        mag = np.abs(band_rows(og, int(i))) @ np.abs(bj)
+        assert abs(C[i, j] - want) <= 1e-12 * mag, (i, j, C[i, j], want)
+
+
+def test_empty_and_k0():
+    z = blaz.BlazMatrix.empty(0, 16)
+    blaz.compress(torch.empty((0, 16), dtype=torch.float64, device="cuda"), out=z)
+    a = blaz.BlazMatrix.empty(16, 0)
+    C = blaz.matmul(a, torch.empty((0, 24), dtype=torch.float64, device="cuda"))
+    assert C.shape == (16, 24) and torch.all(C == 0)

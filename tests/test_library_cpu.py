@@ -1,0 +1,168 @@
+"""Host-side checks of libblaz that need no GPU: the library loads, exports
+every entry point include/libblaz.h declares, and rejects invalid arguments
+before enqueuing anything (these calls never reach the HIP runtime).
+Also checks of the parity rules themselves."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "libblaz.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2202_13007_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2202_13007_amd import _build
+        _build.build()
+    return _lib.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(blaz_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    from paper_2202_13007_amd import _lib
+    names = declared_functions()
+    assert len(names) >= 12
+    assert sorted(_lib.EXPORTS) == names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_no_other_symbols_exported(L):
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", L._name], capture_output=True, text=True).stdout
+    syms = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert {s for s in syms if s.startswith("blaz_")} == set(declared_functions())
+
+
+def test_block_count_and_bytes(L):
+    assert L.blaz_block_count(16, 24) == 6
+    assert L.blaz_block_count(0, 8) == 0
+    assert L.blaz_block_count(8, 12) == -2
+    assert L.blaz_block_count(-8, 8) == -2
+    assert L.blaz_compressed_bytes(16, 16) == 4 * 45
+    assert L.blaz_compressed_bytes(8192, 8192) == 47185920
+    assert L.blaz_compressed_bytes(7, 8) == 0
+
+
+def test_status_strings(L):
+    for st in range(-8, 1):
+        assert len(L.blaz_status_string(st)) > 5
+
+
+def mat(rows, cols, base):
+    from paper_2202_13007_amd._lib import BlazMatrixC
+    nb = max(0, (rows // 8) * (cols // 8))
+    # fake device addresses, laid out without overlap; never dereferenced
+    return BlazMatrixC(rows, cols, base, base + 8 * nb + 64, base + 16 * nb + 128,
+                       base + (17 * nb + 256 + 15) // 16 * 16)
+
+
+B = ctypes.byref
+
+
+def test_compress_validation(L):
+    out = mat(16, 16, 0x100000)
+    A = 0x200000
+    assert L.blaz_compress(None, 16, B(out), 0, None, None) == -1
+    assert L.blaz_compress(A, 8, B(out), 0, None, None) == -2          # lda < cols
+    assert L.blaz_compress(A + 4, 16, B(out), 0, None, None) == -4     # misaligned A
+    assert L.blaz_compress(A, 16, B(out), 9, None, None) == -5         # bad precision
+    assert L.blaz_compress(0x100000, 16, B(out), 0, None, None) == -5  # A overlaps the output
+    bad = mat(12, 16, 0x100000)
+    assert L.blaz_compress(A, 16, B(bad), 0, None, None) == -2
+    nul = mat(16, 16, 0x100000)
+    nul.codes = None
+    assert L.blaz_compress(A, 16, B(nul), 0, None, None) == -1
+    mis = mat(16, 16, 0x100000)
+    mis.codes = 0x100002
+    assert L.blaz_compress(A, 16, B(mis), 0, None, None) == -4
+    assert L.blaz_compress(A, 16, B(out), 0, 0x300008, None) == -4    # psi not 16-aligned
+    empty = mat(0, 16, 0)
+    assert L.blaz_compress(None, 16, B(empty), 0, None, None) == 0    # empty: no-op
+
+
+def test_decompress_validation(L):
+    x = mat(16, 16, 0x100000)
+    assert L.blaz_decompress(B(x), None, 16, None) == -1
+    assert L.blaz_decompress(B(x), 0x200000, 15, None) == -2
+    assert L.blaz_decompress(B(x), 0x200001, 16, None) == -4
+    assert L.blaz_decompress(B(x), 0x100000 - 64, 16, None) == -5    # overlaps f
+
+
+def test_add_scale_validation(L):
+    x, y, z = mat(16, 16, 0x100000), mat(16, 16, 0x200000), mat(16, 16, 0x300000)
+    w = mat(16, 24, 0x400000)
+    assert L.blaz_add(B(x), B(w), B(z), None) == -3
+    assert L.blaz_sub(B(x), B(y), B(w), None) == -3
+    part = mat(16, 16, 0x100000 + 8)                                  # overlaps x, not equal
+    assert L.blaz_add(B(x), B(y), B(part), None) == -5
+    assert L.blaz_scale(B(x), 2.0, B(part), None) == -5
+    assert L.blaz_scale(B(x), 2.0, B(w), None) == -3
+    assert L.blaz_add(None, B(y), B(z), None) == -1
+    e = mat(0, 0, 0)
+    assert L.blaz_add(B(e), B(e), B(e), None) == 0
+
+
+def test_dot_validation(L):
+    x, y = mat(16, 24, 0x100000), mat(24, 8, 0x200000)
+    idx, out = 0x300000, 0x400000
+    assert L.blaz_dot(B(x), idx, B(x), idx, 4, out, None) == -3     # 24 != 16
+    assert L.blaz_dot(B(x), idx, B(y), idx, -1, out, None) == -5
+    assert L.blaz_dot(B(x), None, B(y), idx, 4, out, None) == -1
+    assert L.blaz_dot(B(x), idx + 4, B(y), idx, 4, out, None) == -4
+    assert L.blaz_dot(B(x), idx, B(y), idx, 0, None, None) == 0       # count 0: no-op
+    assert L.blaz_dot_dense(B(x), idx, 0x500008, 0, 4, out, None) == -4   # v not 16-aligned
+    assert L.blaz_dot_dense(B(x), idx, 0x500000, 23, 4, out, None) == -2  # ldv < cols
+    assert L.blaz_dot_dense(B(x), idx, 0x500000, 25, 4, out, None) == -4  # odd ldv
+    assert L.blaz_dot_dense(B(x), idx, 0x500000, -2, 4, out, None) == -5
+
+
+def test_matmul_validation(L):
+    a, b = mat(16, 24, 0x100000), mat(24, 8, 0x200000)
+    C, ws = 0x300000, 0x400000
+    need = L.blaz_matmul_workspace_bytes(16, 8, 24, 1, 0)
+    assert need >= 8 * (16 * 24 + 24 * 8)
+    assert L.blaz_matmul(B(a), B(b), 0x500000, 8, 8, C, 8, 0, ws, need, None) == -5   # both B forms
+    assert L.blaz_matmul(B(a), None, None, 8, 8, C, 8, 0, ws, need, None) == -5       # no B
+    assert L.blaz_matmul(B(a), B(b), None, 16, 8, C, 16, 0, ws, need, None) == -3     # n != b.cols
+    assert L.blaz_matmul(B(a), B(b), None, 8, 8, C, 8, 0, ws, need - 8, None) == -7
+    assert L.blaz_matmul(B(a), B(b), None, 8, 8, C, 8, 0, None, need, None) == -7
+    assert L.blaz_matmul(B(a), B(b), None, 8, 8, C, 8, 0, ws + 8, need, None) == -4
+    assert L.blaz_matmul(B(a), B(b), None, 8, 8, C, 4, 0, ws, need, None) == -2       # ldc < n
+    assert L.blaz_matmul(B(a), None, 0x500008, 8, 8, C, 8, 0, ws, need, None) == -4   # B not 16-aligned
+    assert L.blaz_matmul(B(a), B(b), None, 8, 8, ws, 8, 0, ws, need, None) == -5      # C overlaps ws
+    assert L.blaz_matmul(B(a), B(b), None, 8, 8, C, 8, 5, ws, need, None) == -5       # bad precision
+
+
+# --------------------------------------------------------------------------
+# The parity rules (tests/parity.py) catch what they should
+# --------------------------------------------------------------------------
+
+def test_tie_classifier():
+    from parity import compare_compressed
+    f, s = np.zeros(2), np.ones(2)
+    phi = np.array([20, 20], np.uint8)
+    codes = np.zeros((2, 28), np.int8)
+    code_x = np.full((2, 28), 0.5)
+    code_x[0, 0] = 126.0 - 1e-14          # a boundary tie
+    codes_o = codes.copy()
+    codes_o[0, 0] = 125
+    codes_g = codes.copy()
+    codes_g[0, 0] = 126
+    ties = compare_compressed((f, s, phi, codes_g), (f, s, phi, codes_o), code_x, np.array([20.5, 20.5]))
+    assert ties == 1
+    code_x[0, 0] = 125.7                   # not near an integer: a real mismatch
+    with pytest.raises(AssertionError):
+        compare_compressed((f, s, phi, codes_g), (f, s, phi, codes_o), code_x, np.array([20.5, 20.5]))
+    with pytest.raises(AssertionError):    # s must be bit-exact
+        compare_compressed((f, s + 1e-16 * 4, phi, codes), (f, s, phi, codes), code_x, np.array([20.5, 20.5]))
