@@ -112,7 +112,9 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
         }
     }
 
-    // Accumulator layout: lane holds D[4*(lane/16) + r][lane%16], r = 0..3.
+    // Accumulator layout of v_mfma_f64_16x16x4_f64: value r (0..3) of a lane
+    // holds D[4*r + lane/16][lane%16] (unlike the FP32/BF16 16x16 forms,
+    // whose value r holds row 4*(lane/16) + r).
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
             const int64_t gc = col0 + wn * 64 + j * 16 + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t gr = row0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+                const int64_t gr = row0 + wm * 64 + i * 16 + 4 * r + (lane >> 4);
                 if (gr < M && gc < N) C[gr * ldc + gc] = acc[i][j][r];
             }
         }
