@@ -160,7 +160,8 @@ size_t blaz_matmul_workspace_bytes(int64_t m, int64_t n, int64_t k, int b_compre
  * matrix cores; m = a->rows, k = a->cols.  B is either compressed
  * (b != NULL with b->rows == k and b->cols == n, bdense == NULL) or dense
  * binary64 (b == NULL, bdense k x n with leading dimension ldb >= n, ldb
- * even, 16-byte aligned).  k == 0 writes zeros to C.
+ * even, 16-byte aligned; it may be NULL only when k == 0).  Passing both
+ * forms is BLAZ_ERR_ARG.  k == 0 writes zeros to C.
  * prec selects the contraction arithmetic (FP64, FP32, or BF16x3 with FP32
  * accumulation); the output is binary64 in every case.  workspace must hold
  * blaz_matmul_workspace_bytes() bytes, 256-byte aligned.  C must not overlap

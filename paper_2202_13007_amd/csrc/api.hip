@@ -202,7 +202,8 @@ BLAZ_API blaz_status blaz_matmul(const blaz_matrix* a, const blaz_matrix* b, con
                                  size_t ws_bytes, hipStream_t stream)
 {
     if (blaz_status st = check_matrix(a)) return st;
-    if ((b == nullptr) == (bdense == nullptr)) return BLAZ_ERR_ARG;
+    if (b && bdense) return BLAZ_ERR_ARG;  // exactly one form of B
+    if (!b && !bdense && a->cols > 0) return BLAZ_ERR_NULL;
     if (prec != BLAZ_PREC_FP64 && prec != BLAZ_PREC_FP32 && prec != BLAZ_PREC_BF16X3) return BLAZ_ERR_ARG;
     if (prec != BLAZ_PREC_FP64) return BLAZ_ERR_UNSUPPORTED;
     const int64_t m = a->rows, k = a->cols;

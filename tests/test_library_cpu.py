@@ -133,7 +133,7 @@ def test_matmul_validation(L):
     need = L.blaz_matmul_workspace_bytes(16, 8, 24, 1, 0)
     assert need >= 8 * (16 * 24 + 24 * 8)
     assert L.blaz_matmul(B(a), B(b), 0x500000, 8, 8, C, 8, 0, ws, need, None) == -5   # both B forms
-    assert L.blaz_matmul(B(a), None, None, 8, 8, C, 8, 0, ws, need, None) == -5       # no B
+    assert L.blaz_matmul(B(a), None, None, 8, 8, C, 8, 0, ws, need, None) == -1       # no B
     assert L.blaz_matmul(B(a), B(b), None, 16, 8, C, 16, 0, ws, need, None) == -3     # n != b.cols
     assert L.blaz_matmul(B(a), B(b), None, 8, 8, C, 8, 0, ws, need - 8, None) == -7
     assert L.blaz_matmul(B(a), B(b), None, 8, 8, C, 8, 0, None, need, None) == -7
