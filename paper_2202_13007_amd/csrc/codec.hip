@@ -4,9 +4,9 @@
 // Mapping: one lane per 8x8 block.  A block's 64 values live in the lane's
 // VGPRs for the whole pipeline, so normalization, the two slope reductions,
 // both 8-point transform passes and the max reduction are plain in-register
-// arithmetic with no cross-lane traffic and no LDS round trips.  A wave owns
-// 64 consecutive blocks of a block row, so each of the 8 row loads of a wave
-// reads one contiguous 4 KiB segment (64 lanes x 64 B) of the matrix.
+// arithmetic with no cross-lane traffic.  A workgroup is one wave owning 64
+// consecutive blocks; its HBM traffic is staged through LDS (below) so that
+// every global access instruction covers a contiguous run.
 #include <hip/hip_runtime.h>
 
 #include "blaz_device.hpp"
@@ -33,45 +33,6 @@ __device__ __forceinline__ double pairwise64(F v)
     return t[0];
 }
 
-template <bool kVec>
-__device__ __forceinline__ void load_block(const double* __restrict__ src, int64_t lda, double x[64])
-{
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const double* row = src + r * lda;
-        if constexpr (kVec) {
-#pragma unroll
-            for (int c = 0; c < 8; c += 2) {
-                const f64x2 v = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(row + c));
-                x[r * 8 + c] = v[0];
-                x[r * 8 + c + 1] = v[1];
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < 8; ++c) x[r * 8 + c] = row[c];
-        }
-    }
-}
-
-template <bool kVec>
-__device__ __forceinline__ void store_block(double* __restrict__ dst, int64_t lda, const double x[64])
-{
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        double* row = dst + r * lda;
-        if constexpr (kVec) {
-#pragma unroll
-            for (int c = 0; c < 8; c += 2) {
-                const f64x2 v = {x[r * 8 + c], x[r * 8 + c + 1]};
-                __builtin_nontemporal_store(v, reinterpret_cast<f64x2*>(row + c));
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < 8; ++c) row[c] = x[r * 8 + c];
-        }
-    }
-}
-
 // Normalization, Eq. eqnorm, in place.  Processing from the bottom-right
 // corner backwards keeps every left and upper neighbour unmodified when it is
 // read.  The interior term is ((M - Mup) + (M - Mleft)) * 0.5 exactly as
@@ -91,20 +52,106 @@ __device__ __forceinline__ void normalize(double x[64])
     x[0] = 0.0;
 }
 
-template <bool kVec, bool kPsi>
-__global__ __launch_bounds__(256) void compress_f64_kernel(const double* __restrict__ A, int64_t lda,
-                                                           int64_t nbc, int64_t nblk, double* __restrict__ fo,
-                                                           double* __restrict__ so, uint8_t* __restrict__ phio,
-                                                           uint32_t* __restrict__ codes,
-                                                           uint8_t* __restrict__ psi)
+// ---------------------------------------------------------------------------
+// Wave-cooperative staging.  A workgroup is one wave of 64 lanes owning 64
+// consecutive blocks.  Row r of those blocks is moved between HBM and the
+// lanes' registers through a 5 KiB LDS tile: every global instruction moves
+// 16 B per lane over a contiguous 1 KiB run (4 lanes per block row segment,
+// 16 blocks per instruction), and each lane then reads or writes its own
+// block's 64 B in LDS.  The tile gives each lane a 80-byte slot (64 B of data
+// + 16 B of padding) so that the per-lane LDS accesses spread over all banks.
+// ---------------------------------------------------------------------------
+constexpr int kWave = 64;
+constexpr int kSlot = 10;  // doubles per lane slot in the LDS tile
+
+// Global offsets (in doubles, row 0) of the four 16-byte chunks a lane moves:
+// chunk k covers part (lane & 3) of block wave_base + (lane >> 2) + 16 k.
+struct WaveChunks {
+    int64_t off[4];
+    bool ok[4];
+};
+
+__device__ __forceinline__ WaveChunks wave_chunks(int64_t wave_base, int lane, int64_t nbc, int64_t nblk,
+                                                  int64_t lda)
 {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nblk) return;
-    const int64_t I = b / nbc;
-    const int64_t J = b - I * nbc;
+    WaveChunks w;
+    int64_t I0 = 0, J0 = 0;
+    if (nbc >= kWave) {  // wave-uniform: the 64 blocks wrap into the next block row at most once
+        I0 = wave_base / nbc;
+        J0 = wave_base - I0 * nbc;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int q = (lane >> 2) + 16 * k;
+        const int64_t bb = wave_base + q;
+        int64_t I, J;
+        if (nbc >= kWave) {
+            I = I0;
+            J = J0 + q;
+            if (J >= nbc) {
+                J -= nbc;
+                ++I;
+            }
+        } else {
+            I = bb / nbc;
+            J = bb - I * nbc;
+        }
+        w.ok[k] = bb < nblk;
+        w.off[k] = (8 * I) * lda + 8 * J + 2 * (lane & 3);
+    }
+    return w;
+}
+
+template <bool kVec, bool kPsi>
+__global__ __launch_bounds__(kWave) void compress_f64_kernel(const double* __restrict__ A, int64_t lda,
+                                                             int64_t nbc, int64_t nblk, double* __restrict__ fo,
+                                                             double* __restrict__ so, uint8_t* __restrict__ phio,
+                                                             uint32_t* __restrict__ codes,
+                                                             uint8_t* __restrict__ psi)
+{
+    __shared__ __align__(16) double tile[kWave * kSlot];
+    const int lane = threadIdx.x;
+    const int64_t wave_base = (int64_t)blockIdx.x * kWave;
+    const int64_t b = wave_base + lane;
+    const bool valid = b < nblk;
 
     double x[64];
-    load_block<kVec>(A + (I * 8) * lda + J * 8, lda, x);
+    if constexpr (kVec) {
+        const WaveChunks wc = wave_chunks(wave_base, lane, nbc, nblk, lda);
+        f64x2 g[8][4];
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                g[r][k] = wc.ok[k] ? __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(A + wc.off[k] + r * lda))
+                                   : f64x2{0.0, 0.0};
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                *reinterpret_cast<f64x2*>(&tile[((lane >> 2) + 16 * k) * kSlot + 2 * (lane & 3)]) = g[r][k];
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const f64x2 v = *reinterpret_cast<const f64x2*>(&tile[lane * kSlot + 2 * p]);
+                x[r * 8 + 2 * p] = v[0];
+                x[r * 8 + 2 * p + 1] = v[1];
+            }
+            __syncthreads();
+        }
+    } else {
+        if (valid) {
+            const int64_t I = b / nbc, J = b - (b / nbc) * nbc;
+            const double* src = A + (I * 8) * lda + J * 8;
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) x[r * 8 + c] = src[r * lda + c];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 64; ++e) x[e] = 0.0;
+        }
+    }
     const double f = x[0];
 
     // Normalization (Eq. eqnorm) and mean slope (Eqs. eqslope, eqslope2).
@@ -148,9 +195,11 @@ __global__ __launch_bounds__(256) void compress_f64_kernel(const double* __restr
                 w[e / 4] |= (uint32_t)k << (8 * (e % 4));
             }
         }
-        uint4* dst = reinterpret_cast<uint4*>(psi + b * 64);
+        if (valid) {
+            uint4* dst = reinterpret_cast<uint4*>(psi + b * 64);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+            for (int q = 0; q < 4; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+        }
     }
 
     // Two-dimensional DCT-II (Eq. eqdct): rows, then columns, in place.
@@ -177,57 +226,108 @@ __global__ __launch_bounds__(256) void compress_f64_kernel(const double* __restr
         w[t / 4] |= ((uint32_t)c & 0xffu) << (8 * (t % 4));
     }
 
-    fo[b] = f;
-    so[b] = s;
-    phio[b] = (uint8_t)phi;
-    uint32_t* cw = codes + b * kCodeWords;
+    if (valid) {
+        fo[b] = f;
+        so[b] = s;
+        phio[b] = (uint8_t)phi;
+    }
+    // The wave's codes are one contiguous run of 64 * 28 bytes: packed in LDS,
+    // then written as consecutive dwords.
+    uint32_t* ct = reinterpret_cast<uint32_t*>(tile);
 #pragma unroll
-    for (int q = 0; q < kCodeWords; ++q) cw[q] = w[q];
+    for (int q = 0; q < kCodeWords; ++q) ct[lane * kCodeWords + q] = w[q];
+    __syncthreads();
+    const int64_t nwords = (nblk - wave_base < kWave ? nblk - wave_base : kWave) * kCodeWords;
+    uint32_t* cdst = codes + wave_base * kCodeWords;
+#pragma unroll
+    for (int k = 0; k < kCodeWords; ++k) {
+        const int idx = lane + kWave * k;
+        if (idx < nwords) cdst[idx] = ct[idx];
+    }
 }
 
 template <bool kVec>
-__global__ __launch_bounds__(256) void decompress_kernel(const double* __restrict__ f, const double* __restrict__ s,
-                                                         const uint8_t* __restrict__ phi,
-                                                         const uint32_t* __restrict__ codes, int64_t nbc,
-                                                         int64_t nblk, double* __restrict__ A, int64_t lda)
+__global__ __launch_bounds__(kWave) void decompress_kernel(const double* __restrict__ f, const double* __restrict__ s,
+                                                           const uint8_t* __restrict__ phi,
+                                                           const uint32_t* __restrict__ codes, int64_t nbc,
+                                                           int64_t nblk, double* __restrict__ A, int64_t lda)
 {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nblk) return;
-    const int64_t I = b / nbc;
-    const int64_t J = b - I * nbc;
+    __shared__ __align__(16) double tile[kWave * kSlot];
+    const int lane = threadIdx.x;
+    const int64_t wave_base = (int64_t)blockIdx.x * kWave;
+    const int64_t b = wave_base + lane;
+    const bool valid = b < nblk;
 
+    // The wave's codes: consecutive dwords into LDS, then each lane's 7.
+    uint32_t* ct = reinterpret_cast<uint32_t*>(tile);
+    const int64_t nwords = (nblk - wave_base < kWave ? nblk - wave_base : kWave) * kCodeWords;
+    const uint32_t* csrc = codes + wave_base * kCodeWords;
+#pragma unroll
+    for (int k = 0; k < kCodeWords; ++k) {
+        const int idx = lane + kWave * k;
+        if (idx < nwords) ct[idx] = csrc[idx];
+    }
+    __syncthreads();
     uint32_t w[kCodeWords];
 #pragma unroll
-    for (int q = 0; q < kCodeWords; ++q) w[q] = codes[b * kCodeWords + q];
+    for (int q = 0; q < kCodeWords; ++q) w[q] = ct[lane * kCodeWords + q];
+    __syncthreads();
+
+    const double fb = valid ? f[b] : 0.0;
+    const double sb = valid ? s[b] : 0.0;
+    const double pb = valid ? (double)phi[b] : 1.0;
     // Dhat = C / phi at the kept positions (zero elsewhere); the slope factor
     // of Eq. eqbbb is folded in by linearity of the inverse DCT.
     double coef[kKept];
-    unpack_codes(w, s[b] / (double)phi[b], coef);
+    unpack_codes(w, sb / pb, coef);
     double x[64];
     inverse_transform(coef, x);
-    inverse_normalize(f[b], x);
-    store_block<kVec>(A + (I * 8) * lda + J * 8, lda, x);
+    inverse_normalize(fb, x);
+
+    if constexpr (kVec) {
+        const WaveChunks wc = wave_chunks(wave_base, lane, nbc, nblk, lda);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+                *reinterpret_cast<f64x2*>(&tile[lane * kSlot + 2 * p]) = f64x2{x[r * 8 + 2 * p], x[r * 8 + 2 * p + 1]};
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const f64x2 v = *reinterpret_cast<const f64x2*>(&tile[((lane >> 2) + 16 * k) * kSlot + 2 * (lane & 3)]);
+                if (wc.ok[k]) __builtin_nontemporal_store(v, reinterpret_cast<f64x2*>(A + wc.off[k] + r * lda));
+            }
+            __syncthreads();
+        }
+    } else if (valid) {
+        const int64_t I = b / nbc, J = b - (b / nbc) * nbc;
+        double* dst = A + (I * 8) * lda + J * 8;
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) dst[r * lda + c] = x[r * 8 + c];
+    }
 }
 
 namespace detail {
 
-static inline unsigned grid_for(int64_t nblk, int threads) { return (unsigned)((nblk + threads - 1) / threads); }
+static inline unsigned grid_for(int64_t nblk) { return (unsigned)((nblk + kWave - 1) / kWave); }
 
 hipError_t launch_compress_f64(const double* A, int64_t lda, const blaz_matrix& m, uint8_t* psi, hipStream_t st)
 {
     const int64_t nbc = m.cols / 8;
     const int64_t nblk = (m.rows / 8) * nbc;
     const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % 2 == 0);
-    const unsigned grid = grid_for(nblk, 256);
+    const unsigned grid = grid_for(nblk);
     auto* cw = reinterpret_cast<uint32_t*>(m.codes);
     if (vec && psi)
-        compress_f64_kernel<true, true><<<grid, 256, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw, psi);
+        compress_f64_kernel<true, true><<<grid, kWave, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw, psi);
     else if (vec)
-        compress_f64_kernel<true, false><<<grid, 256, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw, psi);
+        compress_f64_kernel<true, false><<<grid, kWave, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw, psi);
     else if (psi)
-        compress_f64_kernel<false, true><<<grid, 256, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw, psi);
+        compress_f64_kernel<false, true><<<grid, kWave, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw, psi);
     else
-        compress_f64_kernel<false, false><<<grid, 256, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw, psi);
+        compress_f64_kernel<false, false><<<grid, kWave, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw, psi);
     return hipGetLastError();
 }
 
@@ -236,12 +336,12 @@ hipError_t launch_decompress(const blaz_matrix& m, double* A, int64_t lda, hipSt
     const int64_t nbc = m.cols / 8;
     const int64_t nblk = (m.rows / 8) * nbc;
     const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % 2 == 0);
-    const unsigned grid = grid_for(nblk, 256);
+    const unsigned grid = grid_for(nblk);
     const auto* cw = reinterpret_cast<const uint32_t*>(m.codes);
     if (vec)
-        decompress_kernel<true><<<grid, 256, 0, st>>>(m.f, m.s, m.phi, cw, nbc, nblk, A, lda);
+        decompress_kernel<true><<<grid, kWave, 0, st>>>(m.f, m.s, m.phi, cw, nbc, nblk, A, lda);
     else
-        decompress_kernel<false><<<grid, 256, 0, st>>>(m.f, m.s, m.phi, cw, nbc, nblk, A, lda);
+        decompress_kernel<false><<<grid, kWave, 0, st>>>(m.f, m.s, m.phi, cw, nbc, nblk, A, lda);
     return hipGetLastError();
 }
 
