@@ -90,6 +90,49 @@ def cpu_baseline(A, B, rows):
     }
 
 
+def matmul_leg(blaz, torch, workload_inputs):
+    """Compressed 4096^2 field A times dense U[-1, 1] B in FP64, FP32 and
+    BF16x3, against torch's FP64 product of the decompressed A ("plain").
+    Errors: each precision against the FP64 path (relative Frobenius), and the
+    method's own error, |A_hat B - A B| / |A B| with A the uncompressed field."""
+    Am, Bm, _ = workload_inputs("linalg-4096")
+    n = Am.shape[0]
+    dA = torch.from_numpy(Am).cuda()
+    g = blaz.compress(dA)
+    dB = torch.from_numpy(Bm).cuda()
+    ws = torch.empty(max(blaz.matmul_workspace_bytes(n, n, n, False, p) for p in ("fp64", "fp32", "bf16x3")),
+                     dtype=torch.uint8, device="cuda")
+    Ad = blaz.decompress(g)
+    outs = {p: torch.empty((n, n), dtype=torch.float64, device="cuda") for p in ("fp64", "fp32", "bf16x3", "plain")}
+    legs = {}
+    runs = [(p, (lambda p=p: blaz.matmul(g, dB, out=outs[p], prec=p, workspace=ws))) for p in ("fp64", "fp32", "bf16x3")]
+    runs.append(("plain", lambda: torch.matmul(Ad, dB, out=outs["plain"])))
+    peaks = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3, "plain": 78.6}
+    for name, fn in runs:
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(5):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 5
+        tf = 2 * n ** 3 / ms / 1e9
+        legs[name] = {"ms": round(ms, 4), "TFLOPs": round(tf, 2), "mfma_frac": round(tf / peaks[name], 4)}
+    ref = outs["fp64"]
+    nref = torch.linalg.norm(ref).item()
+    for p in ("fp32", "bf16x3", "plain"):
+        legs[p]["rel_err_vs_fp64"] = float(f"{torch.linalg.norm(outs[p] - ref).item() / nref:.3e}")
+    exact = torch.matmul(dA, dB)
+    method = torch.linalg.norm(ref - exact).item() / torch.linalg.norm(exact).item()
+    legs["plain"]["what"] = "torch FP64 matmul of the decompressed A"
+    legs["bf16x3"]["mfma_frac_note"] = "against 1/3 of the BF16 peak (three products)"
+    return {"legs": legs, "method_rel_err": float(f"{method:.3e}"),
+            "note": "TFLOPs count 2 n^3 useful flops; times include decompressing A and preparing B"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -220,30 +263,7 @@ def main():
     del dA, dB, D
 
     if not args.no_matmul:
-        Am, Bm, _ = workload_inputs("linalg-4096")
-        g = blaz.compress(torch.from_numpy(Am).cuda())
-        dBm = torch.from_numpy(Bm).cuda()
-        Cm = torch.empty((4096, 4096), dtype=torch.float64, device="cuda")
-        ws = torch.empty(blaz.matmul_workspace_bytes(4096, 4096, 4096, False), dtype=torch.uint8, device="cuda")
-        Ad = blaz.decompress(g)
-        legs = {}
-        for name, fn in (("blaz_fp64", lambda: blaz.matmul(g, dBm, out=Cm, workspace=ws)),
-                         ("plain_dense_fp64_torch", lambda: torch.matmul(Ad, dBm, out=Cm))):
-            fn()
-            torch.cuda.synchronize()
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(5):
-                fn()
-            b.record()
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b) / 5
-            tf = 2 * 4096 ** 3 / ms / 1e9
-            legs[name] = {"ms": round(ms, 4), "TFLOPs": round(tf, 2),
-                          "mfma_frac": round(tf / FP64_MFMA_PEAK_TFLOPS, 4)}
-        result["matmul_4096"] = legs
-        del g, dBm, Cm, ws, Ad
+        result["matmul_4096"] = matmul_leg(blaz, torch, workload_inputs)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(A, B, min(args.cpu_rows, n))

@@ -188,13 +188,46 @@ BLAZ_API blaz_status blaz_dot_dense(const blaz_matrix* x, const int64_t* xrow, c
     return hip_status(blaz::detail::launch_dot_dense(*x, xrow, v, ldv, count, out, stream));
 }
 
+// Workspace regions of blaz_matmul, each 256-byte aligned: the rebuilt A
+// and the prepared B in the contraction's operand form, plus a binary64
+// staging area for a compressed B when the contraction is not binary64.
+struct MatmulWorkspace {
+    size_t a_bytes, b_bytes, tmp_bytes;
+    size_t total() const { return a_bytes + b_bytes + tmp_bytes; }
+};
+
+static MatmulWorkspace matmul_workspace(int64_t m, int64_t n, int64_t k, bool b_compressed, blaz_precision prec)
+{
+    const size_t mk = (size_t)m * (size_t)k, kn = (size_t)k * (size_t)n;
+    MatmulWorkspace w{0, 0, 0};
+    switch (prec) {
+        case BLAZ_PREC_FP64:
+            w.a_bytes = round_up(mk * 8, 256);
+            w.b_bytes = b_compressed ? round_up(kn * 8, 256) : 0;
+            break;
+        case BLAZ_PREC_FP32:
+            w.a_bytes = round_up(mk * 4, 256);
+            w.b_bytes = round_up(kn * 4, 256);
+            w.tmp_bytes = b_compressed ? round_up(kn * 8, 256) : 0;
+            break;
+        case BLAZ_PREC_BF16X3:
+            w.a_bytes = 2 * round_up(mk * 2, 256);  // hi, lo
+            w.b_bytes = 2 * round_up(kn * 2, 256);
+            w.tmp_bytes = b_compressed ? round_up(kn * 8, 256) : 0;
+            break;
+    }
+    return w;
+}
+
+static bool valid_precision(blaz_precision prec)
+{
+    return prec == BLAZ_PREC_FP64 || prec == BLAZ_PREC_FP32 || prec == BLAZ_PREC_BF16X3;
+}
+
 BLAZ_API size_t blaz_matmul_workspace_bytes(int64_t m, int64_t n, int64_t k, int b_compressed, blaz_precision prec)
 {
-    if (check_shape(m, k) != BLAZ_OK || check_shape(k, n) != BLAZ_OK) return 0;
-    (void)prec;  // every precision stages the rebuilt operands in binary64
-    size_t bytes = round_up((size_t)m * (size_t)k * 8, 256);
-    if (b_compressed) bytes += round_up((size_t)k * (size_t)n * 8, 256);
-    return bytes;
+    if (check_shape(m, k) != BLAZ_OK || check_shape(k, n) != BLAZ_OK || !valid_precision(prec)) return 0;
+    return matmul_workspace(m, n, k, b_compressed != 0, prec).total();
 }
 
 BLAZ_API blaz_status blaz_matmul(const blaz_matrix* a, const blaz_matrix* b, const double* bdense, int64_t n,
@@ -204,8 +237,7 @@ BLAZ_API blaz_status blaz_matmul(const blaz_matrix* a, const blaz_matrix* b, con
     if (blaz_status st = check_matrix(a)) return st;
     if (b && bdense) return BLAZ_ERR_ARG;  // exactly one form of B
     if (!b && !bdense && a->cols > 0) return BLAZ_ERR_NULL;
-    if (prec != BLAZ_PREC_FP64 && prec != BLAZ_PREC_FP32 && prec != BLAZ_PREC_BF16X3) return BLAZ_ERR_ARG;
-    if (prec != BLAZ_PREC_FP64) return BLAZ_ERR_UNSUPPORTED;
+    if (!valid_precision(prec)) return BLAZ_ERR_ARG;
     const int64_t m = a->rows, k = a->cols;
     if (b) {
         if (blaz_status st = check_matrix(b)) return st;
@@ -220,7 +252,8 @@ BLAZ_API blaz_status blaz_matmul(const blaz_matrix* a, const blaz_matrix* b, con
         if (ldb < n) return BLAZ_ERR_SHAPE;
         if (!aligned(bdense, 16) || ldb % 2 != 0) return BLAZ_ERR_ALIGN;
     }
-    const size_t need = blaz_matmul_workspace_bytes(m, n, k, b != nullptr, prec);
+    const MatmulWorkspace wl = matmul_workspace(m, n, k, b != nullptr, prec);
+    const size_t need = wl.total();
     if (k > 0 && (!workspace || ws_bytes < need)) return BLAZ_ERR_WORKSPACE;
     if (k > 0 && !aligned(workspace, 256)) return BLAZ_ERR_ALIGN;
     const Range rc = span(c, dense_span(m, n, ldc));
@@ -232,17 +265,49 @@ BLAZ_API blaz_status blaz_matmul(const blaz_matrix* a, const blaz_matrix* b, con
     // empty K loop writes exactly that and reads nothing.
     if (k == 0) return hip_status(blaz::detail::launch_gemm_f64(nullptr, 0, nullptr, 0, c, ldc, m, n, 0, stream));
 
-    double* wa = static_cast<double*>(workspace);
-    if (hipError_t e = blaz::detail::launch_decompress(*a, wa, k, stream)) return hip_status(e);
-    const double* bop = bdense;
-    int64_t ldbop = ldb;
-    if (b) {
-        double* wb = reinterpret_cast<double*>(static_cast<char*>(workspace) + round_up((size_t)m * k * 8, 256));
-        if (hipError_t e = blaz::detail::launch_decompress(*b, wb, n, stream)) return hip_status(e);
-        bop = wb;
-        ldbop = n;
+    char* ws = static_cast<char*>(workspace);
+    char* wa = ws;
+    char* wb = ws + wl.a_bytes;
+    double* wtmp = reinterpret_cast<double*>(ws + wl.a_bytes + wl.b_bytes);
+    using namespace blaz::detail;
+
+    if (prec == BLAZ_PREC_FP64) {
+        double* A64 = reinterpret_cast<double*>(wa);
+        if (hipError_t e = launch_decompress(*a, A64, k, stream)) return hip_status(e);
+        const double* bop = bdense;
+        int64_t ldbop = ldb;
+        if (b) {
+            double* B64 = reinterpret_cast<double*>(wb);
+            if (hipError_t e = launch_decompress(*b, B64, n, stream)) return hip_status(e);
+            bop = B64;
+            ldbop = n;
+        }
+        return hip_status(launch_gemm_f64(A64, k, bop, ldbop, c, ldc, m, n, k, stream));
     }
-    return hip_status(blaz::detail::launch_gemm_f64(wa, k, bop, ldbop, c, ldc, m, n, k, stream));
+
+    // Low-precision contractions: B (dense, or a compressed B rebuilt in
+    // binary64 first) is converted to the operand form.
+    const double* bsrc = bdense;
+    int64_t ldbsrc = ldb;
+    if (b) {
+        if (hipError_t e = launch_decompress(*b, wtmp, n, stream)) return hip_status(e);
+        bsrc = wtmp;
+        ldbsrc = n;
+    }
+    if (prec == BLAZ_PREC_FP32) {
+        float* A32 = reinterpret_cast<float*>(wa);
+        float* B32 = reinterpret_cast<float*>(wb);
+        if (hipError_t e = launch_decompress_f32(*a, A32, k, stream)) return hip_status(e);
+        if (hipError_t e = launch_convert_f32(bsrc, ldbsrc, B32, k, n, stream)) return hip_status(e);
+        return hip_status(launch_gemm_f32(A32, k, B32, n, c, ldc, m, n, k, stream));
+    }
+    __bf16* Ahi = reinterpret_cast<__bf16*>(wa);
+    __bf16* Alo = reinterpret_cast<__bf16*>(wa + wl.a_bytes / 2);
+    __bf16* Bhi = reinterpret_cast<__bf16*>(wb);
+    __bf16* Blo = reinterpret_cast<__bf16*>(wb + wl.b_bytes / 2);
+    if (hipError_t e = launch_decompress_bf16_split(*a, Ahi, Alo, k, stream)) return hip_status(e);
+    if (hipError_t e = launch_convert_bf16_split_t(bsrc, ldbsrc, Bhi, Blo, k, n, stream)) return hip_status(e);
+    return hip_status(launch_gemm_bf16x3(Ahi, Alo, k, Bhi, Blo, k, c, ldc, m, n, k, stream));
 }
 
 BLAZ_API const char* blaz_status_string(blaz_status status)

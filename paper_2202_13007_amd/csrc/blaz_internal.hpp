@@ -12,6 +12,9 @@ namespace detail {
 
 hipError_t launch_compress_f64(const double* A, int64_t lda, const blaz_matrix& m, uint8_t* psi, hipStream_t st);
 hipError_t launch_decompress(const blaz_matrix& m, double* A, int64_t lda, hipStream_t st);
+// Decompression into the operand forms of the low-precision contractions.
+hipError_t launch_decompress_f32(const blaz_matrix& m, float* A, int64_t lda, hipStream_t st);
+hipError_t launch_decompress_bf16_split(const blaz_matrix& m, __bf16* hi, __bf16* lo, int64_t lda, hipStream_t st);
 hipError_t launch_add(const blaz_matrix& x, const blaz_matrix& y, const blaz_matrix& z, bool negate_y,
                       hipStream_t st);
 hipError_t launch_scale(const blaz_matrix& x, double c, const blaz_matrix& z, hipStream_t st);
@@ -22,6 +25,19 @@ hipError_t launch_dot_dense(const blaz_matrix& x, const int64_t* xrow, const dou
 // C (m x n, ldc) = A (m x k, lda) * B (k x n, ldb), all row-major binary64.
 hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                            int64_t m, int64_t n, int64_t k, hipStream_t st);
+// The same product with FP32 operands on FP32 MFMA (FP32 accumulation).
+hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* B, int64_t ldb, double* C, int64_t ldc,
+                           int64_t m, int64_t n, int64_t k, hipStream_t st);
+// The same product with A = Ahi + Alo (m x k) and B^T = Bthi + Btlo (n x k)
+// in BF16: C = Ahi B_hi + Ahi B_lo + Alo B_hi on BF16 MFMA, FP32 accumulation.
+hipError_t launch_gemm_bf16x3(const __bf16* Ahi, const __bf16* Alo, int64_t lda, const __bf16* Bthi,
+                              const __bf16* Btlo, int64_t ldbt, double* C, int64_t ldc, int64_t m, int64_t n,
+                              int64_t k, hipStream_t st);
+// Dense binary64 B (k x n, ldb) to FP32 row-major (k x n, ld n).
+hipError_t launch_convert_f32(const double* B, int64_t ldb, float* out, int64_t k, int64_t n, hipStream_t st);
+// Dense binary64 B (k x n, ldb) to B^T split into BF16 hi + lo (n x k, ld k).
+hipError_t launch_convert_bf16_split_t(const double* B, int64_t ldb, __bf16* hi, __bf16* lo, int64_t k, int64_t n,
+                                       hipStream_t st);
 
 }  // namespace detail
 }  // namespace blaz

@@ -15,6 +15,8 @@
 namespace blaz {
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 // Pairwise sum of the 64 values v(0..63) in row-major order: level 1 adds
 // (v0+v1), (v2+v3), ..., each next level adds adjacent pairs.  This fixed
@@ -246,11 +248,49 @@ __global__ __launch_bounds__(kWave) void compress_f64_kernel(const double* __res
     }
 }
 
-template <bool kVec>
+// Output forms of the decompression: binary64 (the plain method), and the
+// operand forms of the low-precision contractions in blaz_matmul: FP32, or
+// BF16 hi + lo with hi = bf16(x), lo = bf16(x - hi).
+struct OutF64 {
+    double* p;
+    __device__ void store2(int64_t off, double a, double b) const
+    {
+        __builtin_nontemporal_store(f64x2{a, b}, reinterpret_cast<f64x2*>(p + off));
+    }
+    __device__ void store(int64_t off, double a) const { p[off] = a; }
+};
+struct OutF32 {
+    float* p;
+    __device__ void store2(int64_t off, double a, double b) const
+    {
+        *reinterpret_cast<f32x2*>(p + off) = f32x2{(float)a, (float)b};
+    }
+    __device__ void store(int64_t off, double a) const { p[off] = (float)a; }
+};
+struct OutBF16Split {
+    __bf16* hi;
+    __bf16* lo;
+    __device__ static __bf16 high(double x) { return (__bf16)(float)x; }
+    __device__ static __bf16 low(double x, __bf16 h) { return (__bf16)(float)(x - (double)(float)h); }
+    __device__ void store2(int64_t off, double a, double b) const
+    {
+        const __bf16 ha = high(a), hb = high(b);
+        *reinterpret_cast<bf16x2*>(hi + off) = bf16x2{ha, hb};
+        *reinterpret_cast<bf16x2*>(lo + off) = bf16x2{low(a, ha), low(b, hb)};
+    }
+    __device__ void store(int64_t off, double a) const
+    {
+        const __bf16 h = high(a);
+        hi[off] = h;
+        lo[off] = low(a, h);
+    }
+};
+
+template <bool kVec, typename Out>
 __global__ __launch_bounds__(kWave) void decompress_kernel(const double* __restrict__ f, const double* __restrict__ s,
                                                            const uint8_t* __restrict__ phi,
                                                            const uint32_t* __restrict__ codes, int64_t nbc,
-                                                           int64_t nblk, double* __restrict__ A, int64_t lda)
+                                                           int64_t nblk, Out out, int64_t lda)
 {
     __shared__ __align__(16) double tile[kWave * kSlot];
     const int lane = threadIdx.x;
@@ -295,17 +335,17 @@ __global__ __launch_bounds__(kWave) void decompress_kernel(const double* __restr
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const f64x2 v = *reinterpret_cast<const f64x2*>(&tile[((lane >> 2) + 16 * k) * kSlot + 2 * (lane & 3)]);
-                if (wc.ok[k]) __builtin_nontemporal_store(v, reinterpret_cast<f64x2*>(A + wc.off[k] + r * lda));
+                if (wc.ok[k]) out.store2(wc.off[k] + r * lda, v[0], v[1]);
             }
             __syncthreads();
         }
     } else if (valid) {
         const int64_t I = b / nbc, J = b - (b / nbc) * nbc;
-        double* dst = A + (I * 8) * lda + J * 8;
+        const int64_t base = (I * 8) * lda + J * 8;
 #pragma unroll
         for (int r = 0; r < 8; ++r)
 #pragma unroll
-            for (int c = 0; c < 8; ++c) dst[r * lda + c] = x[r * 8 + c];
+            for (int c = 0; c < 8; ++c) out.store(base + r * lda + c, x[r * 8 + c]);
     }
 }
 
@@ -331,18 +371,37 @@ hipError_t launch_compress_f64(const double* A, int64_t lda, const blaz_matrix& 
     return hipGetLastError();
 }
 
-hipError_t launch_decompress(const blaz_matrix& m, double* A, int64_t lda, hipStream_t st)
+template <typename Out>
+static hipError_t launch_decompress_to(const blaz_matrix& m, Out out, bool vec, int64_t lda, hipStream_t st)
 {
     const int64_t nbc = m.cols / 8;
     const int64_t nblk = (m.rows / 8) * nbc;
-    const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % 2 == 0);
     const unsigned grid = grid_for(nblk);
     const auto* cw = reinterpret_cast<const uint32_t*>(m.codes);
     if (vec)
-        decompress_kernel<true><<<grid, kWave, 0, st>>>(m.f, m.s, m.phi, cw, nbc, nblk, A, lda);
+        decompress_kernel<true><<<grid, kWave, 0, st>>>(m.f, m.s, m.phi, cw, nbc, nblk, out, lda);
     else
-        decompress_kernel<false><<<grid, kWave, 0, st>>>(m.f, m.s, m.phi, cw, nbc, nblk, A, lda);
+        decompress_kernel<false><<<grid, kWave, 0, st>>>(m.f, m.s, m.phi, cw, nbc, nblk, out, lda);
     return hipGetLastError();
+}
+
+hipError_t launch_decompress(const blaz_matrix& m, double* A, int64_t lda, hipStream_t st)
+{
+    const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % 2 == 0);
+    return launch_decompress_to(m, OutF64{A}, vec, lda, st);
+}
+
+hipError_t launch_decompress_f32(const blaz_matrix& m, float* A, int64_t lda, hipStream_t st)
+{
+    const bool vec = (reinterpret_cast<uintptr_t>(A) % 8 == 0) && (lda % 2 == 0);
+    return launch_decompress_to(m, OutF32{A}, vec, lda, st);
+}
+
+hipError_t launch_decompress_bf16_split(const blaz_matrix& m, __bf16* hi, __bf16* lo, int64_t lda, hipStream_t st)
+{
+    const bool vec = (reinterpret_cast<uintptr_t>(hi) % 4 == 0) && (reinterpret_cast<uintptr_t>(lo) % 4 == 0) &&
+                     (lda % 2 == 0);
+    return launch_decompress_to(m, OutBF16Split{hi, lo}, vec, lda, st);
 }
 
 }  // namespace detail

@@ -3,12 +3,16 @@
 // The paper's matrix multiplication rebuilds every block once and then
 // multiplies (last paragraph of Section "Basic Linear Algebra Algorithms").
 // The rebuild is the decompression kernel; this file holds the product
-// C = A B of the rebuilt operands: binary64 in, binary64 out, on
-// v_mfma_f64_16x16x4_f64.
+// C = A B of the rebuilt operands in three arithmetics, all writing binary64:
+//   FP64    v_mfma_f64_16x16x4_f64 on binary64 operands (the plain method)
+//   FP32    v_mfma_f32_16x16x4_f32 on FP32 operands, FP32 accumulation
+//   BF16x3  v_mfma_f32_16x16x32_bf16 on A = Ahi + Alo, B = Bhi + Blo:
+//           C = Alo Bhi + Ahi Blo + Ahi Bhi (the Alo Blo term, ~2^-16
+//           relative, is dropped), FP32 accumulation
 //
 // Tiling: a 256-thread workgroup computes a 128x128 tile of C; its four
-// waves each own a 64x64 quadrant as 4x4 MFMA tiles of 16x16.  K advances in
-// steps of 16 through LDS; the next step's global loads are issued into
+// waves each own a 64x64 quadrant as 4x4 MFMA tiles of 16x16.  K advances
+// through LDS in steps of BK; the next step's global loads are issued into
 // registers before the current step's MFMAs, so HBM/L2 latency overlaps the
 // matrix math.  Workgroup ids are remapped so that each XCD (the hardware
 // deals workgroups to the 8 XCDs round-robin) works on a contiguous group of
@@ -19,10 +23,14 @@
 
 namespace blaz {
 
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kBM = 128, kBN = 128, kBK = 16;
-constexpr int kPad = 16;  // doubles; 1152-byte LDS rows put k and k+1 on disjoint banks
+constexpr int kBM = 128, kBN = 128;
+constexpr int kPad = 16;  // elements of padding per LDS row (see the bank notes at each use)
 
 // Tile (tm, tn) for workgroup `wg` of `nwg`: contiguous ranges per XCD, then
 // groups of 8 tile rows walked column by column for L2 reuse.
@@ -39,13 +47,48 @@ __device__ __forceinline__ void tile_of(int wg, int nwg, int ntm, int ntn, int& 
     tn = r / rows;
 }
 
-__global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict__ A, int64_t lda,
-                                                       const double* __restrict__ B, int64_t ldb,
-                                                       double* __restrict__ C, int64_t ldc, int64_t M, int64_t N,
-                                                       int64_t K)
+// The 16x16x4 MFMA for each operand type, and where value r of lane l lands
+// in the 16x16 result (probed on gfx950: the FP64 form places value r of
+// lane l in row 4r + l/16, the FP32 form in row 4(l/16) + r; column l%16).
+template <typename T>
+struct Mfma16x16x4;
+template <>
+struct Mfma16x16x4<double> {
+    using acc_t = f64x4;
+    using vec_t = f64x2;  // 16-byte global/LDS vector
+    static constexpr int kBK = 16;
+    __device__ static acc_t op(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int g, int r) { return 4 * r + g; }
+};
+template <>
+struct Mfma16x16x4<float> {
+    using acc_t = f32x4;
+    using vec_t = f32x4;
+    static constexpr int kBK = 32;
+    __device__ static acc_t op(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int g, int r) { return 4 * g + r; }
+};
+
+// C = A B with A (M x K, lda) and B (K x N, ldb) row-major in T; C binary64.
+// LDS rows hold kBM + kPad elements: 144 doubles (1152 B) or 144 floats
+// (576 B), which puts the four k rows read by one MFMA operand fetch on
+// different banks.
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+                                                   int64_t ldb, double* __restrict__ C, int64_t ldc, int64_t M,
+                                                   int64_t N, int64_t K)
 {
-    __shared__ double As[kBK][kBM + kPad];  // A tile stored k-major (transposed)
-    __shared__ double Bs[kBK][kBN + kPad];
+    using MF = Mfma16x16x4<T>;
+    using acc_t = typename MF::acc_t;
+    using vec_t = typename MF::vec_t;
+    constexpr int BK = MF::kBK;
+    constexpr int V = 16 / sizeof(T);     // elements per 16-byte vector
+    constexpr int AV = BK / V;            // vectors per A tile row
+    constexpr int BV = kBN / V;           // vectors per B tile row
+    static_assert(kBM * AV == 1024 && BK * BV == 1024, "4 vectors of A and of B per thread");
+
+    __shared__ T As[BK][kBM + kPad];  // A tile stored k-major (transposed)
+    __shared__ T Bs[BK][kBN + kPad];
 
     const int ntm = (int)((M + kBM - 1) / kBM);
     const int ntn = (int)((N + kBN - 1) / kBN);
@@ -57,50 +100,49 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
-    // Global -> register staging: 4 double2 of A and 4 of B per thread.
-    double2 ra[4], rb[4];
+    vec_t ra[4], rb[4];
     auto load_stage = [&](int64_t k0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int q = tid + 256 * r;
-            const int am = q >> 3, ak = (q & 7) * 2;          // A: 128 rows x 8 double2
+            const int am = q / AV, ak = (q % AV) * V;
             const int64_t gr = row0 + am, gk = k0 + ak;
-            ra[r] = (gr < M && gk < K) ? *reinterpret_cast<const double2*>(A + gr * lda + gk) : double2{0.0, 0.0};
-            const int bk = q >> 6, bn = (q & 63) * 2;         // B: 16 rows x 64 double2
+            ra[r] = (gr < M && gk < K) ? *reinterpret_cast<const vec_t*>(A + gr * lda + gk) : vec_t{};
+            const int bk = q / BV, bn = (q % BV) * V;
             const int64_t hk = k0 + bk, hn = col0 + bn;
-            rb[r] = (hk < K && hn < N) ? *reinterpret_cast<const double2*>(B + hk * ldb + hn) : double2{0.0, 0.0};
+            rb[r] = (hk < K && hn < N) ? *reinterpret_cast<const vec_t*>(B + hk * ldb + hn) : vec_t{};
         }
     };
     auto store_stage = [&]() {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int q = tid + 256 * r;
-            const int am = q >> 3, ak = (q & 7) * 2;
-            As[ak][am] = ra[r].x;
-            As[ak + 1][am] = ra[r].y;
-            const int bk = q >> 6, bn = (q & 63) * 2;
-            *reinterpret_cast<double2*>(&Bs[bk][bn]) = rb[r];
+            const int am = q / AV, ak = (q % AV) * V;
+#pragma unroll
+            for (int e = 0; e < V; ++e) As[ak + e][am] = ra[r][e];
+            const int bk = q / BV, bn = (q % BV) * V;
+            *reinterpret_cast<vec_t*>(&Bs[bk][bn]) = rb[r];
         }
     };
 
-    f64x4 acc[4][4];
+    acc_t acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{};
 
-    const int nk = (int)((K + kBK - 1) / kBK);
+    const int nk = (int)((K + BK - 1) / BK);
     load_stage(0);
     for (int kt = 0; kt < nk; ++kt) {
         __syncthreads();
         store_stage();
         __syncthreads();
-        if (kt + 1 < nk) load_stage((int64_t)(kt + 1) * kBK);
+        if (kt + 1 < nk) load_stage((int64_t)(kt + 1) * BK);
 #pragma unroll
-        for (int kk = 0; kk < kBK; kk += 4) {
-            // A operand of a 16x16x4 MFMA: lane holds A[m = lane%16][k = lane/16];
-            // B operand: lane holds B[k = lane/16][n = lane%16].
-            double a[4], b[4];
+        for (int kk = 0; kk < BK; kk += 4) {
+            // A operand: lane holds A[m = lane%16][k = lane/16]; B operand:
+            // lane holds B[k = lane/16][n = lane%16].
+            T a[4], b[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) a[i] = As[kk + (lane >> 4)][wm * 64 + i * 16 + (lane & 15)];
 #pragma unroll
@@ -108,13 +150,10 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < 4; ++j) acc[i][j] = MF::op(a[i], b[j], acc[i][j]);
         }
     }
 
-    // Accumulator layout of v_mfma_f64_16x16x4_f64: value r (0..3) of a lane
-    // holds D[4*r + lane/16][lane%16] (unlike the FP32/BF16 16x16 forms,
-    // whose value r holds row 4*(lane/16) + r).
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -122,19 +161,206 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
             const int64_t gc = col0 + wn * 64 + j * 16 + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t gr = row0 + wm * 64 + i * 16 + 4 * r + (lane >> 4);
-                if (gr < M && gc < N) C[gr * ldc + gc] = acc[i][j][r];
+                const int64_t gr = row0 + wm * 64 + i * 16 + MF::row(lane >> 4, r);
+                if (gr < M && gc < N) C[gr * ldc + gc] = (double)acc[i][j][r];
             }
         }
 }
 
+// BF16x3: A hi/lo (M x K, lda) and B^T hi/lo (N x K, ldbt), all with k
+// contiguous, so that one 16-byte load gives an MFMA lane its 8 k-values.
+// K advances in steps of 32.  LDS rows hold 32 + 8 bf16 (80 B): the 16 rows
+// read by one 16-lane group then start on 16 distinct 4-bank groups.
+constexpr int kBKb = 32;
+constexpr int kRowB = kBKb + 8;
+
+__global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restrict__ Ahi, const __bf16* __restrict__ Alo,
+                                                          int64_t lda, const __bf16* __restrict__ Bhi,
+                                                          const __bf16* __restrict__ Blo, int64_t ldbt,
+                                                          double* __restrict__ C, int64_t ldc, int64_t M, int64_t N,
+                                                          int64_t K)
+{
+    __shared__ __align__(16) __bf16 Ash[kBM * kRowB];
+    __shared__ __align__(16) __bf16 Asl[kBM * kRowB];
+    __shared__ __align__(16) __bf16 Bsh[kBN * kRowB];
+    __shared__ __align__(16) __bf16 Bsl[kBN * kRowB];
+
+    const int ntm = (int)((M + kBM - 1) / kBM);
+    const int ntn = (int)((N + kBN - 1) / kBN);
+    int tm, tn;
+    tile_of(blockIdx.x, gridDim.x, ntm, ntn, tm, tn);
+    const int64_t row0 = (int64_t)tm * kBM, col0 = (int64_t)tn * kBN;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    // Each of the four 128 x 32 tiles is 512 16-byte chunks: 2 per thread.
+    uint4 rah[2], ral[2], rbh[2], rbl[2];
+    auto load_stage = [&](int64_t k0) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int q = tid + 256 * r;
+            const int row = q >> 2, kc = (q & 3) * 8;
+            const int64_t gk = k0 + kc;
+            const int64_t ga = row0 + row, gb = col0 + row;
+            const bool oka = ga < M && gk < K, okb = gb < N && gk < K;
+            rah[r] = oka ? *reinterpret_cast<const uint4*>(Ahi + ga * lda + gk) : uint4{0, 0, 0, 0};
+            ral[r] = oka ? *reinterpret_cast<const uint4*>(Alo + ga * lda + gk) : uint4{0, 0, 0, 0};
+            rbh[r] = okb ? *reinterpret_cast<const uint4*>(Bhi + gb * ldbt + gk) : uint4{0, 0, 0, 0};
+            rbl[r] = okb ? *reinterpret_cast<const uint4*>(Blo + gb * ldbt + gk) : uint4{0, 0, 0, 0};
+        }
+    };
+    auto store_stage = [&]() {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int q = tid + 256 * r;
+            const int off = (q >> 2) * kRowB + (q & 3) * 8;
+            *reinterpret_cast<uint4*>(&Ash[off]) = rah[r];
+            *reinterpret_cast<uint4*>(&Asl[off]) = ral[r];
+            *reinterpret_cast<uint4*>(&Bsh[off]) = rbh[r];
+            *reinterpret_cast<uint4*>(&Bsl[off]) = rbl[r];
+        }
+    };
+
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int nk = (int)((K + kBKb - 1) / kBKb);
+    load_stage(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        __syncthreads();
+        store_stage();
+        __syncthreads();
+        if (kt + 1 < nk) load_stage((int64_t)(kt + 1) * kBKb);
+        // Operands of a 16x16x32 MFMA: lane l holds the 8 k-values
+        // 8*(l/16) .. 8*(l/16)+7 of row (A) or column (B) l%16; any fixed
+        // assignment of k to (lane group, element) works as long as A and B
+        // use the same one.
+        const int koff = 8 * (lane >> 4);
+        bf16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int off = (wm * 64 + i * 16 + (lane & 15)) * kRowB + koff;
+            ah[i] = *reinterpret_cast<const bf16x8*>(&Ash[off]);
+            al[i] = *reinterpret_cast<const bf16x8*>(&Asl[off]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int off = (wn * 64 + j * 16 + (lane & 15)) * kRowB + koff;
+            bh[j] = *reinterpret_cast<const bf16x8*>(&Bsh[off]);
+            bl[j] = *reinterpret_cast<const bf16x8*>(&Bsl[off]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            }
+    }
+
+    // Value r of lane l holds row 4*(l/16) + r, column l%16 (BF16 16x16 form).
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t gc = col0 + wn * 64 + j * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gr = row0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+                if (gr < M && gc < N) C[gr * ldc + gc] = (double)acc[i][j][r];
+            }
+        }
+}
+
+// Dense binary64 (k x n, ldb) to FP32 (k x n, ld n): rows strided over
+// the y dimension of the grid, two elements per thread.
+__global__ __launch_bounds__(256) void convert_f32_kernel(const double* __restrict__ B, int64_t ldb,
+                                                          float* __restrict__ out, int64_t k, int64_t n)
+{
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2;
+    if (c >= n) return;
+    for (int64_t row = blockIdx.y; row < k; row += gridDim.y) {
+        const f64x2 v = *reinterpret_cast<const f64x2*>(B + row * ldb + c);
+        *reinterpret_cast<float2*>(out + row * n + c) = make_float2((float)v[0], (float)v[1]);
+    }
+}
+
+// Dense binary64 (k x n, ldb) to its transpose split into BF16 hi + lo
+// (n x k, ld k), through a 64 x 64 LDS tile so that both the reads (along
+// n) and the writes (along k) are contiguous.
+__global__ __launch_bounds__(256) void convert_bf16_split_t_kernel(const double* __restrict__ B, int64_t ldb,
+                                                                   __bf16* __restrict__ hi, __bf16* __restrict__ lo,
+                                                                   int64_t k, int64_t n)
+{
+    __shared__ double t[64][65];
+    const int64_t k0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int kk = ty + 4 * r;
+        const bool ok = k0 + kk < k && n0 + tx < n;
+        t[kk][tx] = ok ? B[(k0 + kk) * ldb + n0 + tx] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int nn = ty + 4 * r;
+        if (n0 + nn < n && k0 + tx < k) {
+            const double x = t[tx][nn];
+            const __bf16 h = (__bf16)(float)x;
+            const __bf16 l = (__bf16)(float)(x - (double)(float)h);
+            hi[(n0 + nn) * k + k0 + tx] = h;
+            lo[(n0 + nn) * k + k0 + tx] = l;
+        }
+    }
+}
+
 namespace detail {
+
+static unsigned gemm_grid(int64_t m, int64_t n) { return (unsigned)(((m + kBM - 1) / kBM) * ((n + kBN - 1) / kBN)); }
 
 hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                            int64_t m, int64_t n, int64_t k, hipStream_t st)
 {
-    const int64_t tiles = ((m + kBM - 1) / kBM) * ((n + kBN - 1) / kBN);
-    gemm_f64_kernel<<<(unsigned)tiles, 256, 0, st>>>(A, lda, B, ldb, C, ldc, m, n, k);
+    gemm_kernel<double><<<gemm_grid(m, n), 256, 0, st>>>(A, lda, B, ldb, C, ldc, m, n, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* B, int64_t ldb, double* C, int64_t ldc,
+                           int64_t m, int64_t n, int64_t k, hipStream_t st)
+{
+    gemm_kernel<float><<<gemm_grid(m, n), 256, 0, st>>>(A, lda, B, ldb, C, ldc, m, n, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_bf16x3(const __bf16* Ahi, const __bf16* Alo, int64_t lda, const __bf16* Bthi,
+                              const __bf16* Btlo, int64_t ldbt, double* C, int64_t ldc, int64_t m, int64_t n,
+                              int64_t k, hipStream_t st)
+{
+    gemm_bf16x3_kernel<<<gemm_grid(m, n), 256, 0, st>>>(Ahi, Alo, lda, Bthi, Btlo, ldbt, C, ldc, m, n, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_f32(const double* B, int64_t ldb, float* out, int64_t k, int64_t n, hipStream_t st)
+{
+    if (k == 0 || n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((n / 2 + 255) / 256), (unsigned)(k < 4096 ? k : 4096));
+    convert_f32_kernel<<<grid, 256, 0, st>>>(B, ldb, out, k, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_bf16_split_t(const double* B, int64_t ldb, __bf16* hi, __bf16* lo, int64_t k, int64_t n,
+                                       hipStream_t st)
+{
+    if (k == 0 || n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((k + 63) / 64));
+    convert_bf16_split_t_kernel<<<grid, 256, 0, st>>>(B, ldb, hi, lo, k, n);
     return hipGetLastError();
 }
 

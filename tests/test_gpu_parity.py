@@ -408,6 +408,71 @@ def test_matmul_full_size_4096_sampled():
         assert abs(C[i, j] - want) <= 1e-12 * mag, (i, j, C[i, j], want)
 
 
+# Low-precision contractions (FP32, BF16 hi+lo with three products).  Bound
+# on |C - C64| relative to sum_k |a_k b_k|: operand rounding (FP32: 2 u32;
+# BF16x3: 3 * 2^-16 from the split and the dropped lo*lo term) plus FP32
+# accumulation over K terms (K * u32 for BF16x3, whose MFMA sums 32 products
+# per step; K/4 * u32 for the FP32 16x16x4 form).
+U32 = 2.0 ** -24
+
+
+def low_precision_tol(prec, k):
+    return (2 + k / 4 + 4) * U32 if prec == "fp32" else 3 * 2.0 ** -16 + (k + 4) * U32
+
+
+def low_precision_fro(prec, k):
+    """Expected-size bound on the relative Frobenius error: rounding errors of
+    the K-term FP32 accumulation grow like sqrt(K) u32 with random signs."""
+    return (2 + 4 * np.sqrt(k)) * U32 if prec == "fp32" else 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("m,k,n", [(64, 64, 64), (136, 200, 72), (8, 8, 8), (392, 136, 264)])
+def test_matmul_low_precision_dense_b(prec, m, k, n):
+    A = smooth_field(m, 4, 2.0, 1e-3, 450 + m, cols=k)
+    B = uniform_matrix(k, n, 451)
+    ox = oracle.compress(A)
+    got = blaz.matmul(upload(ox), dev(B), prec=prec).cpu().numpy()
+    Xd = oracle.decompress(ox)
+    want = oracle.gemm(Xd, B)
+    mag = np.abs(Xd) @ np.abs(B)
+    assert_dots_close(got, want, mag, rel=low_precision_tol(prec, k), what=f"matmul {prec}")
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert rel < low_precision_fro(prec, k), rel
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_matmul_low_precision_compressed_b(prec):
+    A, B = workload_inputs("plain-64")
+    ox, oy = oracle.compress(A), oracle.compress(B)
+    got = blaz.matmul(upload(ox), upload(oy), prec=prec).cpu().numpy()
+    Xd, Yd = oracle.decompress(ox), oracle.decompress(oy)
+    want = oracle.gemm(Xd, Yd)
+    assert_dots_close(got, want, np.abs(Xd) @ np.abs(Yd), rel=low_precision_tol(prec, 64),
+                      what=f"matmul {prec} compressed B")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_matmul_low_precision_full_size_4096_sampled(prec):
+    """Compressed 4096^2 field times dense U[-1, 1] in FP32 / BF16x3: sampled
+    entries against the oracle, and the whole product against the FP64 path."""
+    A, B, _ = workload_inputs("linalg-4096")
+    g, _ = gpu_compress(A)
+    dB = dev(B)
+    C = blaz.matmul(g, dB, prec=prec)
+    C64 = blaz.matmul(g, dB, prec="fp64")
+    rel = (torch.linalg.norm(C - C64) / torch.linalg.norm(C64)).item()
+    assert rel < low_precision_fro(prec, 4096), rel
+    Ch = C.cpu().numpy()
+    og = oracle.Compressed(4096, 4096, *host(g))
+    rng = np.random.default_rng(6)
+    for i, j in [(0, 0), (4095, 4095)] + [tuple(rng.integers(0, 4096, 2)) for _ in range(6)]:
+        bj = np.ascontiguousarray(B[:, j])
+        want = oracle.dot_dense(og, [i], bj, 0)[0]
+        mag = np.abs(band_rows(og, int(i))) @ np.abs(bj)
+        assert abs(Ch[i, j] - want) <= low_precision_tol(prec, 4096) * mag, (i, j, Ch[i, j], want)
+
+
 def test_empty_and_k0():
     z = blaz.BlazMatrix.empty(0, 16)
     blaz.compress(torch.empty((0, 16), dtype=torch.float64, device="cuda"), out=z)
