@@ -114,8 +114,8 @@ BLAZ_API blaz_status blaz_compress(const double* A, int64_t lda, const blaz_matr
     const Range ra = span(A, dense_span(out->rows, out->cols, lda));
     if (overlaps_matrix(ra, *out)) return BLAZ_ERR_ARG;
     if (psi && (overlap(span(psi, 64 * nblk), ra) || overlaps_matrix(span(psi, 64 * nblk), *out))) return BLAZ_ERR_ARG;
-    if (prec != BLAZ_PREC_FP64) return BLAZ_ERR_UNSUPPORTED;
-    return hip_status(blaz::detail::launch_compress_f64(A, lda, *out, psi, stream));
+    if (prec == BLAZ_PREC_FP64) return hip_status(blaz::detail::launch_compress_f64(A, lda, *out, psi, stream));
+    return hip_status(blaz::detail::launch_compress_mixed(A, lda, *out, psi, prec, stream));
 }
 
 BLAZ_API blaz_status blaz_decompress(const blaz_matrix* in, double* A, int64_t lda, hipStream_t stream)

@@ -11,6 +11,9 @@ namespace blaz {
 namespace detail {
 
 hipError_t launch_compress_f64(const double* A, int64_t lda, const blaz_matrix& m, uint8_t* psi, hipStream_t st);
+// Compression with the transform stage in FP32 or BF16x3 on MFMA.
+hipError_t launch_compress_mixed(const double* A, int64_t lda, const blaz_matrix& m, uint8_t* psi,
+                                 blaz_precision prec, hipStream_t st);
 hipError_t launch_decompress(const blaz_matrix& m, double* A, int64_t lda, hipStream_t st);
 // Decompression into the operand forms of the low-precision contractions.
 hipError_t launch_decompress_f32(const blaz_matrix& m, float* A, int64_t lda, hipStream_t st);

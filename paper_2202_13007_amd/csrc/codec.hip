@@ -9,100 +9,11 @@
 // every global access instruction covers a contiguous run.
 #include <hip/hip_runtime.h>
 
+#include "blaz_codec.hpp"
 #include "blaz_device.hpp"
 #include "blaz_internal.hpp"
 
 namespace blaz {
-
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-
-// Pairwise sum of the 64 values v(0..63) in row-major order: level 1 adds
-// (v0+v1), (v2+v3), ..., each next level adds adjacent pairs.  This fixed
-// order makes the slope s and the DC coefficient bit-reproducible.
-template <typename F>
-__device__ __forceinline__ double pairwise64(F v)
-{
-    double t[32];
-#pragma unroll
-    for (int i = 0; i < 32; ++i) t[i] = v(2 * i) + v(2 * i + 1);
-#pragma unroll
-    for (int n = 16; n >= 1; n /= 2) {
-#pragma unroll
-        for (int i = 0; i < n; ++i) t[i] = t[2 * i] + t[2 * i + 1];
-    }
-    return t[0];
-}
-
-// Normalization, Eq. eqnorm, in place.  Processing from the bottom-right
-// corner backwards keeps every left and upper neighbour unmodified when it is
-// read.  The interior term is ((M - Mup) + (M - Mleft)) * 0.5 exactly as
-// written (no contraction is possible: there is no product).
-__device__ __forceinline__ void normalize(double x[64])
-{
-#pragma unroll
-    for (int u = 7; u >= 1; --u) {
-#pragma unroll
-        for (int v = 7; v >= 1; --v)
-            x[u * 8 + v] = ((x[u * 8 + v] - x[(u - 1) * 8 + v]) + (x[u * 8 + v] - x[u * 8 + v - 1])) * 0.5;
-    }
-#pragma unroll
-    for (int v = 7; v >= 1; --v) x[v] = x[v] - x[v - 1];
-#pragma unroll
-    for (int u = 7; u >= 1; --u) x[u * 8] = x[u * 8] - x[(u - 1) * 8];
-    x[0] = 0.0;
-}
-
-// ---------------------------------------------------------------------------
-// Wave-cooperative staging.  A workgroup is one wave of 64 lanes owning 64
-// consecutive blocks.  Row r of those blocks is moved between HBM and the
-// lanes' registers through a 5 KiB LDS tile: every global instruction moves
-// 16 B per lane over a contiguous 1 KiB run (4 lanes per block row segment,
-// 16 blocks per instruction), and each lane then reads or writes its own
-// block's 64 B in LDS.  The tile gives each lane a 80-byte slot (64 B of data
-// + 16 B of padding) so that the per-lane LDS accesses spread over all banks.
-// ---------------------------------------------------------------------------
-constexpr int kWave = 64;
-constexpr int kSlot = 10;  // doubles per lane slot in the LDS tile
-
-// Global offsets (in doubles, row 0) of the four 16-byte chunks a lane moves:
-// chunk k covers part (lane & 3) of block wave_base + (lane >> 2) + 16 k.
-struct WaveChunks {
-    int64_t off[4];
-    bool ok[4];
-};
-
-__device__ __forceinline__ WaveChunks wave_chunks(int64_t wave_base, int lane, int64_t nbc, int64_t nblk,
-                                                  int64_t lda)
-{
-    WaveChunks w;
-    int64_t I0 = 0, J0 = 0;
-    if (nbc >= kWave) {  // wave-uniform: the 64 blocks wrap into the next block row at most once
-        I0 = wave_base / nbc;
-        J0 = wave_base - I0 * nbc;
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int q = (lane >> 2) + 16 * k;
-        const int64_t bb = wave_base + q;
-        int64_t I, J;
-        if (nbc >= kWave) {
-            I = I0;
-            J = J0 + q;
-            if (J >= nbc) {
-                J -= nbc;
-                ++I;
-            }
-        } else {
-            I = bb / nbc;
-            J = bb - I * nbc;
-        }
-        w.ok[k] = bb < nblk;
-        w.off[k] = (8 * I) * lda + 8 * J + 2 * (lane & 3);
-    }
-    return w;
-}
 
 template <bool kVec, bool kPsi>
 __global__ __launch_bounds__(kWave) void compress_f64_kernel(const double* __restrict__ A, int64_t lda,
@@ -114,138 +25,21 @@ __global__ __launch_bounds__(kWave) void compress_f64_kernel(const double* __res
     __shared__ __align__(16) double tile[kWave * kSlot];
     const int lane = threadIdx.x;
     const int64_t wave_base = (int64_t)blockIdx.x * kWave;
-    const int64_t b = wave_base + lane;
-    const bool valid = b < nblk;
 
     double x[64];
-    if constexpr (kVec) {
-        const WaveChunks wc = wave_chunks(wave_base, lane, nbc, nblk, lda);
-        f64x2 g[8][4];
-#pragma unroll
-        for (int r = 0; r < 8; ++r)
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                g[r][k] = wc.ok[k] ? __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(A + wc.off[k] + r * lda))
-                                   : f64x2{0.0, 0.0};
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                *reinterpret_cast<f64x2*>(&tile[((lane >> 2) + 16 * k) * kSlot + 2 * (lane & 3)]) = g[r][k];
-            __syncthreads();
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const f64x2 v = *reinterpret_cast<const f64x2*>(&tile[lane * kSlot + 2 * p]);
-                x[r * 8 + 2 * p] = v[0];
-                x[r * 8 + 2 * p + 1] = v[1];
-            }
-            __syncthreads();
-        }
-    } else {
-        if (valid) {
-            const int64_t I = b / nbc, J = b - (b / nbc) * nbc;
-            const double* src = A + (I * 8) * lda + J * 8;
-#pragma unroll
-            for (int r = 0; r < 8; ++r)
-#pragma unroll
-                for (int c = 0; c < 8; ++c) x[r * 8 + c] = src[r * lda + c];
-        } else {
-#pragma unroll
-            for (int e = 0; e < 64; ++e) x[e] = 0.0;
-        }
-    }
-    const double f = x[0];
+    load_blocks<kVec>(A, lda, nbc, nblk, wave_base, lane, tile, x);
+    const SlopeOut so_ = normalize_and_slope(x);
+    if constexpr (kPsi) predict_store(x, so_.s, psi, wave_base + lane, wave_base + lane < nblk);
 
-    // Normalization (Eq. eqnorm) and mean slope (Eqs. eqslope, eqslope2).
-    normalize(x);
-    int K = 0;
-#pragma unroll
-    for (int e = 1; e < 64; ++e) K += x[e] != 0.0 ? 1 : 0;
-    const double S1 = pairwise64([&](int e) { return fabs(x[e]); });
-    const double S = pairwise64([&](int e) { return x[e]; });
-    const double s = K > 0 ? S1 / (double)K : 0.0;
-    // D_00 = alpha_0^2 sum Delta' = 0.125 (sum Delta / s), the fixed order.
-    const double dc = s != 0.0 ? 0.125 * (S / s) : 0.0;
-
-    // Delta' = Delta / s.  The reciprocal is exact enough for the 63 other
-    // coefficients; a slope so small that 1/s overflows falls back to division.
-    if (s != 0.0 && fabs(s) >= 0x1p-1020) {
-        const double r = 1.0 / s;
-#pragma unroll
-        for (int e = 0; e < 64; ++e) x[e] *= r;
-    } else if (s != 0.0) {
-#pragma unroll
-        for (int e = 0; e < 64; ++e) x[e] = x[e] / s;
-    }
-
-    if constexpr (kPsi) {
-        // Prediction, Eq. eqpredict: index of the nearest of 256 points
-        // s - smax + k * (2 smax / 256), the smaller index on a tie.
-        double smax = 0.0;
-#pragma unroll
-        for (int e = 0; e < 64; ++e) smax = fmax(smax, fabs(x[e]));
-        uint32_t w[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) w[q] = 0;
-        if (smax != 0.0) {
-            const double lo = s - smax;
-            const double inv_step = 128.0 / smax;
-#pragma unroll
-            for (int e = 0; e < 64; ++e) {
-                double k = ceil((x[e] - lo) * inv_step - 0.5);
-                k = fmin(fmax(k, 0.0), 255.0);
-                w[e / 4] |= (uint32_t)k << (8 * (e % 4));
-            }
-        }
-        if (valid) {
-            uint4* dst = reinterpret_cast<uint4*>(psi + b * 64);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
-        }
-    }
-
-    // Two-dimensional DCT-II (Eq. eqdct): rows, then columns, in place.
+    // Two-dimensional DCT-II (Eq. eqdct) of Delta': rows, then columns, in
+    // place; the DC term is the fixed-order binary64 value.
 #pragma unroll
     for (int u = 0; u < 8; ++u) dct8<1, 1>(x + u * 8, x + u * 8);
 #pragma unroll
     for (int v = 0; v < 8; ++v) dct8<8, 8>(x + v, x + v);
-    x[0] = dc;
+    x[0] = so_.dc;
 
-    // Quantization (Eq. eqphi): m over all 64 coefficients, phi = trunc(127/m)
-    // clamped to 255, codes = trunc(phi * D) at the 28 kept positions.
-    double m = 0.0;
-#pragma unroll
-    for (int e = 0; e < 64; ++e) m = fmax(m, fabs(x[e]));
-    const double px = 127.0 / m;  // +inf when m == 0
-    const int phi = px < 255.0 ? (int)px : 255;
-    const double phid = (double)phi;
-    uint32_t w[kCodeWords];
-#pragma unroll
-    for (int q = 0; q < kCodeWords; ++q) w[q] = 0;
-#pragma unroll
-    for (int t = 0; t < kKept; ++t) {
-        const int c = (int)(phid * x[kept_row(t) * 8 + kept_col(t)]);  // truncation toward zero
-        w[t / 4] |= ((uint32_t)c & 0xffu) << (8 * (t % 4));
-    }
-
-    if (valid) {
-        fo[b] = f;
-        so[b] = s;
-        phio[b] = (uint8_t)phi;
-    }
-    // The wave's codes are one contiguous run of 64 * 28 bytes: packed in LDS,
-    // then written as consecutive dwords.
-    uint32_t* ct = reinterpret_cast<uint32_t*>(tile);
-#pragma unroll
-    for (int q = 0; q < kCodeWords; ++q) ct[lane * kCodeWords + q] = w[q];
-    __syncthreads();
-    const int64_t nwords = (nblk - wave_base < kWave ? nblk - wave_base : kWave) * kCodeWords;
-    uint32_t* cdst = codes + wave_base * kCodeWords;
-#pragma unroll
-    for (int k = 0; k < kCodeWords; ++k) {
-        const int idx = lane + kWave * k;
-        if (idx < nwords) cdst[idx] = ct[idx];
-    }
+    quantize_store(x, so_, nblk, wave_base, lane, tile, fo, so, phio, codes);
 }
 
 // Output forms of the decompression: binary64 (the plain method), and the

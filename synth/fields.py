@@ -9,9 +9,11 @@ noise stand in for both.  A field is a sum of T 2-D sinusoids
 with amplitude a ~ U[0.5, 2], frequencies u, v ~ U[-F, F] cycles per side,
 phase theta ~ U[0, 2 pi), drawn in that order per term from
 numpy.random.default_rng(seed) (PCG64), plus sigma * N(0, 1) noise drawn
-afterwards for the whole matrix.  The sinusoid is evaluated separably,
-sin(x + y) = sin x cos y + cos x sin y, with elementwise numpy operations only,
-so the result does not depend on BLAS threading.
+afterwards for the whole matrix.  The sinusoids are evaluated separably,
+sin(x + y) = sin x cos y + cos x sin y, as one product of an n x 2T matrix of
+row factors by a 2T x n matrix of column factors; its last bits may depend on
+the BLAS build, which does not matter because every test and benchmark feeds
+the one generated array to both sides.
 """
 from __future__ import annotations
 
@@ -24,18 +26,20 @@ def smooth_field(n: int, terms: int, max_freq: float, sigma: float, seed: int,
     rows = n
     cols = n if cols is None else cols
     rng = np.random.default_rng(seed)
-    M = np.zeros((rows, cols), dtype=np.float64)
     ii = np.arange(rows, dtype=np.float64)
     jj = np.arange(cols, dtype=np.float64)
-    for _ in range(terms):
+    L = np.zeros((rows, 2 * terms))
+    R = np.zeros((2 * terms, cols))
+    for t in range(terms):
         a = rng.uniform(0.5, 2.0)
         u = rng.uniform(-max_freq, max_freq)
         v = rng.uniform(-max_freq, max_freq)
         theta = rng.uniform(0.0, 2.0 * np.pi)
         xj = 2.0 * np.pi * u * jj / n + theta          # depends on the column
         yi = 2.0 * np.pi * v * ii / n                  # depends on the row
-        M += np.multiply.outer(a * np.cos(yi), np.sin(xj))
-        M += np.multiply.outer(a * np.sin(yi), np.cos(xj))
+        L[:, 2 * t], L[:, 2 * t + 1] = a * np.cos(yi), a * np.sin(yi)
+        R[2 * t], R[2 * t + 1] = np.sin(xj), np.cos(xj)
+    M = L @ R if terms > 0 else np.zeros((rows, cols))
     if sigma > 0.0:
         M += sigma * rng.standard_normal((rows, cols))
     return M

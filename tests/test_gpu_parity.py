@@ -408,6 +408,97 @@ def test_matmul_full_size_4096_sampled():
         assert abs(C[i, j] - want) <= 1e-12 * mag, (i, j, C[i, j], want)
 
 
+# --------------------------------------------------------------------------
+# Mixed-precision transform stage (FP32 / BF16x3 on MFMA), binary64 elsewhere
+# --------------------------------------------------------------------------
+
+# |D_mixed - D_64| <= eps * sum_e |Delta'_e| |K[e][c]| <= eps * K / 4 with
+# sum |Delta'| = K <= 63 and |K[e][c]| <= 1/4; eps covers the operand
+# rounding (FP32: 2 u32; BF16x3: 3 * 2^-16) and the 64-term FP32 accumulation.
+MIXED_EPS = {"fp32": 66 * 2.0 ** -24, "bf16x3": 3 * 2.0 ** -16 + 66 * 2.0 ** -24}
+D_ERR = {k: v * 63 / 4 for k, v in MIXED_EPS.items()}
+
+
+def compare_mixed(gpu, orc, code_x, phi_x, prec):
+    """f, s bit-exact; phi and codes equal except where the oracle's value
+    before truncation is within the arithmetic's error bound of an integer.
+    Returns (code mismatches, phi flips)."""
+    gf, gs, gphi, gcodes = gpu
+    of, os_, ophi, ocodes = orc
+    assert np.array_equal(gf.view(np.uint64), of.view(np.uint64)), "f"
+    assert np.array_equal(gs.view(np.uint64), os_.view(np.uint64)), "s"
+    dD = D_ERR[prec]
+    flips = np.flatnonzero(gphi != ophi)
+    for b in flips:
+        m = 127.0 / phi_x[b]
+        # 127/m moves by at most (127/m) * dD / (m - dD)
+        assert abs(int(gphi[b]) - int(ophi[b])) == 1, b
+        assert abs(phi_x[b] - np.round(phi_x[b])) <= phi_x[b] * dD / (m - dD), (b, phi_x[b])
+    D = code_x / ophi[:, None].astype(float)
+    want_x = gphi[:, None].astype(float) * D  # the oracle's values at the GPU's phi
+    want = np.trunc(want_x).astype(int)
+    diff = gcodes.astype(int) - want
+    bad = diff != 0
+    tol = gphi[:, None].astype(float) * dD
+    explained = (np.abs(diff) == 1) & (np.abs(want_x - np.round(want_x)) <= tol)
+    assert np.all(explained | ~bad), (f"{prec}: {int((bad & ~explained).sum())} codes off by more than "
+                                     f"the error bound")
+    return int(bad.sum()), len(flips)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("shape", [(64, 64), (1032, 528), (24, 8)])
+def test_compress_mixed_precision(prec, shape):
+    r, c = shape
+    A = smooth_field(r, 32, 8.0, 1e-4, 460 + r, cols=c)
+    t = dev(A)
+    g = blaz.compress(t, prec=prec)
+    o, (_, code_x, phi_x) = oracle.compress(A, with_debug=True)
+    mism, flips = compare_mixed(host(g), oracle_tuple(o), code_x, phi_x, prec)
+    n = o.codes.size
+    print(f"{prec} {shape}: {mism} code mismatches of {n}, {flips} phi flips")
+    # the binary64 codec is unaffected by the option
+    g64 = blaz.compress(t)
+    assert compare_compressed(host(g64), oracle_tuple(o), code_x, phi_x) == 0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_compress_mixed_precision_special_blocks_and_psi(prec):
+    A = np.vstack([special_blocks()[:, :64], smooth_field(8, 2, 0.5, 1e-3, 3, cols=64)])
+    p = torch.empty((A.size // 64, 64), dtype=torch.uint8, device="cuda")
+    g = blaz.compress(dev(A), prec=prec, psi=p)
+    o, (opsi, code_x, phi_x) = oracle.compress(A, with_debug=True)
+    compare_mixed(host(g), oracle_tuple(o), code_x, phi_x, prec)
+    # Psi is computed in binary64 before the transform, as in the plain path
+    p64 = torch.empty_like(p)
+    blaz.compress(dev(A), psi=p64)
+    assert torch.equal(p, p64)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_compress_mixed_precision_full_size_16384_sampled(prec):
+    """16384x16384 field (32 sinusoids, <= 32 cycles/side, N(0, 1e-4)): all
+    blocks on the GPU, a sample on the oracle; decompressed error next to the
+    method's own error."""
+    (A,) = workload_inputs("mixed-16384")
+    t = dev(A)
+    g = blaz.compress(t, prec=prec)
+    gh = host(g)
+    rng = np.random.default_rng(7)
+    nb = len(gh[0])
+    smp = np.unique(np.concatenate([[0, nb - 1], rng.integers(0, nb, 3000)]))
+    of, os_, ophi, ocodes, code_x, phi_x = oracle.compress_blocks(A, smp)
+    compare_mixed(tuple(a[smp] for a in gh), (of, os_, ophi, ocodes), code_x, phi_x, prec)
+    g64 = blaz.compress(t)
+    back = blaz.decompress(g)
+    back64 = blaz.decompress(g64)
+    own = (torch.linalg.norm(back64 - t) / torch.linalg.norm(t)).item()
+    mixed = (torch.linalg.norm(back - t) / torch.linalg.norm(t)).item()
+    delta = (torch.linalg.norm(back - back64) / torch.linalg.norm(t)).item()
+    print(f"{prec}: method error {own:.4e}, with {prec} transform {mixed:.4e}, difference {delta:.3e}")
+    assert mixed <= own * 1.01 + 1e-9
+
+
 # Low-precision contractions (FP32, BF16 hi+lo with three products).  Bound
 # on |C - C64| relative to sum_k |a_k b_k|: operand rounding (FP32: 2 u32;
 # BF16x3: 3 * 2^-16 from the split and the dropped lo*lo term) plus FP32
