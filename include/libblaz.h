@@ -170,6 +170,75 @@ blaz_status blaz_matmul(const blaz_matrix *a, const blaz_matrix *b, const double
                         int64_t ldb, double *c, int64_t ldc, blaz_precision prec, void *workspace,
                         size_t ws_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Batching: many operations, on matrices of any sizes, in one persistent
+ * launch.  Every 8x8 block is independent (the paper's blockwise
+ * generalisation, end of Section "Basic Linear Algebra Algorithms"), so the
+ * work of a batch is a flat queue of chunks -- 64 consecutive blocks of one
+ * compress / decompress / add / sub / scale, or one dot product -- that the
+ * launched workgroups pop with an atomic counter until the queue is empty.
+ * Each operation computes exactly what its standalone entry point computes
+ * (the same per-block code runs), bit for bit.
+ *
+ * Usage: blaz_batch_plan() validates the items with the same rules as the
+ * standalone calls and writes a plan image into caller-owned HOST memory;
+ * the caller copies that image to device memory (any stream-ordered copy);
+ * blaz_batch_run() then enqueues the launch.  The device plan can be run any
+ * number of times, including from a captured HIP graph: a run is two kernel
+ * launches (a one-thread counter reset, then the persistent kernel) and no
+ * memset or copy.  The items of one batch run concurrently: no item may read
+ * or write another item's output.  In a batch, the dense matrix of a
+ * COMPRESS or DECOMPRESS item must be 16-byte aligned with an even ld.
+ * ------------------------------------------------------------------------- */
+typedef enum {
+    BLAZ_OP_COMPRESS = 0,   /* x <- compress(dense, ld); binary64 transform      */
+    BLAZ_OP_DECOMPRESS = 1, /* dense (ld) <- decompress(x)                       */
+    BLAZ_OP_ADD = 2,        /* z <- x + y (Algorithm 1)                          */
+    BLAZ_OP_SUB = 3,        /* z <- x - y                                        */
+    BLAZ_OP_SCALE = 4,      /* z <- c x (Algorithm 2)                            */
+    BLAZ_OP_DOT = 5,        /* out[q] <- <line xrow[q] of x, column ycol[q] of y> */
+    BLAZ_OP_DOT_DENSE = 6   /* out[q] <- <line xrow[q] of x, dense + q*ld>       */
+} blaz_op;
+
+/* One operation of a batch (host memory; the pointers inside are device
+ * pointers, with the layouts and alignment of the standalone calls). */
+typedef struct blaz_batch_item {
+    int32_t op;           /* a blaz_op                                            */
+    int32_t reserved;     /* must be 0                                            */
+    blaz_matrix x;        /* COMPRESS: output; others: first operand              */
+    blaz_matrix y;        /* ADD, SUB: second operand; DOT: right operand         */
+    blaz_matrix z;        /* ADD, SUB, SCALE: output                              */
+    double *dense;        /* COMPRESS: input; DECOMPRESS: output; DOT_DENSE: vectors */
+    int64_t ld;           /* leading dimension of dense (DOT_DENSE: ldv, 0 = shared) */
+    double c;             /* SCALE: the constant                                  */
+    const int64_t *xrow;  /* DOT, DOT_DENSE: line indices (count)                 */
+    const int64_t *ycol;  /* DOT: column indices (count)                          */
+    int64_t count;        /* DOT, DOT_DENSE: number of products                   */
+    double *out;          /* DOT, DOT_DENSE: results (count)                      */
+} blaz_batch_item;
+
+/* Bytes of the plan image for n_items items (an upper bound: items with
+ * nothing to do are dropped from the plan). */
+size_t blaz_batch_plan_bytes(int64_t n_items);
+
+/* Validate items[0..n_items) and write the plan image into plan (host,
+ * plan_bytes >= blaz_batch_plan_bytes(n_items), 8-byte aligned).  On success
+ * *n_plan is the number of planned items and *total_chunks the length of the
+ * work queue.  On failure *n_plan holds the index of the first invalid item
+ * and nothing is written to device memory (nothing is, in any case: this is
+ * a host-only function). */
+blaz_status blaz_batch_plan(const blaz_batch_item *items, int64_t n_items, void *plan, size_t plan_bytes,
+                            int64_t *n_plan, int64_t *total_chunks);
+
+/* Run a plan whose image has been copied to plan_dev (device, 8-byte
+ * aligned).  counter: 8 bytes of device memory owned by the caller, reset
+ * by the run itself; concurrent runs need distinct counters.  workgroups:
+ * number of persistent workgroups (one wave each); 0 picks 8 per compute
+ * unit of the current device.  n_plan and total_chunks as returned by
+ * blaz_batch_plan. */
+blaz_status blaz_batch_run(const void *plan_dev, int64_t n_plan, int64_t total_chunks, uint64_t *counter,
+                           int64_t workgroups, hipStream_t stream);
+
 /* A static description of a status code. */
 const char *blaz_status_string(blaz_status status);
 

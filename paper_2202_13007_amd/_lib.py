@@ -23,7 +23,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 EXPORTS = (
     "blaz_block_count", "blaz_compressed_bytes", "blaz_compress", "blaz_decompress", "blaz_add",
     "blaz_sub", "blaz_scale", "blaz_dot", "blaz_dot_dense", "blaz_matmul_workspace_bytes",
-    "blaz_matmul", "blaz_status_string",
+    "blaz_matmul", "blaz_status_string", "blaz_batch_plan_bytes", "blaz_batch_plan", "blaz_batch_run",
 )
 
 
@@ -37,6 +37,27 @@ class BlazMatrixC(ctypes.Structure):
         ("phi", ctypes.c_void_p),
         ("codes", ctypes.c_void_p),
     ]
+
+
+class BatchItemC(ctypes.Structure):
+    """Mirror of ``blaz_batch_item``."""
+    _fields_ = [
+        ("op", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("x", BlazMatrixC),
+        ("y", BlazMatrixC),
+        ("z", BlazMatrixC),
+        ("dense", ctypes.c_void_p),
+        ("ld", ctypes.c_int64),
+        ("c", ctypes.c_double),
+        ("xrow", ctypes.c_void_p),
+        ("ycol", ctypes.c_void_p),
+        ("count", ctypes.c_int64),
+        ("out", ctypes.c_void_p),
+    ]
+
+
+OPS = {"compress": 0, "decompress": 1, "add": 2, "sub": 3, "scale": 4, "dot": 5, "dot_dense": 6}
 
 
 class BlazError(RuntimeError):
@@ -79,6 +100,9 @@ def lib():
         "blaz_matmul_workspace_bytes": ([I64, I64, I64, I, I], ctypes.c_size_t),
         "blaz_matmul": ([M, M, P, I64, I64, P, I64, I, P, ctypes.c_size_t, P], I),
         "blaz_status_string": ([I], ctypes.c_char_p),
+        "blaz_batch_plan_bytes": ([I64], ctypes.c_size_t),
+        "blaz_batch_plan": ([P, I64, P, ctypes.c_size_t, P, P], I),
+        "blaz_batch_run": ([P, I64, I64, P, I64, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)

@@ -182,3 +182,91 @@ def matmul(a: BlazMatrix, b: BlazMatrix | torch.Tensor, out: torch.Tensor | None
                                  _ptr(out), out.stride(0), _lib.PREC[prec], _ptr(workspace),
                                  workspace.numel(), _stream()), "blaz_matmul")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Batching: many operations in one persistent launch
+# ---------------------------------------------------------------------------
+
+class Batch:
+    """Collects operations; ``plan()`` validates them and uploads the plan.
+
+    Items run concurrently: no item may use another item's output.  Tensors
+    referenced by the items are kept alive by the batch and its plans."""
+
+    def __init__(self):
+        self.items = []
+        self._keep = []
+
+    def _add(self, op, x=None, y=None, z=None, dense=None, ld=0, c=0.0, xrow=None, ycol=None, count=0, out=None):
+        it = _lib.BatchItemC()
+        it.op = _lib.OPS[op]
+        it.reserved = 0
+        empty = BlazMatrixC(0, 0, None, None, None, None)
+        it.x = x.c() if x is not None else empty
+        it.y = y.c() if y is not None else empty
+        it.z = z.c() if z is not None else empty
+        it.dense = None if dense is None else dense.data_ptr()
+        it.ld = ld
+        it.c = float(c)
+        it.xrow = None if xrow is None else xrow.data_ptr()
+        it.ycol = None if ycol is None else ycol.data_ptr()
+        it.count = count
+        it.out = None if out is None else out.data_ptr()
+        self.items.append(it)
+        self._keep.extend(t for t in (x, y, z, dense, xrow, ycol, out) if t is not None)
+        return self
+
+    def compress(self, A: torch.Tensor, out: BlazMatrix):
+        _check_dense(A, "batch compress")
+        return self._add("compress", x=out, dense=A, ld=A.stride(0))
+
+    def decompress(self, x: BlazMatrix, out: torch.Tensor):
+        _check_dense(out, "batch decompress")
+        return self._add("decompress", x=x, dense=out, ld=out.stride(0))
+
+    def add(self, x: BlazMatrix, y: BlazMatrix, out: BlazMatrix):
+        return self._add("add", x=x, y=y, z=out)
+
+    def sub(self, x: BlazMatrix, y: BlazMatrix, out: BlazMatrix):
+        return self._add("sub", x=x, y=y, z=out)
+
+    def scale(self, x: BlazMatrix, c: float, out: BlazMatrix):
+        return self._add("scale", x=x, z=out, c=c)
+
+    def dot(self, x: BlazMatrix, xrow: torch.Tensor, y: BlazMatrix, ycol: torch.Tensor, out: torch.Tensor):
+        return self._add("dot", x=x, y=y, xrow=xrow, ycol=ycol, count=xrow.numel(), out=out)
+
+    def dot_dense(self, x: BlazMatrix, xrow: torch.Tensor, v: torch.Tensor, out: torch.Tensor):
+        ld = 0 if v.dim() == 1 else v.stride(0)
+        return self._add("dot_dense", x=x, dense=v, ld=ld, xrow=xrow, count=xrow.numel(), out=out)
+
+    def plan(self, device=None) -> "BatchPlan":
+        n = len(self.items)
+        arr = (_lib.BatchItemC * max(n, 1))(*self.items)
+        nbytes = int(_lib.lib().blaz_batch_plan_bytes(n))
+        host = torch.empty(max(nbytes, 8), dtype=torch.uint8, pin_memory=torch.cuda.is_available())
+        n_plan = ctypes.c_int64()
+        total = ctypes.c_int64()
+        st = _lib.lib().blaz_batch_plan(ctypes.cast(arr, ctypes.c_void_p), n, ctypes.c_void_p(host.data_ptr()),
+                                        host.numel(), ctypes.byref(n_plan), ctypes.byref(total))
+        if st != _lib.BLAZ_OK:
+            raise _lib.BlazError(st, f"blaz_batch_plan (item {n_plan.value})")
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        plan_dev = host.to(dev, non_blocking=True)
+        counter = torch.zeros(1, dtype=torch.int64, device=dev)
+        return BatchPlan(plan_dev, host, n_plan.value, total.value, counter, list(self._keep))
+
+
+class BatchPlan:
+    """A validated batch resident on the device; ``run()`` enqueues it."""
+
+    def __init__(self, plan_dev, plan_host, n_plan, total_chunks, counter, keep):
+        self.plan_dev, self.plan_host = plan_dev, plan_host
+        self.n_plan, self.total_chunks = n_plan, total_chunks
+        self.counter = counter
+        self._keep = keep
+
+    def run(self, workgroups: int = 0):
+        check(_lib.lib().blaz_batch_run(_ptr(self.plan_dev), self.n_plan, self.total_chunks, _ptr(self.counter),
+                                        int(workgroups), _stream()), "blaz_batch_run")

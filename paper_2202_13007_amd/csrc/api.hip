@@ -5,89 +5,13 @@
 #include <cstdint>
 
 #include "blaz_internal.hpp"
+#include "blaz_validate.hpp"
 
 #define BLAZ_API extern "C" __attribute__((visibility("default")))
 
-namespace {
-
+using namespace blaz::validate;
 using blaz::detail::launch_add;
 
-constexpr int64_t kRecordBytes = 45;  // f (8) + s (8) + phi (1) + 28 codes
-constexpr int64_t kMaxDots = int64_t(1) << 32;  // four dot products per workgroup
-
-bool aligned(const void* p, uintptr_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
-
-blaz_status check_shape(int64_t rows, int64_t cols)
-{
-    if (rows < 0 || cols < 0 || rows % 8 != 0 || cols % 8 != 0) return BLAZ_ERR_SHAPE;
-    // keep the one-lane-per-block grids (256 lanes per workgroup) well
-    // within 2^31 workgroups: at most 2^38 blocks
-    if (rows > 0 && cols > 0 && (rows / 8) > (int64_t(1) << 38) / (cols / 8)) return BLAZ_ERR_SHAPE;
-    return BLAZ_OK;
-}
-
-int64_t nblocks(const blaz_matrix& m) { return (m.rows / 8) * (m.cols / 8); }
-
-// A descriptor is valid if its shape is and, when it holds blocks, its four
-// arrays are present and aligned.
-blaz_status check_matrix(const blaz_matrix* m)
-{
-    if (!m) return BLAZ_ERR_NULL;
-    if (blaz_status st = check_shape(m->rows, m->cols)) return st;
-    if (nblocks(*m) == 0) return BLAZ_OK;
-    if (!m->f || !m->s || !m->phi || !m->codes) return BLAZ_ERR_NULL;
-    if (!aligned(m->f, 8) || !aligned(m->s, 8) || !aligned(m->codes, 4)) return BLAZ_ERR_ALIGN;
-    return BLAZ_OK;
-}
-
-struct Range {
-    uintptr_t lo, hi;
-};
-Range span(const void* p, int64_t bytes)
-{
-    const auto a = reinterpret_cast<uintptr_t>(p);
-    return {a, a + (uintptr_t)(bytes > 0 ? bytes : 0)};
-}
-bool overlap(Range a, Range b) { return a.lo < b.hi && b.lo < a.hi; }
-
-// The byte ranges of a compressed matrix's four arrays.
-void ranges(const blaz_matrix& m, Range r[4])
-{
-    const int64_t n = nblocks(m);
-    r[0] = span(m.f, 8 * n);
-    r[1] = span(m.s, 8 * n);
-    r[2] = span(m.phi, n);
-    r[3] = span(m.codes, 28 * n);
-}
-
-bool overlaps_matrix(Range a, const blaz_matrix& m)
-{
-    Range r[4];
-    ranges(m, r);
-    for (auto& x : r)
-        if (overlap(a, x)) return true;
-    return false;
-}
-
-// z must either be exactly x (same four arrays) or not overlap it at all.
-bool same_or_disjoint(const blaz_matrix& z, const blaz_matrix& x)
-{
-    if (z.f == x.f && z.s == x.s && z.phi == x.phi && z.codes == x.codes) return true;
-    Range rz[4];
-    ranges(z, rz);
-    for (auto& r : rz)
-        if (overlaps_matrix(r, x)) return false;
-    return true;
-}
-
-// Bytes spanned by a rows x cols row-major matrix with leading dimension ld.
-int64_t dense_span(int64_t rows, int64_t cols, int64_t ld) { return rows == 0 ? 0 : ((rows - 1) * ld + cols) * 8; }
-
-blaz_status hip_status(hipError_t e) { return e == hipSuccess ? BLAZ_OK : BLAZ_ERR_HIP; }
-
-size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-}  // namespace
 
 BLAZ_API int64_t blaz_block_count(int64_t rows, int64_t cols)
 {
@@ -104,40 +28,27 @@ BLAZ_API size_t blaz_compressed_bytes(int64_t rows, int64_t cols)
 BLAZ_API blaz_status blaz_compress(const double* A, int64_t lda, const blaz_matrix* out, blaz_precision prec,
                                    uint8_t* psi, hipStream_t stream)
 {
-    if (blaz_status st = check_matrix(out)) return st;
-    if (prec != BLAZ_PREC_FP64 && prec != BLAZ_PREC_FP32 && prec != BLAZ_PREC_BF16X3) return BLAZ_ERR_ARG;
-    const int64_t nblk = nblocks(*out);
-    if (nblk == 0) return BLAZ_OK;
-    if (!A) return BLAZ_ERR_NULL;
-    if (lda < out->cols) return BLAZ_ERR_SHAPE;
-    if (!aligned(A, 8) || (psi && !aligned(psi, 16))) return BLAZ_ERR_ALIGN;
-    const Range ra = span(A, dense_span(out->rows, out->cols, lda));
-    if (overlaps_matrix(ra, *out)) return BLAZ_ERR_ARG;
-    if (psi && (overlap(span(psi, 64 * nblk), ra) || overlaps_matrix(span(psi, 64 * nblk), *out))) return BLAZ_ERR_ARG;
+    bool empty;
+    if (blaz_status st = validate_compress(A, lda, out, prec, psi, &empty)) return st;
+    if (empty) return BLAZ_OK;
     if (prec == BLAZ_PREC_FP64) return hip_status(blaz::detail::launch_compress_f64(A, lda, *out, psi, stream));
     return hip_status(blaz::detail::launch_compress_mixed(A, lda, *out, psi, prec, stream));
 }
 
 BLAZ_API blaz_status blaz_decompress(const blaz_matrix* in, double* A, int64_t lda, hipStream_t stream)
 {
-    if (blaz_status st = check_matrix(in)) return st;
-    if (nblocks(*in) == 0) return BLAZ_OK;
-    if (!A) return BLAZ_ERR_NULL;
-    if (lda < in->cols) return BLAZ_ERR_SHAPE;
-    if (!aligned(A, 8)) return BLAZ_ERR_ALIGN;
-    if (overlaps_matrix(span(A, dense_span(in->rows, in->cols, lda)), *in)) return BLAZ_ERR_ARG;
+    bool empty;
+    if (blaz_status st = validate_decompress(in, A, lda, &empty)) return st;
+    if (empty) return BLAZ_OK;
     return hip_status(blaz::detail::launch_decompress(*in, A, lda, stream));
 }
 
 static blaz_status add_or_sub(const blaz_matrix* x, const blaz_matrix* y, const blaz_matrix* z, bool sub,
                               hipStream_t stream)
 {
-    for (const blaz_matrix* m : {x, y, z})
-        if (blaz_status st = check_matrix(m)) return st;
-    if (x->rows != y->rows || x->cols != y->cols || x->rows != z->rows || x->cols != z->cols)
-        return BLAZ_ERR_MISMATCH;
-    if (nblocks(*x) == 0) return BLAZ_OK;
-    if (!same_or_disjoint(*z, *x) || !same_or_disjoint(*z, *y)) return BLAZ_ERR_ARG;
+    bool empty;
+    if (blaz_status st = validate_add(x, y, z, &empty)) return st;
+    if (empty) return BLAZ_OK;
     return hip_status(launch_add(*x, *y, *z, sub, stream));
 }
 
@@ -153,38 +64,27 @@ BLAZ_API blaz_status blaz_sub(const blaz_matrix* x, const blaz_matrix* y, const 
 
 BLAZ_API blaz_status blaz_scale(const blaz_matrix* x, double c, const blaz_matrix* z, hipStream_t stream)
 {
-    for (const blaz_matrix* m : {x, z})
-        if (blaz_status st = check_matrix(m)) return st;
-    if (x->rows != z->rows || x->cols != z->cols) return BLAZ_ERR_MISMATCH;
-    if (nblocks(*x) == 0) return BLAZ_OK;
-    if (!same_or_disjoint(*z, *x)) return BLAZ_ERR_ARG;
+    bool empty;
+    if (blaz_status st = validate_scale(x, z, &empty)) return st;
+    if (empty) return BLAZ_OK;
     return hip_status(blaz::detail::launch_scale(*x, c, *z, stream));
 }
 
 BLAZ_API blaz_status blaz_dot(const blaz_matrix* x, const int64_t* xrow, const blaz_matrix* y, const int64_t* ycol,
                               int64_t count, double* out, hipStream_t stream)
 {
-    for (const blaz_matrix* m : {x, y})
-        if (blaz_status st = check_matrix(m)) return st;
-    if (x->cols != y->rows) return BLAZ_ERR_MISMATCH;
-    if (count < 0 || count > kMaxDots) return BLAZ_ERR_ARG;
-    if (count == 0) return BLAZ_OK;
-    if (!xrow || !ycol || !out) return BLAZ_ERR_NULL;
-    if (!aligned(xrow, 8) || !aligned(ycol, 8) || !aligned(out, 8)) return BLAZ_ERR_ALIGN;
-    if (overlaps_matrix(span(out, 8 * count), *x) || overlaps_matrix(span(out, 8 * count), *y)) return BLAZ_ERR_ARG;
+    bool empty;
+    if (blaz_status st = validate_dot(x, xrow, y, ycol, count, out, &empty)) return st;
+    if (empty) return BLAZ_OK;
     return hip_status(blaz::detail::launch_dot(*x, xrow, *y, ycol, count, out, stream));
 }
 
 BLAZ_API blaz_status blaz_dot_dense(const blaz_matrix* x, const int64_t* xrow, const double* v, int64_t ldv,
                                     int64_t count, double* out, hipStream_t stream)
 {
-    if (blaz_status st = check_matrix(x)) return st;
-    if (count < 0 || count > kMaxDots || ldv < 0) return BLAZ_ERR_ARG;
-    if (ldv != 0 && ldv < x->cols) return BLAZ_ERR_SHAPE;
-    if (count == 0) return BLAZ_OK;
-    if (!xrow || !v || !out) return BLAZ_ERR_NULL;
-    if (!aligned(xrow, 8) || !aligned(out, 8) || !aligned(v, 16) || ldv % 2 != 0) return BLAZ_ERR_ALIGN;
-    if (overlaps_matrix(span(out, 8 * count), *x)) return BLAZ_ERR_ARG;
+    bool empty;
+    if (blaz_status st = validate_dot_dense(x, xrow, v, ldv, count, out, &empty)) return st;
+    if (empty) return BLAZ_OK;
     return hip_status(blaz::detail::launch_dot_dense(*x, xrow, v, ldv, count, out, stream));
 }
 

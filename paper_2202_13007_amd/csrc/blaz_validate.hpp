@@ -1,0 +1,182 @@
+// Host-side argument checks shared by the C-ABI entry points: shapes,
+// NULL and alignment of descriptors, and byte-range overlap tests.  None of
+// them touches device memory or calls the HIP runtime.
+#pragma once
+
+#include <cstdint>
+
+#include "libblaz.h"
+
+namespace blaz {
+namespace validate {
+
+constexpr int64_t kRecordBytes = 45;  // f (8) + s (8) + phi (1) + 28 codes
+constexpr int64_t kMaxDots = int64_t(1) << 32;  // four dot products per workgroup
+
+inline bool aligned(const void* p, uintptr_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
+
+inline blaz_status check_shape(int64_t rows, int64_t cols)
+{
+    if (rows < 0 || cols < 0 || rows % 8 != 0 || cols % 8 != 0) return BLAZ_ERR_SHAPE;
+    // keep the one-lane-per-block grids (256 lanes per workgroup) well
+    // within 2^31 workgroups: at most 2^38 blocks
+    if (rows > 0 && cols > 0 && (rows / 8) > (int64_t(1) << 38) / (cols / 8)) return BLAZ_ERR_SHAPE;
+    return BLAZ_OK;
+}
+
+inline int64_t nblocks(const blaz_matrix& m) { return (m.rows / 8) * (m.cols / 8); }
+
+// A descriptor is valid if its shape is and, when it holds blocks, its four
+// arrays are present and aligned.
+inline blaz_status check_matrix(const blaz_matrix* m)
+{
+    if (!m) return BLAZ_ERR_NULL;
+    if (blaz_status st = check_shape(m->rows, m->cols)) return st;
+    if (nblocks(*m) == 0) return BLAZ_OK;
+    if (!m->f || !m->s || !m->phi || !m->codes) return BLAZ_ERR_NULL;
+    if (!aligned(m->f, 8) || !aligned(m->s, 8) || !aligned(m->codes, 4)) return BLAZ_ERR_ALIGN;
+    return BLAZ_OK;
+}
+
+struct Range {
+    uintptr_t lo, hi;
+};
+inline Range span(const void* p, int64_t bytes)
+{
+    const auto a = reinterpret_cast<uintptr_t>(p);
+    return {a, a + (uintptr_t)(bytes > 0 ? bytes : 0)};
+}
+inline bool overlap(Range a, Range b) { return a.lo < b.hi && b.lo < a.hi; }
+
+// The byte ranges of a compressed matrix's four arrays.
+inline void ranges(const blaz_matrix& m, Range r[4])
+{
+    const int64_t n = nblocks(m);
+    r[0] = span(m.f, 8 * n);
+    r[1] = span(m.s, 8 * n);
+    r[2] = span(m.phi, n);
+    r[3] = span(m.codes, 28 * n);
+}
+
+inline bool overlaps_matrix(Range a, const blaz_matrix& m)
+{
+    Range r[4];
+    ranges(m, r);
+    for (auto& x : r)
+        if (overlap(a, x)) return true;
+    return false;
+}
+
+// z must either be exactly x (same four arrays) or not overlap it at all.
+inline bool same_or_disjoint(const blaz_matrix& z, const blaz_matrix& x)
+{
+    if (z.f == x.f && z.s == x.s && z.phi == x.phi && z.codes == x.codes) return true;
+    Range rz[4];
+    ranges(z, rz);
+    for (auto& r : rz)
+        if (overlaps_matrix(r, x)) return false;
+    return true;
+}
+
+// Bytes spanned by a rows x cols row-major matrix with leading dimension ld.
+inline int64_t dense_span(int64_t rows, int64_t cols, int64_t ld) { return rows == 0 ? 0 : ((rows - 1) * ld + cols) * 8; }
+
+inline blaz_status hip_status(hipError_t e) { return e == hipSuccess ? BLAZ_OK : BLAZ_ERR_HIP; }
+
+inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+
+// ---------------------------------------------------------------------------
+// Per-operation checks.  Each returns BLAZ_OK and sets *empty when the call
+// has nothing to do, or the first violated rule's status.
+// ---------------------------------------------------------------------------
+
+inline blaz_status validate_compress(const double* A, int64_t lda, const blaz_matrix* out, blaz_precision prec,
+                                     const uint8_t* psi, bool* empty)
+{
+    *empty = true;
+    if (blaz_status st = check_matrix(out)) return st;
+    if (prec != BLAZ_PREC_FP64 && prec != BLAZ_PREC_FP32 && prec != BLAZ_PREC_BF16X3) return BLAZ_ERR_ARG;
+    const int64_t nblk = nblocks(*out);
+    if (nblk == 0) return BLAZ_OK;
+    if (!A) return BLAZ_ERR_NULL;
+    if (lda < out->cols) return BLAZ_ERR_SHAPE;
+    if (!aligned(A, 8) || (psi && !aligned(psi, 16))) return BLAZ_ERR_ALIGN;
+    const Range ra = span(A, dense_span(out->rows, out->cols, lda));
+    if (overlaps_matrix(ra, *out)) return BLAZ_ERR_ARG;
+    if (psi && (overlap(span(psi, 64 * nblk), ra) || overlaps_matrix(span(psi, 64 * nblk), *out))) return BLAZ_ERR_ARG;
+    *empty = false;
+    return BLAZ_OK;
+}
+
+inline blaz_status validate_decompress(const blaz_matrix* in, const double* A, int64_t lda, bool* empty)
+{
+    *empty = true;
+    if (blaz_status st = check_matrix(in)) return st;
+    if (nblocks(*in) == 0) return BLAZ_OK;
+    if (!A) return BLAZ_ERR_NULL;
+    if (lda < in->cols) return BLAZ_ERR_SHAPE;
+    if (!aligned(A, 8)) return BLAZ_ERR_ALIGN;
+    if (overlaps_matrix(span(A, dense_span(in->rows, in->cols, lda)), *in)) return BLAZ_ERR_ARG;
+    *empty = false;
+    return BLAZ_OK;
+}
+
+inline blaz_status validate_add(const blaz_matrix* x, const blaz_matrix* y, const blaz_matrix* z, bool* empty)
+{
+    *empty = true;
+    for (const blaz_matrix* m : {x, y, z})
+        if (blaz_status st = check_matrix(m)) return st;
+    if (x->rows != y->rows || x->cols != y->cols || x->rows != z->rows || x->cols != z->cols)
+        return BLAZ_ERR_MISMATCH;
+    if (nblocks(*x) == 0) return BLAZ_OK;
+    if (!same_or_disjoint(*z, *x) || !same_or_disjoint(*z, *y)) return BLAZ_ERR_ARG;
+    *empty = false;
+    return BLAZ_OK;
+}
+
+inline blaz_status validate_scale(const blaz_matrix* x, const blaz_matrix* z, bool* empty)
+{
+    *empty = true;
+    for (const blaz_matrix* m : {x, z})
+        if (blaz_status st = check_matrix(m)) return st;
+    if (x->rows != z->rows || x->cols != z->cols) return BLAZ_ERR_MISMATCH;
+    if (nblocks(*x) == 0) return BLAZ_OK;
+    if (!same_or_disjoint(*z, *x)) return BLAZ_ERR_ARG;
+    *empty = false;
+    return BLAZ_OK;
+}
+
+inline blaz_status validate_dot(const blaz_matrix* x, const int64_t* xrow, const blaz_matrix* y, const int64_t* ycol,
+                                int64_t count, const double* out, bool* empty)
+{
+    *empty = true;
+    for (const blaz_matrix* m : {x, y})
+        if (blaz_status st = check_matrix(m)) return st;
+    if (x->cols != y->rows) return BLAZ_ERR_MISMATCH;
+    if (count < 0 || count > kMaxDots) return BLAZ_ERR_ARG;
+    if (count == 0) return BLAZ_OK;
+    if (!xrow || !ycol || !out) return BLAZ_ERR_NULL;
+    if (!aligned(xrow, 8) || !aligned(ycol, 8) || !aligned(out, 8)) return BLAZ_ERR_ALIGN;
+    if (overlaps_matrix(span(out, 8 * count), *x) || overlaps_matrix(span(out, 8 * count), *y)) return BLAZ_ERR_ARG;
+    *empty = false;
+    return BLAZ_OK;
+}
+
+inline blaz_status validate_dot_dense(const blaz_matrix* x, const int64_t* xrow, const double* v, int64_t ldv,
+                                      int64_t count, const double* out, bool* empty)
+{
+    *empty = true;
+    if (blaz_status st = check_matrix(x)) return st;
+    if (count < 0 || count > kMaxDots || ldv < 0) return BLAZ_ERR_ARG;
+    if (ldv != 0 && ldv < x->cols) return BLAZ_ERR_SHAPE;
+    if (count == 0) return BLAZ_OK;
+    if (!xrow || !v || !out) return BLAZ_ERR_NULL;
+    if (!aligned(xrow, 8) || !aligned(out, 8) || !aligned(v, 16) || ldv % 2 != 0) return BLAZ_ERR_ALIGN;
+    if (overlaps_matrix(span(out, 8 * count), *x)) return BLAZ_ERR_ARG;
+    *empty = false;
+    return BLAZ_OK;
+}
+
+}  // namespace validate
+}  // namespace blaz

@@ -23,62 +23,9 @@ __global__ __launch_bounds__(kWave) void compress_f64_kernel(const double* __res
                                                              uint8_t* __restrict__ psi)
 {
     __shared__ __align__(16) double tile[kWave * kSlot];
-    const int lane = threadIdx.x;
-    const int64_t wave_base = (int64_t)blockIdx.x * kWave;
-
-    double x[64];
-    load_blocks<kVec>(A, lda, nbc, nblk, wave_base, lane, tile, x);
-    const SlopeOut so_ = normalize_and_slope(x);
-    if constexpr (kPsi) predict_store(x, so_.s, psi, wave_base + lane, wave_base + lane < nblk);
-
-    // Two-dimensional DCT-II (Eq. eqdct) of Delta': rows, then columns, in
-    // place; the DC term is the fixed-order binary64 value.
-#pragma unroll
-    for (int u = 0; u < 8; ++u) dct8<1, 1>(x + u * 8, x + u * 8);
-#pragma unroll
-    for (int v = 0; v < 8; ++v) dct8<8, 8>(x + v, x + v);
-    x[0] = so_.dc;
-
-    quantize_store(x, so_, nblk, wave_base, lane, tile, fo, so, phio, codes);
+    compress_wave<kVec, kPsi>(A, lda, nbc, nblk, fo, so, phio, codes, psi, (int64_t)blockIdx.x * kWave,
+                              (int)threadIdx.x, tile);
 }
-
-// Output forms of the decompression: binary64 (the plain method), and the
-// operand forms of the low-precision contractions in blaz_matmul: FP32, or
-// BF16 hi + lo with hi = bf16(x), lo = bf16(x - hi).
-struct OutF64 {
-    double* p;
-    __device__ void store2(int64_t off, double a, double b) const
-    {
-        __builtin_nontemporal_store(f64x2{a, b}, reinterpret_cast<f64x2*>(p + off));
-    }
-    __device__ void store(int64_t off, double a) const { p[off] = a; }
-};
-struct OutF32 {
-    float* p;
-    __device__ void store2(int64_t off, double a, double b) const
-    {
-        *reinterpret_cast<f32x2*>(p + off) = f32x2{(float)a, (float)b};
-    }
-    __device__ void store(int64_t off, double a) const { p[off] = (float)a; }
-};
-struct OutBF16Split {
-    __bf16* hi;
-    __bf16* lo;
-    __device__ static __bf16 high(double x) { return (__bf16)(float)x; }
-    __device__ static __bf16 low(double x, __bf16 h) { return (__bf16)(float)(x - (double)(float)h); }
-    __device__ void store2(int64_t off, double a, double b) const
-    {
-        const __bf16 ha = high(a), hb = high(b);
-        *reinterpret_cast<bf16x2*>(hi + off) = bf16x2{ha, hb};
-        *reinterpret_cast<bf16x2*>(lo + off) = bf16x2{low(a, ha), low(b, hb)};
-    }
-    __device__ void store(int64_t off, double a) const
-    {
-        const __bf16 h = high(a);
-        hi[off] = h;
-        lo[off] = low(a, h);
-    }
-};
 
 template <bool kVec, typename Out>
 __global__ __launch_bounds__(kWave) void decompress_kernel(const double* __restrict__ f, const double* __restrict__ s,
@@ -87,60 +34,7 @@ __global__ __launch_bounds__(kWave) void decompress_kernel(const double* __restr
                                                            int64_t nblk, Out out, int64_t lda)
 {
     __shared__ __align__(16) double tile[kWave * kSlot];
-    const int lane = threadIdx.x;
-    const int64_t wave_base = (int64_t)blockIdx.x * kWave;
-    const int64_t b = wave_base + lane;
-    const bool valid = b < nblk;
-
-    // The wave's codes: consecutive dwords into LDS, then each lane's 7.
-    uint32_t* ct = reinterpret_cast<uint32_t*>(tile);
-    const int64_t nwords = (nblk - wave_base < kWave ? nblk - wave_base : kWave) * kCodeWords;
-    const uint32_t* csrc = codes + wave_base * kCodeWords;
-#pragma unroll
-    for (int k = 0; k < kCodeWords; ++k) {
-        const int idx = lane + kWave * k;
-        if (idx < nwords) ct[idx] = csrc[idx];
-    }
-    __syncthreads();
-    uint32_t w[kCodeWords];
-#pragma unroll
-    for (int q = 0; q < kCodeWords; ++q) w[q] = ct[lane * kCodeWords + q];
-    __syncthreads();
-
-    const double fb = valid ? f[b] : 0.0;
-    const double sb = valid ? s[b] : 0.0;
-    const double pb = valid ? (double)phi[b] : 1.0;
-    // Dhat = C / phi at the kept positions (zero elsewhere); the slope factor
-    // of Eq. eqbbb is folded in by linearity of the inverse DCT.
-    double coef[kKept];
-    unpack_codes(w, sb / pb, coef);
-    double x[64];
-    inverse_transform(coef, x);
-    inverse_normalize(fb, x);
-
-    if constexpr (kVec) {
-        const WaveChunks wc = wave_chunks(wave_base, lane, nbc, nblk, lda);
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-#pragma unroll
-            for (int p = 0; p < 4; ++p)
-                *reinterpret_cast<f64x2*>(&tile[lane * kSlot + 2 * p]) = f64x2{x[r * 8 + 2 * p], x[r * 8 + 2 * p + 1]};
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const f64x2 v = *reinterpret_cast<const f64x2*>(&tile[((lane >> 2) + 16 * k) * kSlot + 2 * (lane & 3)]);
-                if (wc.ok[k]) out.store2(wc.off[k] + r * lda, v[0], v[1]);
-            }
-            __syncthreads();
-        }
-    } else if (valid) {
-        const int64_t I = b / nbc, J = b - (b / nbc) * nbc;
-        const int64_t base = (I * 8) * lda + J * 8;
-#pragma unroll
-        for (int r = 0; r < 8; ++r)
-#pragma unroll
-            for (int c = 0; c < 8; ++c) out.store(base + r * lda + c, x[r * 8 + c]);
-    }
+    decompress_wave<kVec>(f, s, phi, codes, nbc, nblk, out, lda, (int64_t)blockIdx.x * kWave, (int)threadIdx.x, tile);
 }
 
 namespace detail {

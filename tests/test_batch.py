@@ -1,0 +1,216 @@
+"""Batching: one persistent launch over a flat chunk queue.
+
+CPU tests cover the host-only planner (validation, chunk counts, dropped
+empty items).  GPU tests check that every batched result equals the
+standalone entry point's result bit for bit, for several grid sizes and
+when the run is captured in a HIP graph and replayed.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from synth import smooth_field, uniform_matrix
+
+
+# --------------------------------------------------------------------------
+# Planner (host only: fake device addresses are never dereferenced)
+# --------------------------------------------------------------------------
+
+def _lib():
+    import os
+    from paper_2202_13007_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2202_13007_amd import _build
+        _build.build()
+    return L
+
+
+def fake_matrix(rows, cols, base):
+    L = _lib()
+    nb = (rows // 8) * (cols // 8)
+    return L.BlazMatrixC(rows, cols, base, base + 8 * nb + 64, base + 16 * nb + 128,
+                         base + (17 * nb + 256 + 15) // 16 * 16)
+
+
+def item(op, **kw):
+    L = _lib()
+    it = L.BatchItemC()
+    it.op = L.OPS[op]
+    for k, v in kw.items():
+        setattr(it, k, v)
+    return it
+
+
+def plan(items):
+    L = _lib()
+    n = len(items)
+    arr = (L.BatchItemC * max(n, 1))(*items)
+    nbytes = L.lib().blaz_batch_plan_bytes(n)
+    buf = (ctypes.c_uint8 * max(nbytes, 8))()
+    n_plan, total = ctypes.c_int64(), ctypes.c_int64()
+    st = L.lib().blaz_batch_plan(ctypes.cast(arr, ctypes.c_void_p), n, ctypes.cast(buf, ctypes.c_void_p),
+                                 max(nbytes, 8), ctypes.byref(n_plan), ctypes.byref(total))
+    return st, n_plan.value, total.value
+
+
+def test_plan_counts_chunks_and_drops_empty_items():
+    items = [
+        item("compress", x=fake_matrix(16, 1032, 0x1000000), dense=0x8000000, ld=1032),   # 258 blocks -> 5
+        item("add", x=fake_matrix(8, 8, 0x2000000), y=fake_matrix(8, 8, 0x3000000),
+             z=fake_matrix(8, 8, 0x4000000)),                                             # 1 block -> 1
+        item("scale", x=fake_matrix(0, 64, 0), z=fake_matrix(0, 64, 0), c=2.0),          # empty
+        item("dot", x=fake_matrix(16, 24, 0x5000000), y=fake_matrix(24, 8, 0x6000000),
+             xrow=0x7000000, ycol=0x7100000, count=7, out=0x7200000),                     # 7 dots -> 7
+        item("decompress", x=fake_matrix(64, 64, 0x9000000), dense=0xa000000, ld=64),    # 64 blocks -> 1
+    ]
+    st, n_plan, total = plan(items)
+    assert st == 0 and n_plan == 4 and total == 5 + 1 + 7 + 1
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(op=9), -5),                                   # unknown op
+    (dict(reserved=1), -5),
+    (dict(ld=8), -2),                                   # ld < cols
+    (dict(dense=0x8000008), -4),                        # batched codec items need 16-byte alignment
+    (dict(ld=1033), -4),                                # ... and an even ld
+    (dict(dense=0), -1),
+])
+def test_plan_rejects_invalid_item_and_reports_its_index(bad, status):
+    good = item("scale", x=fake_matrix(8, 64, 0x2000000), z=fake_matrix(8, 64, 0x3000000), c=1.5)
+    it = item("compress", x=fake_matrix(16, 1032, 0x1000000), dense=0x8000000, ld=1034)
+    for k, v in bad.items():
+        setattr(it, k, v)
+    st, n_plan, total = plan([good, it, good])
+    assert st == status and n_plan == 1 and total == 0
+
+
+def test_plan_rejects_partial_overlap():
+    x = fake_matrix(8, 64, 0x2000000)
+    z = fake_matrix(8, 64, 0x2000000 + 8)
+    st, n_plan, _ = plan([item("scale", x=x, z=z, c=2.0)])
+    assert st == -5 and n_plan == 0
+
+
+# --------------------------------------------------------------------------
+# GPU: batched results equal the standalone calls
+# --------------------------------------------------------------------------
+
+def make_workload(torch, blaz):
+    """A mix of operations on matrices of uneven sizes, with both the batch
+    and the standalone results' destinations."""
+    rng = np.random.default_rng(0)
+    shapes = [(8, 8), (64, 64), (24, 1032), (264, 520), (1032, 528)]
+    dense = [torch.from_numpy(smooth_field(r, 6, 3.0, 1e-3, 900 + i, cols=c)).cuda() for i, (r, c) in enumerate(shapes)]
+    dense2 = [torch.from_numpy(smooth_field(r, 6, 3.0, 1e-3, 950 + i, cols=c)).cuda() for i, (r, c) in enumerate(shapes)]
+    # operands for the ops, compressed by the standalone path
+    X = [blaz.compress(d) for d in dense]
+    Y = [blaz.compress(d) for d in dense2]
+    B = blaz.Batch()
+    expect = []  # (batched destination, standalone result)
+    for i, (r, c) in enumerate(shapes):
+        out = blaz.BlazMatrix.empty(r, c)
+        B.compress(dense[i], out)
+        expect.append((out, X[i]))
+        z = blaz.BlazMatrix.empty(r, c)
+        B.add(X[i], Y[i], z)
+        expect.append((z, blaz.add(X[i], Y[i])))
+        w = blaz.BlazMatrix.empty(r, c)
+        B.sub(X[i], Y[i], w)
+        expect.append((w, blaz.sub(X[i], Y[i])))
+        v = blaz.BlazMatrix.empty(r, c)
+        B.scale(Y[i], -1.7, v)
+        expect.append((v, blaz.scale(Y[i], -1.7)))
+        D = torch.empty((r, c), dtype=torch.float64, device="cuda")
+        B.decompress(X[i], D)
+        expect.append((D, blaz.decompress(X[i])))
+    # dot products: 264x520 times (520x?) -> use x = X[3] (264x520) with y = compressed 520x64
+    ymat = blaz.compress(torch.from_numpy(smooth_field(520, 4, 2.0, 1e-3, 990, cols=64)).cuda())
+    xrow = torch.from_numpy(rng.integers(0, 264, 100)).cuda()
+    ycol = torch.from_numpy(rng.integers(0, 64, 100)).cuda()
+    out = torch.empty(100, dtype=torch.float64, device="cuda")
+    B.dot(X[3], xrow, ymat, ycol, out)
+    expect.append((out, blaz.dot(X[3], xrow, ymat, ycol)))
+    V = torch.from_numpy(uniform_matrix(50, 528, 991)).cuda()
+    rows = torch.from_numpy(rng.integers(0, 1032, 50)).cuda()
+    out2 = torch.empty(50, dtype=torch.float64, device="cuda")
+    B.dot_dense(X[4], rows, V, out2)
+    expect.append((out2, blaz.dot_dense(X[4], rows, V)))
+    return B, expect
+
+
+def assert_equal(a, b):
+    import torch
+    if isinstance(a, torch.Tensor):
+        assert torch.equal(a.view(torch.int64), b.view(torch.int64))
+    else:
+        for name in ("f", "s", "phi", "codes"):
+            ta, tb = getattr(a, name), getattr(b, name)
+            if ta.dtype == torch.float64:
+                ta, tb = ta.view(torch.int64), tb.view(torch.int64)
+            assert torch.equal(ta, tb), name
+
+
+def clear(a):
+    import torch
+    if isinstance(a, torch.Tensor):
+        a.zero_()
+    else:
+        for t in (a.f, a.s, a.phi, a.codes):
+            t.zero_()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("workgroups", [0, 1, 7, 100000])
+def test_batch_matches_standalone(workgroups):
+    import torch
+    import paper_2202_13007_amd as blaz
+    B, expect = make_workload(torch, blaz)
+    P = B.plan()
+    P.run(workgroups)
+    torch.cuda.synchronize()
+    for got, want in expect:
+        assert_equal(got, want)
+
+
+@pytest.mark.gpu
+def test_batch_graph_capture_replays():
+    """The run is two kernel launches (counter reset, persistent kernel), so a
+    captured graph replays it; every replay is checked after clearing the
+    outputs eagerly in between."""
+    import torch
+    import paper_2202_13007_amd as blaz
+    B, expect = make_workload(torch, blaz)
+    P = B.plan()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        P.run()  # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        P.run()
+    for rep in range(3):
+        for got, _ in expect:
+            clear(got)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for got, want in expect:
+            assert_equal(got, want)
+
+
+@pytest.mark.gpu
+def test_batch_rejects_invalid_item_without_launching():
+    import torch
+    import paper_2202_13007_amd as blaz
+    x = blaz.BlazMatrix.empty(16, 16)
+    B = blaz.Batch()
+    B.scale(x, 2.0, blaz.BlazMatrix.empty(16, 16))
+    A = torch.zeros((16, 24), dtype=torch.float64, device="cuda")
+    B.compress(A[:, 1:17], x)  # 8-byte aligned only
+    with pytest.raises(blaz.BlazError) as e:
+        B.plan()
+    assert "item 1" in str(e.value)
