@@ -170,6 +170,16 @@ blaz_status blaz_matmul(const blaz_matrix *a, const blaz_matrix *b, const double
                         int64_t ldb, double *c, int64_t ldc, blaz_precision prec, void *workspace,
                         size_t ws_bytes, hipStream_t stream);
 
+/* blaz_matmul with an explicit output tile for the contraction: 128 (a
+ * 128 x 128 tile per workgroup) or 64; 0 lets the library choose, as
+ * blaz_matmul does (128 when that still gives every compute unit a
+ * workgroup, 64 below).  Results are the same for every tile: the K loop and
+ * its summation order do not depend on it.  Any other value is BLAZ_ERR_ARG.
+ * This is the knob the autotuner of the Python package sets per size class. */
+blaz_status blaz_matmul_tiled(const blaz_matrix *a, const blaz_matrix *b, const double *bdense, int64_t n,
+                              int64_t ldb, double *c, int64_t ldc, blaz_precision prec, void *workspace,
+                              size_t ws_bytes, int32_t tile, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Batching: many operations, on matrices of any sizes, in one persistent
  * launch.  Every 8x8 block is independent (the paper's blockwise

@@ -164,8 +164,10 @@ def matmul_workspace_bytes(m: int, n: int, k: int, b_compressed: bool, prec: str
 
 
 def matmul(a: BlazMatrix, b: BlazMatrix | torch.Tensor, out: torch.Tensor | None = None, prec: str = "fp64",
-           workspace: torch.Tensor | None = None) -> torch.Tensor:
-    """C = A B with A compressed and B compressed or dense float64; C dense float64."""
+           workspace: torch.Tensor | None = None, tile: int = 0) -> torch.Tensor:
+    """C = A B with A compressed and B compressed or dense float64; C dense float64.
+
+    tile: output tile of the contraction (64 or 128); 0 = the library's choice."""
     compressed_b = isinstance(b, BlazMatrix)
     n = b.cols if compressed_b else b.shape[1]
     if not compressed_b:
@@ -177,10 +179,10 @@ def matmul(a: BlazMatrix, b: BlazMatrix | torch.Tensor, out: torch.Tensor | None
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=a.f.device)
     ma = a.c()
     mb = b.c() if compressed_b else None
-    check(_lib.lib().blaz_matmul(ctypes.byref(ma), ctypes.byref(mb) if compressed_b else None,
-                                 None if compressed_b else _ptr(b), n, 0 if compressed_b else b.stride(0),
-                                 _ptr(out), out.stride(0), _lib.PREC[prec], _ptr(workspace),
-                                 workspace.numel(), _stream()), "blaz_matmul")
+    check(_lib.lib().blaz_matmul_tiled(ctypes.byref(ma), ctypes.byref(mb) if compressed_b else None,
+                                       None if compressed_b else _ptr(b), n, 0 if compressed_b else b.stride(0),
+                                       _ptr(out), out.stride(0), _lib.PREC[prec], _ptr(workspace),
+                                       workspace.numel(), int(tile), _stream()), "blaz_matmul")
     return out
 
 

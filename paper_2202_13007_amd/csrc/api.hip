@@ -2,6 +2,7 @@
 // kernel launches.  Nothing here allocates, synchronizes or keeps state.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 
 #include "blaz_internal.hpp"
@@ -130,10 +131,41 @@ BLAZ_API size_t blaz_matmul_workspace_bytes(int64_t m, int64_t n, int64_t k, int
     return matmul_workspace(m, n, k, b_compressed != 0, prec).total();
 }
 
-BLAZ_API blaz_status blaz_matmul(const blaz_matrix* a, const blaz_matrix* b, const double* bdense, int64_t n,
-                                 int64_t ldb, double* c, int64_t ldc, blaz_precision prec, void* workspace,
-                                 size_t ws_bytes, hipStream_t stream)
+namespace blaz {
+namespace detail {
+
+int device_cu_count()
 {
+    // looked up once per device: not a stream operation, so later calls may
+    // be made while a stream is being captured into a graph
+    static std::atomic<int> cu_count[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    int cus = dev < 64 ? cu_count[dev].load() : 0;
+    if (cus == 0) {
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        if (dev < 64) cu_count[dev].store(cus);
+    }
+    return cus;
+}
+
+}  // namespace detail
+}  // namespace blaz
+
+// The library's tile choice: the 128 tile once it gives every compute unit a
+// workgroup, the 64 tile (four times as many workgroups) below that.
+static int default_gemm_tile(int64_t m, int64_t n)
+{
+    const int64_t tiles128 = ((m + 127) / 128) * ((n + 127) / 128);
+    const int cus = blaz::detail::device_cu_count();
+    return tiles128 >= (cus > 0 ? cus : 256) ? 128 : 64;
+}
+
+static blaz_status matmul_impl(const blaz_matrix* a, const blaz_matrix* b, const double* bdense, int64_t n,
+                               int64_t ldb, double* c, int64_t ldc, blaz_precision prec, void* workspace,
+                               size_t ws_bytes, int32_t tile, hipStream_t stream)
+{
+    if (tile != 0 && tile != 64 && tile != 128) return BLAZ_ERR_ARG;
     if (blaz_status st = check_matrix(a)) return st;
     if (b && bdense) return BLAZ_ERR_ARG;  // exactly one form of B
     if (!b && !bdense && a->cols > 0) return BLAZ_ERR_NULL;
@@ -163,7 +195,8 @@ BLAZ_API blaz_status blaz_matmul(const blaz_matrix* a, const blaz_matrix* b, con
         return BLAZ_ERR_ARG;
     // k == 0: the product is the zero matrix; the contraction kernel with an
     // empty K loop writes exactly that and reads nothing.
-    if (k == 0) return hip_status(blaz::detail::launch_gemm_f64(nullptr, 0, nullptr, 0, c, ldc, m, n, 0, stream));
+    if (tile == 0) tile = default_gemm_tile(m, n);
+    if (k == 0) return hip_status(blaz::detail::launch_gemm_f64(nullptr, 0, nullptr, 0, c, ldc, m, n, 0, tile, stream));
 
     char* ws = static_cast<char*>(workspace);
     char* wa = ws;
@@ -182,7 +215,7 @@ BLAZ_API blaz_status blaz_matmul(const blaz_matrix* a, const blaz_matrix* b, con
             bop = B64;
             ldbop = n;
         }
-        return hip_status(launch_gemm_f64(A64, k, bop, ldbop, c, ldc, m, n, k, stream));
+        return hip_status(launch_gemm_f64(A64, k, bop, ldbop, c, ldc, m, n, k, tile, stream));
     }
 
     // Low-precision contractions: B (dense, or a compressed B rebuilt in
@@ -199,7 +232,7 @@ BLAZ_API blaz_status blaz_matmul(const blaz_matrix* a, const blaz_matrix* b, con
         float* B32 = reinterpret_cast<float*>(wb);
         if (hipError_t e = launch_decompress_f32(*a, A32, k, stream)) return hip_status(e);
         if (hipError_t e = launch_convert_f32(bsrc, ldbsrc, B32, k, n, stream)) return hip_status(e);
-        return hip_status(launch_gemm_f32(A32, k, B32, n, c, ldc, m, n, k, stream));
+        return hip_status(launch_gemm_f32(A32, k, B32, n, c, ldc, m, n, k, tile, stream));
     }
     __bf16* Ahi = reinterpret_cast<__bf16*>(wa);
     __bf16* Alo = reinterpret_cast<__bf16*>(wa + wl.a_bytes / 2);
@@ -207,7 +240,21 @@ BLAZ_API blaz_status blaz_matmul(const blaz_matrix* a, const blaz_matrix* b, con
     __bf16* Blo = reinterpret_cast<__bf16*>(wb + wl.b_bytes / 2);
     if (hipError_t e = launch_decompress_bf16_split(*a, Ahi, Alo, k, stream)) return hip_status(e);
     if (hipError_t e = launch_convert_bf16_split_t(bsrc, ldbsrc, Bhi, Blo, k, n, stream)) return hip_status(e);
-    return hip_status(launch_gemm_bf16x3(Ahi, Alo, k, Bhi, Blo, k, c, ldc, m, n, k, stream));
+    return hip_status(launch_gemm_bf16x3(Ahi, Alo, k, Bhi, Blo, k, c, ldc, m, n, k, tile, stream));
+}
+
+BLAZ_API blaz_status blaz_matmul(const blaz_matrix* a, const blaz_matrix* b, const double* bdense, int64_t n,
+                                 int64_t ldb, double* c, int64_t ldc, blaz_precision prec, void* workspace,
+                                 size_t ws_bytes, hipStream_t stream)
+{
+    return matmul_impl(a, b, bdense, n, ldb, c, ldc, prec, workspace, ws_bytes, 0, stream);
+}
+
+BLAZ_API blaz_status blaz_matmul_tiled(const blaz_matrix* a, const blaz_matrix* b, const double* bdense, int64_t n,
+                                       int64_t ldb, double* c, int64_t ldc, blaz_precision prec, void* workspace,
+                                       size_t ws_bytes, int32_t tile, hipStream_t stream)
+{
+    return matmul_impl(a, b, bdense, n, ldb, c, ldc, prec, workspace, ws_bytes, tile, stream);
 }
 
 BLAZ_API const char* blaz_status_string(blaz_status status)

@@ -13,7 +13,6 @@
 // the grid always drains.
 #include <hip/hip_runtime.h>
 
-#include <atomic>
 #include <cstring>
 
 #include "blaz_codec.hpp"
@@ -243,17 +242,8 @@ BLAZ_API blaz_status blaz_batch_run(const void* plan_dev, int64_t n_plan, int64_
     if (!plan_dev || !counter) return BLAZ_ERR_NULL;
     if (!aligned(plan_dev, 8) || !aligned(counter, 8)) return BLAZ_ERR_ALIGN;
     if (workgroups == 0) {
-        // compute units per device, looked up once per device (not a stream
-        // operation, so a later run may be captured in a graph)
-        static std::atomic<int> cu_count[64];
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess) return BLAZ_ERR_HIP;
-        int cus = dev < 64 ? cu_count[dev].load() : 0;
-        if (cus == 0) {
-            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-                return BLAZ_ERR_HIP;
-            if (dev < 64) cu_count[dev].store(cus);
-        }
+        const int cus = blaz::detail::device_cu_count();
+        if (cus == 0) return BLAZ_ERR_HIP;
         workgroups = 8 * (int64_t)cus;
     }
     if (workgroups > total_chunks) workgroups = total_chunks;

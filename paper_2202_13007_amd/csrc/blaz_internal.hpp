@@ -10,6 +10,9 @@
 namespace blaz {
 namespace detail {
 
+// Compute units of the current device (cached per device; 0 on error).
+int device_cu_count();
+
 hipError_t launch_compress_f64(const double* A, int64_t lda, const blaz_matrix& m, uint8_t* psi, hipStream_t st);
 // Compression with the transform stage in FP32 or BF16x3 on MFMA.
 hipError_t launch_compress_mixed(const double* A, int64_t lda, const blaz_matrix& m, uint8_t* psi,
@@ -26,16 +29,17 @@ hipError_t launch_dot(const blaz_matrix& x, const int64_t* xrow, const blaz_matr
 hipError_t launch_dot_dense(const blaz_matrix& x, const int64_t* xrow, const double* v, int64_t ldv,
                             int64_t count, double* out, hipStream_t st);
 // C (m x n, ldc) = A (m x k, lda) * B (k x n, ldb), all row-major binary64.
+// tile: 64 or 128 (the output tile of one workgroup).
 hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
-                           int64_t m, int64_t n, int64_t k, hipStream_t st);
+                           int64_t m, int64_t n, int64_t k, int tile, hipStream_t st);
 // The same product with FP32 operands on FP32 MFMA (FP32 accumulation).
 hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* B, int64_t ldb, double* C, int64_t ldc,
-                           int64_t m, int64_t n, int64_t k, hipStream_t st);
+                           int64_t m, int64_t n, int64_t k, int tile, hipStream_t st);
 // The same product with A = Ahi + Alo (m x k) and B^T = Bthi + Btlo (n x k)
 // in BF16: C = Ahi B_hi + Ahi B_lo + Alo B_hi on BF16 MFMA, FP32 accumulation.
 hipError_t launch_gemm_bf16x3(const __bf16* Ahi, const __bf16* Alo, int64_t lda, const __bf16* Bthi,
                               const __bf16* Btlo, int64_t ldbt, double* C, int64_t ldc, int64_t m, int64_t n,
-                              int64_t k, hipStream_t st);
+                              int64_t k, int tile, hipStream_t st);
 // Dense binary64 B (k x n, ldb) to FP32 row-major (k x n, ld n).
 hipError_t launch_convert_f32(const double* B, int64_t ldb, float* out, int64_t k, int64_t n, hipStream_t st);
 // Dense binary64 B (k x n, ldb) to B^T split into BF16 hi + lo (n x k, ld k).

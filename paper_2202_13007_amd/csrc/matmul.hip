@@ -10,8 +10,9 @@
 //           C = Alo Bhi + Ahi Blo + Ahi Bhi (the Alo Blo term, ~2^-16
 //           relative, is dropped), FP32 accumulation
 //
-// Tiling: a 256-thread workgroup computes a 128x128 tile of C; its four
-// waves each own a 64x64 quadrant as 4x4 MFMA tiles of 16x16.  K advances
+// Tiling: a 256-thread workgroup computes a BMxBM tile of C (BM = 128 or 64);
+// its four waves each own a quadrant as (BM/32)x(BM/32) MFMA tiles of 16x16.
+// The 64 tile gives small products four times as many workgroups.  K advances
 // through LDS in steps of BK; the next step's global loads are issued into
 // registers before the current step's MFMAs, so HBM/L2 latency overlaps the
 // matrix math.  Workgroup ids are remapped so that each XCD (the hardware
@@ -29,7 +30,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kBM = 128, kBN = 128;
 constexpr int kPad = 16;  // elements of padding per LDS row (see the bank notes at each use)
 
 // Tile (tm, tn) for workgroup `wg` of `nwg`: contiguous ranges per XCD, then
@@ -70,10 +70,10 @@ struct Mfma16x16x4<float> {
 };
 
 // C = A B with A (M x K, lda) and B (K x N, ldb) row-major in T; C binary64.
-// LDS rows hold kBM + kPad elements: 144 doubles (1152 B) or 144 floats
-// (576 B), which puts the four k rows read by one MFMA operand fetch on
-// different banks.
-template <typename T>
+// LDS rows hold kBM + kPad elements (144 or 80 doubles, 144 or 80 floats),
+// which puts the four k rows read by one MFMA operand fetch on different
+// banks.
+template <typename T, int kBM>
 __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
                                                    int64_t ldb, double* __restrict__ C, int64_t ldc, int64_t M,
                                                    int64_t N, int64_t K)
@@ -81,11 +81,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
     using MF = Mfma16x16x4<T>;
     using acc_t = typename MF::acc_t;
     using vec_t = typename MF::vec_t;
+    constexpr int kBN = kBM;
+    constexpr int TW = kBM / 32;          // MFMA tiles per wave and dimension
     constexpr int BK = MF::kBK;
     constexpr int V = 16 / sizeof(T);     // elements per 16-byte vector
     constexpr int AV = BK / V;            // vectors per A tile row
     constexpr int BV = kBN / V;           // vectors per B tile row
-    static_assert(kBM * AV == 1024 && BK * BV == 1024, "4 vectors of A and of B per thread");
+    constexpr int RV = kBM * AV / 256;    // vectors of A (and of B) per thread
+    static_assert(kBM * AV == BK * BV && RV * 256 == kBM * AV, "whole vectors per thread");
 
     __shared__ T As[BK][kBM + kPad];  // A tile stored k-major (transposed)
     __shared__ T Bs[BK][kBN + kPad];
@@ -100,10 +103,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
-    vec_t ra[4], rb[4];
+    vec_t ra[RV], rb[RV];
     auto load_stage = [&](int64_t k0) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < RV; ++r) {
             const int q = tid + 256 * r;
             const int am = q / AV, ak = (q % AV) * V;
             const int64_t gr = row0 + am, gk = k0 + ak;
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
     };
     auto store_stage = [&]() {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < RV; ++r) {
             const int q = tid + 256 * r;
             const int am = q / AV, ak = (q % AV) * V;
 #pragma unroll
@@ -125,11 +128,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
         }
     };
 
-    acc_t acc[4][4];
+    acc_t acc[TW][TW];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TW; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{};
+        for (int j = 0; j < TW; ++j) acc[i][j] = acc_t{};
 
     const int nk = (int)((K + BK - 1) / BK);
     load_stage(0);
@@ -142,26 +145,26 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
         for (int kk = 0; kk < BK; kk += 4) {
             // A operand: lane holds A[m = lane%16][k = lane/16]; B operand:
             // lane holds B[k = lane/16][n = lane%16].
-            T a[4], b[4];
+            T a[TW], b[TW];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk + (lane >> 4)][wm * 64 + i * 16 + (lane & 15)];
+            for (int i = 0; i < TW; ++i) a[i] = As[kk + (lane >> 4)][wm * (kBM / 2) + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk + (lane >> 4)][wn * 64 + j * 16 + (lane & 15)];
+            for (int j = 0; j < TW; ++j) b[j] = Bs[kk + (lane >> 4)][wn * (kBN / 2) + j * 16 + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TW; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = MF::op(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < TW; ++j) acc[i][j] = MF::op(a[i], b[j], acc[i][j]);
         }
     }
 
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TW; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t gc = col0 + wn * 64 + j * 16 + (lane & 15);
+        for (int j = 0; j < TW; ++j) {
+            const int64_t gc = col0 + wn * (kBN / 2) + j * 16 + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t gr = row0 + wm * 64 + i * 16 + MF::row(lane >> 4, r);
+                const int64_t gr = row0 + wm * (kBM / 2) + i * 16 + MF::row(lane >> 4, r);
                 if (gr < M && gc < N) C[gr * ldc + gc] = (double)acc[i][j][r];
             }
         }
@@ -174,12 +177,16 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
 constexpr int kBKb = 32;
 constexpr int kRowB = kBKb + 8;
 
+template <int kBM>
 __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restrict__ Ahi, const __bf16* __restrict__ Alo,
                                                           int64_t lda, const __bf16* __restrict__ Bhi,
                                                           const __bf16* __restrict__ Blo, int64_t ldbt,
                                                           double* __restrict__ C, int64_t ldc, int64_t M, int64_t N,
                                                           int64_t K)
 {
+    constexpr int kBN = kBM;
+    constexpr int TW = kBM / 32;
+    constexpr int RC = kBM / 64;  // 16-byte chunks of each operand tile per thread
     __shared__ __align__(16) __bf16 Ash[kBM * kRowB];
     __shared__ __align__(16) __bf16 Asl[kBM * kRowB];
     __shared__ __align__(16) __bf16 Bsh[kBN * kRowB];
@@ -195,11 +202,11 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
-    // Each of the four 128 x 32 tiles is 512 16-byte chunks: 2 per thread.
-    uint4 rah[2], ral[2], rbh[2], rbl[2];
+    // Each of the four BM x 32 tiles is 4 BM 16-byte chunks: BM/64 per thread.
+    uint4 rah[RC], ral[RC], rbh[RC], rbl[RC];
     auto load_stage = [&](int64_t k0) {
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < RC; ++r) {
             const int q = tid + 256 * r;
             const int row = q >> 2, kc = (q & 3) * 8;
             const int64_t gk = k0 + kc;
@@ -213,7 +220,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
     };
     auto store_stage = [&]() {
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < RC; ++r) {
             const int q = tid + 256 * r;
             const int off = (q >> 2) * kRowB + (q & 3) * 8;
             *reinterpret_cast<uint4*>(&Ash[off]) = rah[r];
@@ -223,11 +230,11 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
         }
     };
 
-    f32x4 acc[4][4];
+    f32x4 acc[TW][TW];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TW; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     const int nk = (int)((K + kBKb - 1) / kBKb);
     load_stage(0);
@@ -241,23 +248,23 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
         // assignment of k to (lane group, element) works as long as A and B
         // use the same one.
         const int koff = 8 * (lane >> 4);
-        bf16x8 ah[4], al[4], bh[4], bl[4];
+        bf16x8 ah[TW], al[TW], bh[TW], bl[TW];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int off = (wm * 64 + i * 16 + (lane & 15)) * kRowB + koff;
+        for (int i = 0; i < TW; ++i) {
+            const int off = (wm * (kBM / 2) + i * 16 + (lane & 15)) * kRowB + koff;
             ah[i] = *reinterpret_cast<const bf16x8*>(&Ash[off]);
             al[i] = *reinterpret_cast<const bf16x8*>(&Asl[off]);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int off = (wn * 64 + j * 16 + (lane & 15)) * kRowB + koff;
+        for (int j = 0; j < TW; ++j) {
+            const int off = (wn * (kBN / 2) + j * 16 + (lane & 15)) * kRowB + koff;
             bh[j] = *reinterpret_cast<const bf16x8*>(&Bsh[off]);
             bl[j] = *reinterpret_cast<const bf16x8*>(&Bsl[off]);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < TW; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < TW; ++j) {
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
@@ -266,13 +273,13 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
 
     // Value r of lane l holds row 4*(l/16) + r, column l%16 (BF16 16x16 form).
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TW; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t gc = col0 + wn * 64 + j * 16 + (lane & 15);
+        for (int j = 0; j < TW; ++j) {
+            const int64_t gc = col0 + wn * (kBN / 2) + j * 16 + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t gr = row0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+                const int64_t gr = row0 + wm * (kBM / 2) + i * 16 + 4 * (lane >> 4) + r;
                 if (gr < M && gc < N) C[gr * ldc + gc] = (double)acc[i][j][r];
             }
         }
@@ -323,27 +330,39 @@ __global__ __launch_bounds__(256) void convert_bf16_split_t_kernel(const double*
 
 namespace detail {
 
-static unsigned gemm_grid(int64_t m, int64_t n) { return (unsigned)(((m + kBM - 1) / kBM) * ((n + kBN - 1) / kBN)); }
+static unsigned gemm_grid(int64_t m, int64_t n, int tile)
+{
+    return (unsigned)(((m + tile - 1) / tile) * ((n + tile - 1) / tile));
+}
 
 hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
-                           int64_t m, int64_t n, int64_t k, hipStream_t st)
+                           int64_t m, int64_t n, int64_t k, int tile, hipStream_t st)
 {
-    gemm_kernel<double><<<gemm_grid(m, n), 256, 0, st>>>(A, lda, B, ldb, C, ldc, m, n, k);
+    if (tile == 64)
+        gemm_kernel<double, 64><<<gemm_grid(m, n, 64), 256, 0, st>>>(A, lda, B, ldb, C, ldc, m, n, k);
+    else
+        gemm_kernel<double, 128><<<gemm_grid(m, n, 128), 256, 0, st>>>(A, lda, B, ldb, C, ldc, m, n, k);
     return hipGetLastError();
 }
 
 hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* B, int64_t ldb, double* C, int64_t ldc,
-                           int64_t m, int64_t n, int64_t k, hipStream_t st)
+                           int64_t m, int64_t n, int64_t k, int tile, hipStream_t st)
 {
-    gemm_kernel<float><<<gemm_grid(m, n), 256, 0, st>>>(A, lda, B, ldb, C, ldc, m, n, k);
+    if (tile == 64)
+        gemm_kernel<float, 64><<<gemm_grid(m, n, 64), 256, 0, st>>>(A, lda, B, ldb, C, ldc, m, n, k);
+    else
+        gemm_kernel<float, 128><<<gemm_grid(m, n, 128), 256, 0, st>>>(A, lda, B, ldb, C, ldc, m, n, k);
     return hipGetLastError();
 }
 
 hipError_t launch_gemm_bf16x3(const __bf16* Ahi, const __bf16* Alo, int64_t lda, const __bf16* Bthi,
                               const __bf16* Btlo, int64_t ldbt, double* C, int64_t ldc, int64_t m, int64_t n,
-                              int64_t k, hipStream_t st)
+                              int64_t k, int tile, hipStream_t st)
 {
-    gemm_bf16x3_kernel<<<gemm_grid(m, n), 256, 0, st>>>(Ahi, Alo, lda, Bthi, Btlo, ldbt, C, ldc, m, n, k);
+    if (tile == 64)
+        gemm_bf16x3_kernel<64><<<gemm_grid(m, n, 64), 256, 0, st>>>(Ahi, Alo, lda, Bthi, Btlo, ldbt, C, ldc, m, n, k);
+    else
+        gemm_bf16x3_kernel<128><<<gemm_grid(m, n, 128), 256, 0, st>>>(Ahi, Alo, lda, Bthi, Btlo, ldbt, C, ldc, m, n, k);
     return hipGetLastError();
 }
 

@@ -1,0 +1,276 @@
+"""Continuous-batching serving loop over the libblaz entry points.
+
+Requests -- compress, add, scale, dot and matmul on square n x n matrices --
+arrive over time.  Their operands are compressed matrices resident on the
+device (and, for compress, dense matrices resident in HBM).  Two forms:
+
+* ``plain``: every request is launched on its own, with the standalone entry
+  points, on one stream, as soon as it has arrived and its memory fits.
+* ``batched``: continuous batching.  The server admits arrived requests while
+  their outputs (and workspaces) fit an HBM budget, and on every tick turns
+  the newly admitted block-level requests (compress, add, scale, dot) into
+  one batch -- one persistent launch over a flat chunk queue -- on one
+  stream, and launches the admitted matmuls on a second stream, so the two
+  kinds of work overlap on the device.  Ticks do not wait for each other: up
+  to ``max_inflight`` ticks run at once, and requests arriving meanwhile are
+  admitted into the next tick as memory frees up.  The matmul contraction
+  may run in FP64, FP32 or BF16x3 (``matmul_prec``).
+
+Completion times come from events recorded after each request's work and
+read against an event recorded when the run starts, so latency (completion
+minus arrival) is on the device's clock, not the polling loop's.  Every
+request's result is what the same standalone call computes alone: the
+batched code paths run the same device code (tests check this bit for bit).
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import api
+
+OPS = ("compress", "add", "scale", "dot", "matmul")
+SCALE_C = 1.7
+
+
+@dataclass
+class Request:
+    rid: int
+    op: str
+    n: int
+    arrival: float                  # seconds after the start of the run
+    done: float = math.nan          # seconds after the start (device clock)
+    nbytes: int = 0                 # device memory held while in flight
+    result: object = None
+    _hold: list = field(default_factory=list, repr=False)
+
+
+def make_requests(count: int, rate: float, seed: int = 501, n_min: int = 64, n_max: int = 8192,
+                  mix=(0.30, 0.25, 0.15, 0.15, 0.15)) -> list[Request]:
+    """Poisson arrivals (exponential gaps of mean 1/rate seconds), sides
+    log-uniform in [n_min, n_max] rounded to multiples of 8, operations drawn
+    with probabilities `mix` over (compress, add, scale, dot, matmul)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, count) if rate > 0 else np.zeros(count)
+    t = np.cumsum(gaps) - gaps[0]
+    n = 8 * np.maximum(1, np.round(np.exp(rng.uniform(np.log(n_min), np.log(n_max), count)) / 8)).astype(int)
+    n = np.clip(n, n_min, n_max)
+    ops = rng.choice(len(OPS), size=count, p=np.asarray(mix) / np.sum(mix))
+    return [Request(i, OPS[o], int(s), float(a)) for i, (o, s, a) in enumerate(zip(ops, n, t))]
+
+
+class OperandPool:
+    """Resident operands: for every side n, the n x n top-left corner of two
+    dense fields (views with the fields' leading dimension) and their
+    compressed forms, plus index vectors 0..n-1 for the dot requests."""
+
+    def __init__(self, A: torch.Tensor, B: torch.Tensor, sides):
+        self.A, self.B = A, B
+        self.x, self.y, self.idx = {}, {}, {}
+        for n in sorted(set(sides)):
+            self.x[n] = api.compress(A[:n, :n])
+            self.y[n] = api.compress(B[:n, :n])
+            self.idx[n] = torch.arange(n, dtype=torch.int64, device=A.device)
+        torch.cuda.synchronize()
+
+    def dense(self, n):
+        return self.A[:n, :n]
+
+
+def output_bytes(op: str, n: int, matmul_prec: str) -> int:
+    nb = (n // 8) ** 2
+    if op in ("compress", "add", "scale"):
+        return 45 * nb
+    if op == "dot":
+        return 8 * n
+    return 8 * n * n + api.matmul_workspace_bytes(n, n, n, True, matmul_prec)
+
+
+def fp64_equiv_bytes(op: str, n: int) -> int:
+    """Bytes the same request moves on dense binary64 matrices."""
+    return {"compress": 8, "add": 24, "scale": 16, "dot": 16, "matmul": 24}[op] * n * n
+
+
+class Server:
+    def __init__(self, pool: OperandPool, hbm_budget: int = 16 << 30, matmul_prec: str = "fp64",
+                 max_inflight: int = 4, tuner=None, keep_results: bool = False):
+        self.pool = pool
+        self.budget = int(hbm_budget)
+        self.matmul_prec = matmul_prec
+        self.max_inflight = max_inflight
+        self.tuner = tuner
+        self.keep = keep_results
+        self.s_block = torch.cuda.Stream()
+        self.s_mm = torch.cuda.Stream()
+
+    # -- per-request work ------------------------------------------------------
+    def _alloc(self, r: Request):
+        n = r.n
+        if r.op in ("compress", "add", "scale"):
+            r.result = api.BlazMatrix.empty(n, n)
+        elif r.op == "dot":
+            r.result = torch.empty(n, dtype=torch.float64, device="cuda")
+        else:
+            r.result = torch.empty((n, n), dtype=torch.float64, device="cuda")
+            ws = api.matmul_workspace_bytes(n, n, n, True, self.matmul_prec)
+            r._hold.append(torch.empty(max(ws, 1), dtype=torch.uint8, device="cuda"))
+
+    def _standalone(self, r: Request):
+        p, n = self.pool, r.n
+        if r.op == "compress":
+            api.compress(p.dense(n), out=r.result)
+        elif r.op == "add":
+            api.add(p.x[n], p.y[n], out=r.result)
+        elif r.op == "scale":
+            api.scale(p.x[n], SCALE_C, out=r.result)
+        elif r.op == "dot":
+            api.dot(p.x[n], p.idx[n], p.y[n], p.idx[n], out=r.result)
+        else:
+            tile = self.tuner.matmul_tile(n, n, n, self.matmul_prec, True) if self.tuner else 0
+            api.matmul(p.x[n], p.y[n], out=r.result, prec=self.matmul_prec, workspace=r._hold[0], tile=tile)
+
+    def _add_to_batch(self, batch: api.Batch, r: Request):
+        p, n = self.pool, r.n
+        if r.op == "compress":
+            batch.compress(p.dense(n), r.result)
+        elif r.op == "add":
+            batch.add(p.x[n], p.y[n], r.result)
+        elif r.op == "scale":
+            batch.scale(p.x[n], SCALE_C, r.result)
+        else:
+            batch.dot(p.x[n], p.idx[n], p.y[n], p.idx[n], r.result)
+
+    # -- the loop -----------------------------------------------------------------
+    def prepare(self, requests: list[Request]):
+        """Tune every size class the run will meet before it starts (tuning
+        times kernels and would otherwise stall the loop)."""
+        if not self.tuner:
+            return
+        for n in sorted({r.n for r in requests if r.op == "matmul"}):
+            self.tuner.matmul_tile(n, n, n, self.matmul_prec, True)
+        for c in range(0, 15):
+            self.tuner.batch_workgroups(1 << c)
+
+    def run(self, requests: list[Request], mode: str = "batched") -> dict:
+        assert mode in ("plain", "batched")
+        for r in requests:
+            r.nbytes = output_bytes(r.op, r.n, self.matmul_prec)
+            if r.nbytes > self.budget:
+                raise ValueError(f"request {r.rid} needs {r.nbytes} bytes, more than the whole budget")
+        limit = self.max_inflight if mode == "batched" else 1 << 30
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        ready: deque[Request] = deque()
+        units: list = []               # (event, [requests], held objects): one per launch unit
+        ticks_inflight: dict = {}      # tick id -> units still running
+        used = 0
+        self.peak_used = 0
+        ndone = 0
+        ticks = 0
+        # The device clock starts when start_ev executes; the host clock is read
+        # only after that, so device-clock completion times are never early
+        # with respect to host-clock arrivals (latency is over-estimated by the
+        # few microseconds the synchronization takes, never under-estimated).
+        start_ev = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start_ev.record(self.s_block)
+        self.s_mm.wait_stream(self.s_block)
+        start_ev.synchronize()
+        t0 = time.perf_counter()
+
+        def complete_ready():
+            nonlocal used, ndone, units
+            still, progressed = [], False
+            for ev, reqs, held, tick in units:
+                if not ev.query():
+                    still.append((ev, reqs, held, tick))
+                    continue
+                t_done = start_ev.elapsed_time(ev) / 1e3
+                for r in reqs:
+                    r.done = t_done
+                    used -= r.nbytes
+                    r._hold.clear()
+                    if not self.keep:
+                        r.result = None
+                ndone += len(reqs)
+                ticks_inflight[tick] -= 1
+                if ticks_inflight[tick] == 0:
+                    del ticks_inflight[tick]
+                progressed = True
+            units = still
+            return progressed
+
+        while ndone < len(requests):
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival <= now:
+                ready.append(pending.popleft())
+            progressed = complete_ready()
+            if ready and len(ticks_inflight) < limit and used + ready[0].nbytes <= self.budget:
+                admitted = []
+                while ready and used + ready[0].nbytes <= self.budget and (mode == "batched" or not admitted):
+                    r = ready.popleft()
+                    used += r.nbytes
+                    self._alloc(r)
+                    admitted.append(r)
+                self.peak_used = max(self.peak_used, used)
+                new_units = self._launch(admitted, mode)
+                ticks_inflight[ticks] = len(new_units)
+                units.extend((ev, reqs, held, ticks) for ev, reqs, held in new_units)
+                ticks += 1
+                continue
+            if not progressed:
+                # nothing to launch: wait briefly for an arrival or a completion
+                wait = pending[0].arrival - now if pending else 0.0
+                time.sleep(min(max(wait, 0.0), 2e-4) if (ready or units or wait > 0) else 0.0)
+        torch.cuda.synchronize()
+        return self._report(requests, mode, ticks)
+
+    def _launch(self, admitted, mode):
+        """Enqueue the admitted requests; returns their completion units."""
+        units = []
+        if mode == "plain":
+            with torch.cuda.stream(self.s_block):
+                for r in admitted:
+                    self._standalone(r)
+                    ev = torch.cuda.Event(enable_timing=True)
+                    ev.record(self.s_block)
+                    units.append((ev, [r], []))
+            return units
+        blocks = [r for r in admitted if r.op != "matmul"]
+        mms = [r for r in admitted if r.op == "matmul"]
+        if blocks:
+            batch = api.Batch()
+            for r in blocks:
+                self._add_to_batch(batch, r)
+            with torch.cuda.stream(self.s_block):
+                plan = batch.plan()
+                wg = self.tuner.batch_workgroups(plan.total_chunks) if self.tuner else 0
+                plan.run(wg)
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record(self.s_block)
+            units.append((ev, blocks, [plan]))
+        if mms:
+            with torch.cuda.stream(self.s_mm):
+                for r in mms:
+                    self._standalone(r)
+                    ev = torch.cuda.Event(enable_timing=True)
+                    ev.record(self.s_mm)
+                    units.append((ev, [r], []))
+        return units
+
+    def _report(self, requests, mode, ticks) -> dict:
+        lat = np.array([(r.done - r.arrival) * 1e3 for r in requests])
+        first = min(r.arrival for r in requests)
+        last = max(r.done for r in requests)
+        span = max(last - first, 1e-9)
+        eq = sum(fp64_equiv_bytes(r.op, r.n) for r in requests)
+        flop = sum(2 * r.n ** 3 for r in requests if r.op == "matmul")
+        return {"mode": mode, "requests": len(requests), "ticks": ticks,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_ms": float(lat.mean()), "makespan_s": span, "req_per_s": len(requests) / span,
+                "fp64_equiv_GBps": eq / span / 1e9, "matmul_TFLOPs": flop / span / 1e12,
+                "matmul_prec": self.matmul_prec}

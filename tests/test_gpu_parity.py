@@ -564,6 +564,20 @@ def test_matmul_low_precision_full_size_4096_sampled(prec):
         assert abs(Ch[i, j] - want) <= low_precision_tol(prec, 4096) * mag, (i, j, Ch[i, j], want)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("m,k,n", [(392, 136, 264), (64, 64, 64)])
+def test_matmul_tiles_give_identical_results(prec, m, k, n):
+    """The contraction tile (64 or 128) changes the grid, not the K order."""
+    A = smooth_field(m, 4, 2.0, 1e-3, 470 + m, cols=k)
+    B = uniform_matrix(k, n, 471)
+    x, dB = upload(oracle.compress(A)), dev(B)
+    c64 = blaz.matmul(x, dB, prec=prec, tile=64)
+    c128 = blaz.matmul(x, dB, prec=prec, tile=128)
+    assert torch.equal(c64.view(torch.int64), c128.view(torch.int64))
+    with pytest.raises(blaz.BlazError):
+        blaz.matmul(x, dB, prec=prec, tile=96)
+
+
 def test_empty_and_k0():
     z = blaz.BlazMatrix.empty(0, 16)
     blaz.compress(torch.empty((0, 16), dtype=torch.float64, device="cuda"), out=z)
