@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-matmul", action="store_true", help="skip the matmul leg")
     ap.add_argument("--cpu-rows", type=int, default=512, help="rows of each field the oracle times")
+    ap.add_argument("--serve-requests", type=int, default=20000, help="requests of the serving mix (0 skips it)")
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="HBM budget of the serving loop")
     return ap.parse_args()
 
 
@@ -131,6 +133,52 @@ def matmul_leg(blaz, torch, workload_inputs):
     legs["bf16x3"]["mfma_frac_note"] = "against 1/3 of the BF16 peak (three products)"
     return {"legs": legs, "method_rel_err": float(f"{method:.3e}"),
             "note": "TFLOPs count 2 n^3 useful flops; times include decompressing A and preparing B"}
+
+
+def serving_leg(torch, dA, dB, count, budget_gib):
+    """The serving mix: `count` requests (compress 30%, add 25%, scale 15%,
+    dot 15%, matmul 15%), sides log-uniform in [64, 8192], on the two 8192^2
+    fields (each side n uses their n x n corners).  The plain form's capacity
+    is measured with every request of a calibration set arriving at once;
+    the Poisson stream then arrives at 0.8x that rate and is served in the
+    plain form, batched with FP64 matmuls, and batched with BF16x3 matmuls."""
+    from paper_2202_13007_amd.serve import OperandPool, Server, make_requests
+    from paper_2202_13007_amd.tune import Autotuner
+
+    calib = make_requests(min(count, 2000), rate=0.0, seed=502)
+    warm = make_requests(200, rate=0.0, seed=503)
+    sides = [r.n for r in calib + warm + make_requests(count, rate=1.0, seed=501)]
+    pool = OperandPool(dA, dB, sides)
+    tuner = Autotuner(path=None)
+    budget = int(budget_gib * (1 << 30))
+    out = {"requests": count, "hbm_budget_GiB": budget_gib, "mix": "compress .30 add .25 scale .15 dot .15 matmul .15",
+           "sides": "log-uniform in [64, 8192], multiples of 8"}
+    servers = {"plain": Server(pool, budget, "fp64", tuner=tuner),
+               "batched_fp64": Server(pool, budget, "fp64", tuner=tuner),
+               "batched_bf16x3": Server(pool, budget, "bf16x3", tuner=tuner)}
+    for srv in servers.values():
+        srv.prepare(calib)
+    # warm-up and capacity (everything arrives at t = 0)
+    cap = {}
+    for name, srv in servers.items():
+        mode = "plain" if name == "plain" else "batched"
+        srv.run(make_requests(200, rate=0.0, seed=503), mode)  # warm-up (same sides as `warm`)
+        rep = srv.run(make_requests(len(calib), rate=0.0, seed=502), mode)
+        cap[name] = rep["req_per_s"]
+    out["capacity_req_per_s"] = {k: round(v, 1) for k, v in cap.items()}
+    out["capacity_speedup_vs_plain"] = {k: round(v / cap["plain"], 3) for k, v in cap.items()}
+    rate = 0.8 * cap["plain"]
+    out["arrival_rate_req_per_s"] = round(rate, 1)
+    runs = {}
+    for name, srv in servers.items():
+        reqs = make_requests(count, rate=rate, seed=501)
+        srv.prepare(reqs)
+        rep = srv.run(reqs, "plain" if name == "plain" else "batched")
+        runs[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()}
+        print(f"# serving {name}: p50 {rep['p50_ms']:.2f} ms p99 {rep['p99_ms']:.2f} ms "
+              f"{rep['req_per_s']:.0f} req/s", file=sys.stderr, flush=True)
+    out["runs"] = runs
+    return out
 
 
 def main():
@@ -260,7 +308,10 @@ def main():
         "ops": op_report,
         "plain_dense_fp64": plain,
     }
-    del dA, dB, D
+    del D
+    if args.serve_requests > 0:
+        result["serving"] = serving_leg(torch, dA, dB, args.serve_requests, args.serve_budget_gib)
+    del dA, dB
 
     if not args.no_matmul:
         result["matmul_4096"] = matmul_leg(blaz, torch, workload_inputs)

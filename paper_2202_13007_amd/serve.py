@@ -10,8 +10,8 @@ device (and, for compress, dense matrices resident in HBM).  Two forms:
   their outputs (and workspaces) fit an HBM budget, and on every tick turns
   the newly admitted block-level requests (compress, add, scale, dot) into
   one batch -- one persistent launch over a flat chunk queue -- on one
-  stream, and launches the admitted matmuls on a second stream, so the two
-  kinds of work overlap on the device.  Ticks do not wait for each other: up
+  stream, and launches the admitted matmuls round-robin on a few more
+  streams, so the batch and the contractions overlap on the device.  Ticks do not wait for each other: up
   to ``max_inflight`` ticks run at once, and requests arriving meanwhile are
   admitted into the next tick as memory frees up.  The matmul contraction
   may run in FP64, FP32 or BF16x3 (``matmul_prec``).
@@ -98,7 +98,7 @@ def fp64_equiv_bytes(op: str, n: int) -> int:
 
 class Server:
     def __init__(self, pool: OperandPool, hbm_budget: int = 16 << 30, matmul_prec: str = "fp64",
-                 max_inflight: int = 4, tuner=None, keep_results: bool = False):
+                 max_inflight: int = 4, tuner=None, keep_results: bool = False, matmul_streams: int = 4):
         self.pool = pool
         self.budget = int(hbm_budget)
         self.matmul_prec = matmul_prec
@@ -106,7 +106,10 @@ class Server:
         self.tuner = tuner
         self.keep = keep_results
         self.s_block = torch.cuda.Stream()
-        self.s_mm = torch.cuda.Stream()
+        # matmuls go round-robin over a few streams so that small contractions
+        # (a handful of workgroups each) run side by side
+        self.s_mm = [torch.cuda.Stream() for _ in range(max(1, matmul_streams))]
+        self._next_mm = 0
 
     # -- per-request work ------------------------------------------------------
     def _alloc(self, r: Request):
@@ -178,7 +181,8 @@ class Server:
         start_ev = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         start_ev.record(self.s_block)
-        self.s_mm.wait_stream(self.s_block)
+        for st in self.s_mm:
+            st.wait_stream(self.s_block)
         start_ev.synchronize()
         t0 = time.perf_counter()
 
@@ -253,13 +257,14 @@ class Server:
                 ev = torch.cuda.Event(enable_timing=True)
                 ev.record(self.s_block)
             units.append((ev, blocks, [plan]))
-        if mms:
-            with torch.cuda.stream(self.s_mm):
-                for r in mms:
-                    self._standalone(r)
-                    ev = torch.cuda.Event(enable_timing=True)
-                    ev.record(self.s_mm)
-                    units.append((ev, [r], []))
+        for r in mms:
+            st = self.s_mm[self._next_mm % len(self.s_mm)]
+            self._next_mm += 1
+            with torch.cuda.stream(st):
+                self._standalone(r)
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record(st)
+            units.append((ev, [r], []))
         return units
 
     def _report(self, requests, mode, ticks) -> dict:
