@@ -90,8 +90,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
     constexpr int RV = kBM * AV / 256;    // vectors of A (and of B) per thread
     static_assert(kBM * AV == BK * BV && RV * 256 == kBM * AV, "whole vectors per thread");
 
-    __shared__ T As[BK][kBM + kPad];  // A tile stored k-major (transposed)
-    __shared__ T Bs[BK][kBN + kPad];
+    __shared__ T As[2][BK][kBM + kPad];  // A tiles stored k-major (transposed), double-buffered
+    __shared__ T Bs[2][BK][kBN + kPad];
 
     const int ntm = (int)((M + kBM - 1) / kBM);
     const int ntn = (int)((N + kBN - 1) / kBN);
@@ -116,15 +116,15 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
             rb[r] = (hk < K && hn < N) ? *reinterpret_cast<const vec_t*>(B + hk * ldb + hn) : vec_t{};
         }
     };
-    auto store_stage = [&]() {
+    auto store_stage = [&](int buf) {
 #pragma unroll
         for (int r = 0; r < RV; ++r) {
             const int q = tid + 256 * r;
             const int am = q / AV, ak = (q % AV) * V;
 #pragma unroll
-            for (int e = 0; e < V; ++e) As[ak + e][am] = ra[r][e];
+            for (int e = 0; e < V; ++e) As[buf][ak + e][am] = ra[r][e];
             const int bk = q / BV, bn = (q % BV) * V;
-            *reinterpret_cast<vec_t*>(&Bs[bk][bn]) = rb[r];
+            *reinterpret_cast<vec_t*>(&Bs[buf][bk][bn]) = rb[r];
         }
     };
 
@@ -134,27 +134,35 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
 #pragma unroll
         for (int j = 0; j < TW; ++j) acc[i][j] = acc_t{};
 
+    // Pipeline: stage kt is read from LDS buffer kt%2 while stage kt+1 (loaded
+    // into registers one step earlier) is written to the other buffer and
+    // stage kt+2 is fetched from memory; one barrier per step.
     const int nk = (int)((K + BK - 1) / BK);
     load_stage(0);
+    store_stage(0);
+    if (nk > 1) load_stage(BK);
+    __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
-        __syncthreads();
-        store_stage();
-        __syncthreads();
-        if (kt + 1 < nk) load_stage((int64_t)(kt + 1) * BK);
+        const int cur = kt & 1;
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             // A operand: lane holds A[m = lane%16][k = lane/16]; B operand:
             // lane holds B[k = lane/16][n = lane%16].
             T a[TW], b[TW];
 #pragma unroll
-            for (int i = 0; i < TW; ++i) a[i] = As[kk + (lane >> 4)][wm * (kBM / 2) + i * 16 + (lane & 15)];
+            for (int i = 0; i < TW; ++i) a[i] = As[cur][kk + (lane >> 4)][wm * (kBM / 2) + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < TW; ++j) b[j] = Bs[kk + (lane >> 4)][wn * (kBN / 2) + j * 16 + (lane & 15)];
+            for (int j = 0; j < TW; ++j) b[j] = Bs[cur][kk + (lane >> 4)][wn * (kBN / 2) + j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < TW; ++i)
 #pragma unroll
                 for (int j = 0; j < TW; ++j) acc[i][j] = MF::op(a[i], b[j], acc[i][j]);
         }
+        if (kt + 1 < nk) {
+            store_stage(cur ^ 1);
+            if (kt + 2 < nk) load_stage((int64_t)(kt + 2) * BK);
+        }
+        __syncthreads();
     }
 
 #pragma unroll
@@ -187,10 +195,10 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
     constexpr int kBN = kBM;
     constexpr int TW = kBM / 32;
     constexpr int RC = kBM / 64;  // 16-byte chunks of each operand tile per thread
-    __shared__ __align__(16) __bf16 Ash[kBM * kRowB];
-    __shared__ __align__(16) __bf16 Asl[kBM * kRowB];
-    __shared__ __align__(16) __bf16 Bsh[kBN * kRowB];
-    __shared__ __align__(16) __bf16 Bsl[kBN * kRowB];
+    __shared__ __align__(16) __bf16 Ash[2][kBM * kRowB];  // double-buffered operand tiles
+    __shared__ __align__(16) __bf16 Asl[2][kBM * kRowB];
+    __shared__ __align__(16) __bf16 Bsh[2][kBN * kRowB];
+    __shared__ __align__(16) __bf16 Bsl[2][kBN * kRowB];
 
     const int ntm = (int)((M + kBM - 1) / kBM);
     const int ntn = (int)((N + kBN - 1) / kBN);
@@ -218,15 +226,15 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
             rbl[r] = okb ? *reinterpret_cast<const uint4*>(Blo + gb * ldbt + gk) : uint4{0, 0, 0, 0};
         }
     };
-    auto store_stage = [&]() {
+    auto store_stage = [&](int buf) {
 #pragma unroll
         for (int r = 0; r < RC; ++r) {
             const int q = tid + 256 * r;
             const int off = (q >> 2) * kRowB + (q & 3) * 8;
-            *reinterpret_cast<uint4*>(&Ash[off]) = rah[r];
-            *reinterpret_cast<uint4*>(&Asl[off]) = ral[r];
-            *reinterpret_cast<uint4*>(&Bsh[off]) = rbh[r];
-            *reinterpret_cast<uint4*>(&Bsl[off]) = rbl[r];
+            *reinterpret_cast<uint4*>(&Ash[buf][off]) = rah[r];
+            *reinterpret_cast<uint4*>(&Asl[buf][off]) = ral[r];
+            *reinterpret_cast<uint4*>(&Bsh[buf][off]) = rbh[r];
+            *reinterpret_cast<uint4*>(&Bsl[buf][off]) = rbl[r];
         }
     };
 
@@ -236,13 +244,15 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
 #pragma unroll
         for (int j = 0; j < TW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // Same pipeline as gemm_kernel: compute on one LDS buffer while the next
+    // stage is stored to the other and the one after is fetched.
     const int nk = (int)((K + kBKb - 1) / kBKb);
     load_stage(0);
+    store_stage(0);
+    if (nk > 1) load_stage(kBKb);
+    __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
-        __syncthreads();
-        store_stage();
-        __syncthreads();
-        if (kt + 1 < nk) load_stage((int64_t)(kt + 1) * kBKb);
+        const int cur = kt & 1;
         // Operands of a 16x16x32 MFMA: lane l holds the 8 k-values
         // 8*(l/16) .. 8*(l/16)+7 of row (A) or column (B) l%16; any fixed
         // assignment of k to (lane group, element) works as long as A and B
@@ -252,14 +262,14 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
 #pragma unroll
         for (int i = 0; i < TW; ++i) {
             const int off = (wm * (kBM / 2) + i * 16 + (lane & 15)) * kRowB + koff;
-            ah[i] = *reinterpret_cast<const bf16x8*>(&Ash[off]);
-            al[i] = *reinterpret_cast<const bf16x8*>(&Asl[off]);
+            ah[i] = *reinterpret_cast<const bf16x8*>(&Ash[cur][off]);
+            al[i] = *reinterpret_cast<const bf16x8*>(&Asl[cur][off]);
         }
 #pragma unroll
         for (int j = 0; j < TW; ++j) {
             const int off = (wn * (kBN / 2) + j * 16 + (lane & 15)) * kRowB + koff;
-            bh[j] = *reinterpret_cast<const bf16x8*>(&Bsh[off]);
-            bl[j] = *reinterpret_cast<const bf16x8*>(&Bsl[off]);
+            bh[j] = *reinterpret_cast<const bf16x8*>(&Bsh[cur][off]);
+            bl[j] = *reinterpret_cast<const bf16x8*>(&Bsl[cur][off]);
         }
 #pragma unroll
         for (int i = 0; i < TW; ++i)
@@ -269,6 +279,11 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
             }
+        if (kt + 1 < nk) {
+            store_stage(cur ^ 1);
+            if (kt + 2 < nk) load_stage((int64_t)(kt + 2) * kBKb);
+        }
+        __syncthreads();
     }
 
     // Value r of lane l holds row 4*(l/16) + r, column l%16 (BF16 16x16 form).
