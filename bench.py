@@ -11,10 +11,14 @@ operations move on dense binary64 matrices (compress and decompress 8 n^2
 each, add 3 * 8 n^2, scale 2 * 8 n^2; 64 n^2 per step).
 
 The JSON line also carries, per operation, the time and the actual and
-FP64-equivalent GB/s; the same operations on dense FP64 on this GPU ("plain");
-the roofline of the dominant kernel (compress) from HIP events on its stream;
-a matmul leg (compressed 4096^2 field times dense U[-1, 1]); and the CPU
-oracle timed on a bounded sample of the same workload.
+FP64-equivalent GB/s inside the step; the same operations on dense FP64 on
+this GPU ("plain"); the roofline of the dominant kernel (compress) from HIP
+events on its stream; each operation launched alone with a cold and a warm
+Infinity Cache; the 64x64 latencies, eager and graph-replayed; the 4096^2
+linear algebra (compressed field times dense U[-1, 1] in FP64, FP32 and
+BF16x3, and 4096 row dot products); the 16384^2 mixed-precision transform
+(codes against the FP64 path, errors against the field); the serving mix at
+three loads; and the CPU oracle timed on a bounded sample of the step.
 """
 from __future__ import annotations
 
@@ -42,9 +46,11 @@ def parse():
     ap.add_argument("--n", type=int, default=8192, help="matrix side (default: the 8192 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-matmul", action="store_true", help="skip the matmul leg")
-    ap.add_argument("--cpu-rows", type=int, default=512, help="rows of each field the oracle times")
+    ap.add_argument("--cpu-rows", type=int, default=768, help="rows of each field the oracle times")
     ap.add_argument("--serve-requests", type=int, default=20000, help="requests of the serving mix (0 skips it)")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="HBM budget of the serving loop")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 64x64 latency, cold-cache and 16384x16384 mixed-precision legs")
     return ap.parse_args()
 
 
@@ -52,19 +58,57 @@ def elapsed_ms(pairs):
     return [a.elapsed_time(b) for a, b in pairs]
 
 
-def traffic_for(kernel_src: str, kernel: str):
+def timed_each(torch, fn, reps, warm=3, flush=None):
+    """Sorted per-launch times in ms, from an event pair around each launch.
+    With `flush` (a 1 GiB tensor), the buffer is read before every launch,
+    outside the timed pair, so that operands come from HBM and not from the
+    256 MB Infinity Cache.  A read leaves only clean lines behind; a write
+    would leave dirty ones whose write-back lands inside the timed launch."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    pairs = []
+    for _ in range(reps):
+        if flush is not None:
+            flush.sum()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        pairs.append((a, b))
+    torch.cuda.synchronize()
+    return sorted(elapsed_ms(pairs))
+
+
+def median(xs):
+    return xs[len(xs) // 2]
+
+
+CODEC_SOURCES = ("paper_2202_13007_amd/csrc/codec.hip", "paper_2202_13007_amd/csrc/blaz_codec.hpp",
+                 "paper_2202_13007_amd/csrc/blaz_device.hpp")
+
+
+def sources_sha256(paths):
+    """SHA-256 over the named source files, concatenated in order."""
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_for(kernel: str, sources):
     """HBM bytes per launch measured with rocprofv3 counters, if the kernel's
-    source is unchanged since the measurement."""
+    sources are unchanged since the measurement."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh).get(kernel)
-    if not rec:
+    if not rec or rec.get("sources") != list(sources):
         return None
-    with open(os.path.join(ROOT, kernel_src), "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()
-    if rec.get("source_sha256") != sha:
+    if rec.get("sources_sha256") != sources_sha256(sources):
         return None
     return rec.get("bytes_per_launch")
 
@@ -97,7 +141,7 @@ def matmul_leg(blaz, torch, workload_inputs):
     BF16x3, against torch's FP64 product of the decompressed A ("plain").
     Errors: each precision against the FP64 path (relative Frobenius), and the
     method's own error, |A_hat B - A B| / |A B| with A the uncompressed field."""
-    Am, Bm, _ = workload_inputs("linalg-4096")
+    Am, Bm, Vm = workload_inputs("linalg-4096")
     n = Am.shape[0]
     dA = torch.from_numpy(Am).cuda()
     g = blaz.compress(dA)
@@ -131,17 +175,168 @@ def matmul_leg(blaz, torch, workload_inputs):
     method = torch.linalg.norm(ref - exact).item() / torch.linalg.norm(exact).item()
     legs["plain"]["what"] = "torch FP64 matmul of the decompressed A"
     legs["bf16x3"]["mfma_frac_note"] = "against 1/3 of the BF16 peak (three products)"
+    del outs, exact, ws
     return {"legs": legs, "method_rel_err": float(f"{method:.3e}"),
-            "note": "TFLOPs count 2 n^3 useful flops; times include decompressing A and preparing B"}
+            "note": "TFLOPs count 2 n^3 useful flops; times include decompressing A and preparing B",
+            "dots": dot_leg(blaz, torch, g, Ad, dB, torch.from_numpy(Vm).cuda())}
 
 
-def serving_leg(torch, dA, dB, count, budget_gib):
+def dot_leg(blaz, torch, g, Ad, dB, dV, reps=20):
+    """4096 dot products of compressed rows: row i of A with its own dense
+    vector V[i] (algorithmic bytes: compressed A once + V + indices + out),
+    with one shared vector (GEMV), and with column i of a compressed B
+    (2 (n/8) records per dot).  'plain' is torch on the decompressed A."""
+    n = Ad.shape[0]
+    nblk = g.nblk
+    rows = torch.arange(n, dtype=torch.int64, device="cuda")
+    gb = blaz.compress(dB)
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    tmp = torch.empty(n, dtype=torch.float64, device="cuda")
+    v0 = dV[0].contiguous()
+    cases = {
+        "own_vectors": (lambda: blaz.dot_dense(g, rows, dV, out=out), RECORD * nblk + 8 * n * n + 16 * n,
+                        lambda: torch.sum(Ad * dV, dim=1)),
+        "shared_vector": (lambda: blaz.dot_dense(g, rows, v0, out=out), RECORD * nblk + 24 * n,
+                          lambda: torch.mv(Ad, v0)),
+        "compressed_pairs": (lambda: blaz.dot(g, rows, gb, rows, out=out), 2 * (n // 8) * RECORD * n + 24 * n,
+                             lambda: torch.sum(Ad * blaz.decompress(gb).t(), dim=1)),
+    }
+    res = {"count": n, "length": n}
+    for k, (fn, nbytes, want) in cases.items():
+        ms = median(timed_each(torch, fn, reps))
+        fn()
+        w = want()
+        scale = torch.max(torch.abs(w)).item()
+        r = {"ms": round(ms, 5), "GBps": round(nbytes / ms / 1e6, 1),
+             "max_abs_diff_vs_plain_rel": float(f"{torch.max(torch.abs(out - w)).item() / scale:.3e}")}
+        if k != "compressed_pairs":
+            pms = median(timed_each(torch, lambda: tmp.copy_(want()), reps))
+            r["plain_ms"] = round(pms, 5)
+        res[k] = r
+    res["note"] = ("GBps = algorithmic bytes / time; compressed_pairs counts 2 (n/8) records per dot, "
+                   "most of them served from cache")
+    return res
+
+
+def latency_leg(blaz, torch, workload_inputs, reps=50):
+    """The 64x64 workload: per-operation latency (median of single launches)
+    and the whole sequence -- compress both, add, scale by 1.7, decompress,
+    dot of row 0 of A with column 0 of B, compressed x compressed matmul --
+    launched eagerly and replayed from a captured graph."""
+    A, B = workload_inputs("plain-64")
+    n = A.shape[0]
+    dA = torch.from_numpy(A).cuda()
+    dB = torch.from_numpy(B).cuda()
+    x, y, z, w = (blaz.BlazMatrix.empty(n, n) for _ in range(4))
+    D = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    C = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    idx = torch.zeros(1, dtype=torch.int64, device="cuda")
+    o = torch.empty(1, dtype=torch.float64, device="cuda")
+    ws = torch.empty(max(1, blaz.matmul_workspace_bytes(n, n, n, True, "fp64")), dtype=torch.uint8, device="cuda")
+    ops = {"compress": lambda: blaz.compress(dA, out=x),
+           "compress_y": lambda: blaz.compress(dB, out=y),
+           "add": lambda: blaz.add(x, y, out=z),
+           "scale": lambda: blaz.scale(z, 1.7, out=w),
+           "decompress": lambda: blaz.decompress(w, out=D),
+           "dot": lambda: blaz.dot(x, idx, y, idx, out=o),
+           "matmul": lambda: blaz.matmul(x, y, out=C, workspace=ws)}
+
+    def seq():
+        for fn in ops.values():
+            fn()
+
+    out = {k: round(1e3 * median(timed_each(torch, fn, reps)), 2) for k, fn in ops.items() if k != "compress_y"}
+    res = {"unit": "us", "per_op_median": out}
+    res["sequence_eager_us"] = round(1e3 * median(timed_each(torch, seq, reps)), 2)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        seq()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        seq()
+    res["sequence_graph_us"] = round(1e3 * median(timed_each(torch, g.replay, reps)), 2)
+    res["note"] = "device time between events; the graph replays the same seven launches"
+    return res
+
+
+def cold_ops_leg(blaz, torch, dA, dB, reps=20):
+    """Each operation of the step on its own, median of single launches, with
+    the operands evicted from the Infinity Cache before every launch (cold)
+    and without (warm); scale also in place (16 B read + 16 B written per
+    block)."""
+    n = dA.shape[0]
+    x = blaz.compress(dA)
+    y = blaz.compress(dB)
+    z, w = blaz.BlazMatrix.empty(n, n), blaz.BlazMatrix.empty(n, n)
+    blaz.add(x, y, out=z)
+    D = torch.empty_like(dA)
+    nblk = x.nblk
+    flush = torch.zeros(1 << 27, dtype=torch.float64, device="cuda")
+    cases = {"compress": (lambda: blaz.compress(dA, out=w), (BLOCK + RECORD) * nblk),
+             "decompress": (lambda: blaz.decompress(x, out=D), (BLOCK + RECORD) * nblk),
+             "add": (lambda: blaz.add(x, y, out=w), 3 * RECORD * nblk),
+             "scale": (lambda: blaz.scale(x, 1.7, out=w), 2 * RECORD * nblk),
+             "scale_in_place": (lambda: blaz.scale(z, 1.0000001, out=z), 32 * nblk)}
+    res = {}
+    for k, (fn, nbytes) in cases.items():
+        cold = median(timed_each(torch, fn, reps, flush=flush))
+        warm = median(timed_each(torch, fn, reps))
+        res[k] = {"cold_ms": round(cold, 5), "cold_GBps": round(nbytes / cold / 1e6, 1),
+                  "cold_hbm_frac": round(nbytes / cold / 1e6 / HBM_PEAK_GBS, 4),
+                  "warm_ms": round(warm, 5), "warm_GBps": round(nbytes / warm / 1e6, 1)}
+    del flush
+    return res
+
+
+def mixed_leg(blaz, torch, workload_inputs, reps=10):
+    """The 16384x16384 field compressed with the transform in FP64, FP32 and
+    BF16x3.  Codes and phi are compared with the FP64 path's; errors of the
+    decompressed matrices are relative Frobenius norms against the field
+    itself (the method's own error for FP64) and against the FP64 path."""
+    (M,) = workload_inputs("mixed-16384")
+    n = M.shape[0]
+    dM = torch.from_numpy(M).cuda()
+    del M
+    precs = ("fp64", "fp32", "bf16x3")
+    outs = {p: blaz.BlazMatrix.empty(n, n) for p in precs}
+    nblk = outs["fp64"].nblk
+    res = {"n": n, "blocks": nblk, "codes": 28 * nblk}
+    norm = torch.linalg.norm(dM).item()
+    ref = outs["fp64"]
+    D64 = None
+    for p in precs:
+        ms = median(timed_each(torch, lambda p=p: blaz.compress(dM, out=outs[p], prec=p), reps))
+        r = {"ms": round(ms, 4), "GBps_actual": round((BLOCK + RECORD) * nblk / ms / 1e6, 1),
+             "GBps_fp64_equiv": round(8 * n * n / ms / 1e6, 1)}
+        D = blaz.decompress(outs[p])
+        r["rel_err_vs_field"] = float(f"{torch.linalg.norm(D - dM).item() / norm:.4e}")
+        if p == "fp64":
+            D64 = D
+        else:
+            o = outs[p]
+            r["f_s_identical"] = bool(torch.equal(o.f.view(torch.int64), ref.f.view(torch.int64))
+                                      and torch.equal(o.s.view(torch.int64), ref.s.view(torch.int64)))
+            r["code_mismatch_rate"] = float(f"{(o.codes != ref.codes).sum().item() / (28 * nblk):.3e}")
+            r["phi_flip_rate"] = float(f"{(o.phi != ref.phi).sum().item() / nblk:.3e}")
+            r["rel_err_vs_fp64_path"] = float(f"{torch.linalg.norm(D - D64).item() / norm:.4e}")
+            del D
+        res[p] = r
+    res["note"] = ("mismatches are against the FP64 path, which the parity tests hold to the oracle "
+                   "(bit-exact except boundary ties); rel_err_vs_field of fp64 is the method's own error")
+    return res
+
+
+def serving_leg(torch, dA, dB, count, budget_gib, loads=(0.5, 0.8, 1.2)):
     """The serving mix: `count` requests (compress 30%, add 25%, scale 15%,
     dot 15%, matmul 15%), sides log-uniform in [64, 8192], on the two 8192^2
     fields (each side n uses their n x n corners).  The plain form's capacity
     is measured with every request of a calibration set arriving at once;
-    the Poisson stream then arrives at 0.8x that rate and is served in the
-    plain form, batched with FP64 matmuls, and batched with BF16x3 matmuls."""
+    the Poisson stream then arrives at 0.5x, 0.8x and 1.2x that rate and is
+    served in the plain form, batched with FP64 matmuls, and batched with
+    BF16x3 matmuls."""
     from paper_2202_13007_amd.serve import OperandPool, Server, make_requests
     from paper_2202_13007_amd.tune import Autotuner
 
@@ -167,17 +362,18 @@ def serving_leg(torch, dA, dB, count, budget_gib):
         cap[name] = rep["req_per_s"]
     out["capacity_req_per_s"] = {k: round(v, 1) for k, v in cap.items()}
     out["capacity_speedup_vs_plain"] = {k: round(v / cap["plain"], 3) for k, v in cap.items()}
-    rate = 0.8 * cap["plain"]
-    out["arrival_rate_req_per_s"] = round(rate, 1)
-    runs = {}
-    for name, srv in servers.items():
-        reqs = make_requests(count, rate=rate, seed=501)
-        srv.prepare(reqs)
-        rep = srv.run(reqs, "plain" if name == "plain" else "batched")
-        runs[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()}
-        print(f"# serving {name}: p50 {rep['p50_ms']:.2f} ms p99 {rep['p99_ms']:.2f} ms "
-              f"{rep['req_per_s']:.0f} req/s", file=sys.stderr, flush=True)
-    out["runs"] = runs
+    out["runs"] = {}
+    for load in loads:
+        rate = load * cap["plain"]
+        runs = {"arrival_rate_req_per_s": round(rate, 1)}
+        for name, srv in servers.items():
+            reqs = make_requests(count, rate=rate, seed=501)
+            srv.prepare(reqs)
+            rep = srv.run(reqs, "plain" if name == "plain" else "batched")
+            runs[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()}
+            print(f"# serving {load}x {name}: p50 {rep['p50_ms']:.2f} ms p99 {rep['p99_ms']:.2f} ms "
+                  f"{rep['req_per_s']:.0f} req/s", file=sys.stderr, flush=True)
+        out["runs"][f"{load}x_plain_capacity"] = runs
     return out
 
 
@@ -283,7 +479,7 @@ def main():
     # Roofline of the dominant kernel: compress, 557 algorithmic bytes per block.
     comp_ms = (per["compress_x"] + per["compress_y"]) / 2
     achieved = (BLOCK + RECORD) * nblk / comp_ms / 1e6
-    traffic = traffic_for("paper_2202_13007_amd/csrc/codec.hip", "compress_f64_kernel")
+    traffic = traffic_for("compress_f64_kernel", CODEC_SOURCES)
     roofline = {"kernel": "compress_f64_kernel", "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic}
@@ -308,13 +504,29 @@ def main():
         "ops": op_report,
         "plain_dense_fp64": plain,
     }
+    result["paper_context"] = {
+        "hardware": "Intel Core i7-1165G7, 4 cores (the paper's machine; no GPU numbers are published)",
+        "blaz_add_n2000_ms": 0.15, "blaz_add_n2000_GBps_fp64_equiv": 640.0,
+        "blaz_scale_n2000_ms": 0.14, "blaz_scale_n2000_GBps_fp64_equiv": 457.0,
+        "dense_add_n2000_GBps": 10.3, "note": "context only, not a target"}
     del D
+    if not args.no_extra:
+        print("# cold/warm single-op leg", file=sys.stderr, flush=True)
+        result["ops_single_launch"] = cold_ops_leg(blaz, torch, dA, dB)
     if args.serve_requests > 0:
         result["serving"] = serving_leg(torch, dA, dB, args.serve_requests, args.serve_budget_gib)
     del dA, dB
 
+    if not args.no_extra:
+        print("# 64x64 latency leg", file=sys.stderr, flush=True)
+        result["latency_64"] = latency_leg(blaz, torch, workload_inputs)
     if not args.no_matmul:
+        print("# 4096 linear-algebra leg", file=sys.stderr, flush=True)
         result["matmul_4096"] = matmul_leg(blaz, torch, workload_inputs)
+    if not args.no_extra:
+        print("# 16384 mixed-precision leg", file=sys.stderr, flush=True)
+        result["mixed_16384"] = mixed_leg(blaz, torch, workload_inputs)
+        torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(A, B, min(args.cpu_rows, n))
