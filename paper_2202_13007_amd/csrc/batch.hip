@@ -1,11 +1,13 @@
-// Batching: a flat queue of 64-block chunks (or single dot products) over
-// many operations on matrices of any sizes, drained by one persistent launch.
+// Batching: a flat queue of 64-block chunks (or groups of 8 dot products)
+// over many operations on matrices of any sizes, drained by one persistent
+// launch.
 //
 // The blocks of the method are independent (each operation is applied
 // blockwise, end of Section "Basic Linear Algebra Algorithms"), so a batch is
-// a list of items, each cut into chunks: a chunk is the unit one wave of the
-// standalone kernels handles -- 64 consecutive blocks of a compress,
-// decompress, add, sub or scale, or one dot product.  The plan stores every
+// a list of items, each cut into chunks: a chunk is the unit one workgroup of
+// the standalone kernels handles -- 64 consecutive blocks of a compress,
+// decompress, add, sub or scale, or a group of 8 consecutive dot products
+// (whose four parts the batch wave runs one after the other).  The plan stores every
 // item's first chunk index (a prefix sum); a fixed grid of one-wave
 // workgroups pops chunk indices from an atomic counter, finds the item by
 // binary search and runs the same device body as the standalone kernel, until
@@ -53,6 +55,7 @@ struct BatchItemDev {
     int64_t nbr_x;  // DOT, DOT_DENSE: block rows of x
     int64_t nbc_y;  // DOT: block columns of y
     int64_t nk;     // DOT: block columns of x = block rows of y
+    int64_t count;  // DOT, DOT_DENSE: dot products
 };
 
 __global__ void batch_reset_kernel(unsigned long long* counter) { *counter = 0ull; }
@@ -108,12 +111,13 @@ __global__ __launch_bounds__(kWave, 2) void batch_kernel(const BatchItemDev* __r
                 break;
             }
             case BLAZ_OP_DOT:
-                dot_wave(local, lane, it.xf, it.xs, it.xphi, it.xc, it.nbr_x, it.yf, it.ys, it.yphi, it.yc, it.nbc_y,
-                         it.nk, it.xrow, it.ycol, it.out);
+                dot_group_one_wave(lane, local * kDotGroup, it.count, DotOperand{it.xf, it.xs, it.xphi, it.xc},
+                                   it.nbr_x, DotOperand{it.yf, it.ys, it.yphi, it.yc}, it.nbc_y, it.nk, it.xrow,
+                                   it.ycol, it.out);
                 break;
             default:  // BLAZ_OP_DOT_DENSE
-                dot_dense_wave(local, lane, it.xf, it.xs, it.xphi, it.xc, it.nbr_x, it.nbc, it.xrow, it.dense, it.ld,
-                               it.out);
+                dot_dense_group_one_wave(lane, local * kDotGroup, it.count, DotOperand{it.xf, it.xs, it.xphi, it.xc},
+                                         it.nbr_x, it.nbc, it.xrow, it.dense, it.ld, it.out);
                 break;
         }
     }
@@ -198,14 +202,16 @@ BLAZ_API blaz_status blaz_batch_plan(const blaz_batch_item* items, int64_t n_ite
                 d.nbr_x = it.x.rows / 8;
                 d.nbc_y = it.y.cols / 8;
                 d.nk = it.x.cols / 8;
-                n = it.count;
+                d.count = it.count;
+                n = (it.count + kDotGroup - 1) / kDotGroup;
                 break;
             case BLAZ_OP_DOT_DENSE:
                 st = validate_dot_dense(&it.x, it.xrow, it.dense, it.ld, it.count, it.out, &empty);
                 set_matrix(it.x, d.xf, d.xs, d.xphi, d.xc);
                 d.nbr_x = it.x.rows / 8;
                 d.nbc = it.x.cols / 8;
-                n = it.count;
+                d.count = it.count;
+                n = (it.count + kDotGroup - 1) / kDotGroup;
                 break;
             default:
                 st = BLAZ_ERR_ARG;

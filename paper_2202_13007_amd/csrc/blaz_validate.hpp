@@ -11,7 +11,7 @@ namespace blaz {
 namespace validate {
 
 constexpr int64_t kRecordBytes = 45;  // f (8) + s (8) + phi (1) + 28 codes
-constexpr int64_t kMaxDots = int64_t(1) << 32;  // four dot products per workgroup
+constexpr int64_t kMaxDots = int64_t(1) << 32;  // eight dot products per workgroup: grid < 2^32
 
 inline bool aligned(const void* p, uintptr_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
 

@@ -61,11 +61,11 @@ def test_plan_counts_chunks_and_drops_empty_items():
              z=fake_matrix(8, 8, 0x4000000)),                                             # 1 block -> 1
         item("scale", x=fake_matrix(0, 64, 0), z=fake_matrix(0, 64, 0), c=2.0),          # empty
         item("dot", x=fake_matrix(16, 24, 0x5000000), y=fake_matrix(24, 8, 0x6000000),
-             xrow=0x7000000, ycol=0x7100000, count=7, out=0x7200000),                     # 7 dots -> 7
+             xrow=0x7000000, ycol=0x7100000, count=17, out=0x7200000),                    # 17 dots -> 3 groups
         item("decompress", x=fake_matrix(64, 64, 0x9000000), dense=0xa000000, ld=64),    # 64 blocks -> 1
     ]
     st, n_plan, total = plan(items)
-    assert st == 0 and n_plan == 4 and total == 5 + 1 + 7 + 1
+    assert st == 0 and n_plan == 4 and total == 5 + 1 + 3 + 1
 
 
 @pytest.mark.parametrize("bad,status", [
@@ -131,6 +131,15 @@ def make_workload(torch, blaz):
     out = torch.empty(100, dtype=torch.float64, device="cuda")
     B.dot(X[3], xrow, ymat, ycol, out)
     expect.append((out, blaz.dot(X[3], xrow, ymat, ycol)))
+    # aligned groups (the 8 lines of a block row in order) take the grouped path
+    lines = torch.arange(64, dtype=torch.int64).cuda()
+    out3 = torch.empty(64, dtype=torch.float64, device="cuda")
+    B.dot(X[3], lines, ymat, lines, out3)
+    expect.append((out3, blaz.dot(X[3], lines, ymat, lines)))
+    V48 = torch.from_numpy(uniform_matrix(48, 528, 992)).cuda()
+    out4 = torch.empty(48, dtype=torch.float64, device="cuda")
+    B.dot_dense(X[4], lines[:48], V48, out4)
+    expect.append((out4, blaz.dot_dense(X[4], lines[:48], V48)))
     V = torch.from_numpy(uniform_matrix(50, 528, 991)).cuda()
     rows = torch.from_numpy(rng.integers(0, 1032, 50)).cuda()
     out2 = torch.empty(50, dtype=torch.float64, device="cuda")

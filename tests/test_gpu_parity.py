@@ -321,6 +321,63 @@ def test_dot_dense(shared):
     assert_dots_close(got, want, mag, what="dot_dense")
 
 
+def _bits(a):
+    return np.asarray(a, dtype=np.float64).view(np.int64)
+
+
+@pytest.mark.parametrize("kind", ["pairs", "own_vectors", "shared_vector"])
+def test_dot_aligned_groups_equal_single_queries(kind):
+    """Queries on the 8 lines of a block row, in order, rebuild each block
+    once for the group; the same queries shifted off that alignment take the
+    per-query path.  Both must give the same bits (2056 columns = 257 blocks
+    per line, so the 256 slots wrap), and match the oracle."""
+    X = smooth_field(64, 4, 2.0, 1e-3, 430, cols=2056)
+    ox = oracle.compress(X)
+    gx = upload(ox)
+    rows = np.arange(64)
+    shifted = np.concatenate([[5], rows])          # every group of 8 is now misaligned
+    if kind == "pairs":
+        oy = oracle.compress(smooth_field(2056, 4, 2.0, 1e-3, 431, cols=64))
+        gy = upload(oy)
+        got = blaz.dot(gx, dev(rows), gy, dev(rows)).cpu().numpy()
+        alt = blaz.dot(gx, dev(shifted), gy, dev(np.concatenate([[3], rows]))).cpu().numpy()[1:]
+        want = oracle.dot(ox, rows, oy, rows)
+        Xd, Yd = oracle.decompress(ox), oracle.decompress(oy)
+        mag = np.array([np.abs(Xd[i]) @ np.abs(Yd[:, i]) for i in rows])
+    else:
+        V = uniform_matrix(65, 2056, 432)
+        if kind == "shared_vector":
+            got = blaz.dot_dense(gx, dev(rows), dev(V[0])).cpu().numpy()
+            alt = blaz.dot_dense(gx, dev(shifted), dev(V[0])).cpu().numpy()[1:]
+            want = oracle.dot_dense(ox, rows, V[0], 0)
+            Vq = np.repeat(V[:1], 64, axis=0)
+        else:
+            got = blaz.dot_dense(gx, dev(rows), dev(V[1:])).cpu().numpy()
+            alt = blaz.dot_dense(gx, dev(shifted), dev(V)).cpu().numpy()[1:]
+            want = oracle.dot_dense(ox, rows, V[1:], 2056)
+            Vq = V[1:]
+        Xd = oracle.decompress(ox)
+        mag = np.array([np.abs(Xd[i]) @ np.abs(Vq[i]) for i in rows])
+    assert np.array_equal(_bits(got), _bits(alt))
+    assert_dots_close(got, want, mag, what=f"dot {kind} aligned")
+
+
+def test_dot_ragged_group_and_invalid_in_aligned_position():
+    """A last group of fewer than 8 queries, and an out-of-range index inside
+    an otherwise aligned run, take the per-query path."""
+    X = smooth_field(32, 4, 2.0, 1e-3, 433, cols=72)
+    ox = oracle.compress(X)
+    gx = upload(ox)
+    V = uniform_matrix(1, 72, 434)[0]
+    rows = np.concatenate([np.arange(8), [8, 9, 10, 99, 12, 13, 14, 15], np.arange(16, 27)])
+    got = blaz.dot_dense(gx, dev(rows), dev(V)).cpu().numpy()
+    ok = rows < 32
+    assert np.isnan(got[~ok]).all() and np.isfinite(got[ok]).all()
+    want = oracle.dot_dense(ox, rows[ok], V, 0)
+    Xd = oracle.decompress(ox)
+    assert_dots_close(got[ok], want, np.array([np.abs(Xd[i]) @ np.abs(V) for i in rows[ok]]), what="ragged")
+
+
 def band_rows(og: oracle.Compressed, i: int) -> np.ndarray:
     """Line i of a compressed matrix, decompressed by the oracle (its block row only)."""
     nbc = og.cols // 8
