@@ -167,6 +167,19 @@ def matmul_leg(blaz, torch, workload_inputs):
         ms = a.elapsed_time(b) / 5
         tf = 2 * n ** 3 / ms / 1e9
         legs[name] = {"ms": round(ms, 4), "TFLOPs": round(tf, 2), "mfma_frac": round(tf / peaks[name], 4)}
+    # the product recompressed (results kept in the 45-byte form)
+    gB = blaz.compress(dB)
+    wsc = torch.empty(max(blaz.matmul_compressed_workspace_bytes(n, n, n, True, p) for p in ("fp64", "bf16x3")),
+                      dtype=torch.uint8, device="cuda")
+    cout = blaz.BlazMatrix.empty(n, n)
+    for p in ("fp64", "bf16x3"):
+        ms = median(timed_each(torch, lambda p=p: blaz.matmul_compressed(g, gB, out=cout, prec=p, workspace=wsc), 5))
+        dms = median(timed_each(torch, lambda p=p: blaz.matmul(g, gB, out=outs[p], prec=p, workspace=wsc), 5))
+        legs[p]["compressed_output"] = {"ms": round(ms, 4), "dense_output_ms_same_operands": round(dms, 4),
+                                        "what": "compressed A x compressed B, product recompressed"}
+    del wsc, cout, gB
+    for p in ("fp64", "bf16x3"):
+        blaz.matmul(g, dB, out=outs[p], prec=p, workspace=ws)
     ref = outs["fp64"]
     nref = torch.linalg.norm(ref).item()
     for p in ("fp32", "bf16x3", "plain"):

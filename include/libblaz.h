@@ -180,6 +180,25 @@ blaz_status blaz_matmul_tiled(const blaz_matrix *a, const blaz_matrix *b, const 
                               int64_t ldb, double *c, int64_t ldc, blaz_precision prec, void *workspace,
                               size_t ws_bytes, int32_t tile, hipStream_t stream);
 
+/* Bytes of workspace blaz_matmul_compressed needs: the contraction's own
+ * workspace plus an m x n binary64 staging area for the product. */
+size_t blaz_matmul_compressed_workspace_bytes(int64_t m, int64_t n, int64_t k, int b_compressed,
+                                              blaz_precision prec);
+
+/* Matrix multiplication with a compressed result: C = A B as in
+ * blaz_matmul_tiled (same operand forms, prec and tile), then C is
+ * compressed blockwise into c (c->rows == a->rows, c->cols == n, else
+ * BLAZ_ERR_MISMATCH) with the binary64 transform, so a product can stay
+ * resident in the 45-byte form.  The paper leaves the output form of the
+ * product open (last paragraph of Section "Basic Linear Algebra Algorithms");
+ * this entry point gives the compressed one.  The result is bit for bit the
+ * compression of blaz_matmul_tiled's output.  workspace holds
+ * blaz_matmul_compressed_workspace_bytes() bytes, 256-byte aligned; c must
+ * not overlap the inputs or the workspace. */
+blaz_status blaz_matmul_compressed(const blaz_matrix *a, const blaz_matrix *b, const double *bdense, int64_t n,
+                                   int64_t ldb, blaz_matrix *c, blaz_precision prec, void *workspace,
+                                   size_t ws_bytes, int32_t tile, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Batching: many operations, on matrices of any sizes, in one persistent
  * launch.  Every 8x8 block is independent (the paper's blockwise

@@ -23,8 +23,8 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 EXPORTS = (
     "blaz_block_count", "blaz_compressed_bytes", "blaz_compress", "blaz_decompress", "blaz_add",
     "blaz_sub", "blaz_scale", "blaz_dot", "blaz_dot_dense", "blaz_matmul_workspace_bytes",
-    "blaz_matmul", "blaz_matmul_tiled", "blaz_status_string", "blaz_batch_plan_bytes", "blaz_batch_plan",
-    "blaz_batch_run",
+    "blaz_matmul", "blaz_matmul_tiled", "blaz_matmul_compressed_workspace_bytes", "blaz_matmul_compressed",
+    "blaz_status_string", "blaz_batch_plan_bytes", "blaz_batch_plan", "blaz_batch_run",
 )
 
 
@@ -101,6 +101,8 @@ def lib():
         "blaz_matmul_workspace_bytes": ([I64, I64, I64, I, I], ctypes.c_size_t),
         "blaz_matmul": ([M, M, P, I64, I64, P, I64, I, P, ctypes.c_size_t, P], I),
         "blaz_matmul_tiled": ([M, M, P, I64, I64, P, I64, I, P, ctypes.c_size_t, ctypes.c_int32, P], I),
+        "blaz_matmul_compressed_workspace_bytes": ([I64, I64, I64, I, I], ctypes.c_size_t),
+        "blaz_matmul_compressed": ([M, M, P, I64, I64, M, I, P, ctypes.c_size_t, ctypes.c_int32, P], I),
         "blaz_status_string": ([I], ctypes.c_char_p),
         "blaz_batch_plan_bytes": ([I64], ctypes.c_size_t),
         "blaz_batch_plan": ([P, I64, P, ctypes.c_size_t, P, P], I),

@@ -186,6 +186,32 @@ def matmul(a: BlazMatrix, b: BlazMatrix | torch.Tensor, out: torch.Tensor | None
     return out
 
 
+def matmul_compressed_workspace_bytes(m: int, n: int, k: int, b_compressed: bool, prec: str = "fp64") -> int:
+    return int(_lib.lib().blaz_matmul_compressed_workspace_bytes(m, n, k, int(b_compressed), _lib.PREC[prec]))
+
+
+def matmul_compressed(a: BlazMatrix, b: BlazMatrix | torch.Tensor, out: BlazMatrix | None = None,
+                      prec: str = "fp64", workspace: torch.Tensor | None = None, tile: int = 0) -> BlazMatrix:
+    """C = A B compressed (the compression of ``matmul(a, b, prec=prec)``)."""
+    compressed_b = isinstance(b, BlazMatrix)
+    n = b.cols if compressed_b else b.shape[1]
+    if not compressed_b:
+        _check_dense(b, "matmul B")
+    if out is None:
+        out = BlazMatrix.empty(a.rows, n, a.f.device)
+    need = matmul_compressed_workspace_bytes(a.rows, n, a.cols, compressed_b, prec)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=a.f.device)
+    ma, mc = a.c(), out.c()
+    mb = b.c() if compressed_b else None
+    check(_lib.lib().blaz_matmul_compressed(ctypes.byref(ma), ctypes.byref(mb) if compressed_b else None,
+                                            None if compressed_b else _ptr(b), n,
+                                            0 if compressed_b else b.stride(0), ctypes.byref(mc),
+                                            _lib.PREC[prec], _ptr(workspace), workspace.numel(), int(tile),
+                                            _stream()), "blaz_matmul_compressed")
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Batching: many operations in one persistent launch
 # ---------------------------------------------------------------------------

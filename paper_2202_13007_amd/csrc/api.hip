@@ -257,6 +257,61 @@ BLAZ_API blaz_status blaz_matmul_tiled(const blaz_matrix* a, const blaz_matrix* 
     return matmul_impl(a, b, bdense, n, ldb, c, ldc, prec, workspace, ws_bytes, tile, stream);
 }
 
+// The compressed-output product: the contraction writes C into a staging
+// region after the contraction's own workspace, then C is compressed.
+static size_t matmul_compressed_workspace(int64_t m, int64_t n, int64_t k, bool b_compressed, blaz_precision prec)
+{
+    return matmul_workspace(m, n, k, b_compressed, prec).total() + round_up((size_t)m * (size_t)n * 8, 256);
+}
+
+BLAZ_API size_t blaz_matmul_compressed_workspace_bytes(int64_t m, int64_t n, int64_t k, int b_compressed,
+                                                       blaz_precision prec)
+{
+    if (check_shape(m, k) != BLAZ_OK || check_shape(k, n) != BLAZ_OK || !valid_precision(prec)) return 0;
+    return matmul_compressed_workspace(m, n, k, b_compressed != 0, prec);
+}
+
+BLAZ_API blaz_status blaz_matmul_compressed(const blaz_matrix* a, const blaz_matrix* b, const double* bdense,
+                                            int64_t n, int64_t ldb, blaz_matrix* c, blaz_precision prec,
+                                            void* workspace, size_t ws_bytes, int32_t tile, hipStream_t stream)
+{
+    if (tile != 0 && tile != 64 && tile != 128) return BLAZ_ERR_ARG;
+    if (blaz_status st = check_matrix(a)) return st;
+    if (blaz_status st = check_matrix(c)) return st;
+    if (b && bdense) return BLAZ_ERR_ARG;
+    if (!b && !bdense && a->cols > 0) return BLAZ_ERR_NULL;
+    if (!valid_precision(prec)) return BLAZ_ERR_ARG;
+    const int64_t m = a->rows, k = a->cols;
+    if (b) {
+        if (blaz_status st = check_matrix(b)) return st;
+        if (b->rows != k || b->cols != n) return BLAZ_ERR_MISMATCH;
+    }
+    if (check_shape(k, n) != BLAZ_OK) return BLAZ_ERR_SHAPE;
+    if (c->rows != m || c->cols != n) return BLAZ_ERR_MISMATCH;
+    if (m == 0 || n == 0) return BLAZ_OK;
+    if (!b && k > 0) {
+        if (ldb < n) return BLAZ_ERR_SHAPE;
+        if (!aligned(bdense, 16) || ldb % 2 != 0) return BLAZ_ERR_ALIGN;
+    }
+    const size_t mm = matmul_workspace(m, n, k, b != nullptr, prec).total();
+    const size_t need = matmul_compressed_workspace(m, n, k, b != nullptr, prec);
+    if (!workspace || ws_bytes < need) return BLAZ_ERR_WORKSPACE;
+    if (!aligned(workspace, 256)) return BLAZ_ERR_ALIGN;
+    const Range rw = span(workspace, (int64_t)need);
+    if (overlaps_matrix(rw, *c) || overlaps_matrix(rw, *a) || (b && overlaps_matrix(rw, *b)) ||
+        (bdense && overlap(rw, span(bdense, dense_span(k, n, ldb)))))
+        return BLAZ_ERR_ARG;
+    Range rc[4];
+    ranges(*c, rc);
+    for (const Range& r : rc)
+        if (overlaps_matrix(r, *a) || (b && overlaps_matrix(r, *b)) ||
+            (bdense && overlap(r, span(bdense, dense_span(k, n, ldb)))))
+            return BLAZ_ERR_ARG;
+    double* stage = reinterpret_cast<double*>(static_cast<char*>(workspace) + mm);
+    if (blaz_status st = matmul_impl(a, b, bdense, n, ldb, stage, n, prec, workspace, mm, tile, stream)) return st;
+    return hip_status(blaz::detail::launch_compress_f64(stage, n, *c, nullptr, stream));
+}
+
 BLAZ_API const char* blaz_status_string(blaz_status status)
 {
     switch (status) {

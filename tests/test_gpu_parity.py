@@ -414,6 +414,98 @@ def test_dot_equals_matmul_element():
     assert np.all(np.abs(d - P) <= 2e-12 * mag)
 
 
+# --------------------------------------------------------------------------
+# Matmul with a compressed result
+# --------------------------------------------------------------------------
+
+def blocks_max(M):
+    r, c = M.shape
+    return M.reshape(r // 8, 8, c // 8, 8).max(axis=(1, 3)).ravel()
+
+
+def assert_compressed_product(got, Xd, Yd, what):
+    """The GPU's compressed product against the oracle's compression of the
+    oracle's product.  The two products differ by rounding only: each is a
+    binary64 sum of k products, within k 2^-53 sum|x y| of the exact value,
+    so per block e = max of 2 k 2^-53 sum|x y|.  Propagated through the
+    compressor: |df| <= e, |ds| <= 128 e / K <= 128 e; the normalized block
+    moves by sum|dD'| <= 256 e / s, so every coefficient by at most
+    max|T_iu T_jv| * 256 e / s = 64 e / s, phi's argument 127/m by
+    127 (64 e / s) / m^2, and a code's argument phi D by phi 64 e / s.  A code
+    (or phi) may differ by exactly 1 where the oracle's argument lies that
+    close to an integer; everything else must agree."""
+    k = Xd.shape[1]
+    P = oracle.gemm(Xd, Yd)
+    o, (_, code_x, phi_x) = oracle.compress(P, with_debug=True)
+    e = blocks_max(2.0 * k * 2.0 ** -53 * (np.abs(Xd) @ np.abs(Yd)))
+    gf, gs, gphi, gcodes = host(got)
+    slack = 2.0 ** -40
+    assert np.all(o.s > 0), "test data must not hold constant product blocks"
+    assert np.all(np.abs(gf - o.f) <= e + slack * np.abs(o.f)), f"{what}: f"
+    assert np.all(np.abs(gs - o.s) <= 128 * e + slack * o.s), f"{what}: s"
+    dD = 64.0 * e / o.s
+    m = 127.0 / phi_x
+    band_phi = 127.0 * dD / m ** 2 + slack * np.maximum(1.0, phi_x)
+    dphi = gphi.astype(int) - o.phi.astype(int)
+    near_phi = np.abs(phi_x - np.round(phi_x)) <= band_phi
+    assert np.all((dphi == 0) | ((np.abs(dphi) == 1) & near_phi)), f"{what}: phi"
+    same = dphi == 0
+    band = (o.phi.astype(float) * dD)[:, None] + slack * np.maximum(1.0, np.abs(code_x))
+    dc = gcodes.astype(int) - o.codes.astype(int)
+    near = np.abs(code_x - np.round(code_x)) <= band
+    ok = (dc == 0) | ((np.abs(dc) == 1) & near)
+    assert np.all(ok[same]), f"{what}: {int((~ok[same]).sum())} codes differ off the perturbation band"
+    return int((dc != 0)[same].sum()) + int((~same).sum())
+
+
+@pytest.mark.parametrize("m,k,n,bform", [(128, 128, 128, "compressed"), (136, 200, 72, "dense"),
+                                         (64, 8, 264, "compressed")])
+def test_matmul_compressed_against_oracle(m, k, n, bform):
+    X = smooth_field(m, 4, 2.0, 1e-3, 440, cols=k)
+    Y = smooth_field(k, 4, 2.0, 1e-3, 441, cols=n) + 3.0
+    ox = oracle.compress(X)
+    Xd = oracle.decompress(ox)
+    if bform == "compressed":
+        oy = oracle.compress(Y)
+        Yd = oracle.decompress(oy)
+        got = blaz.matmul_compressed(upload(ox), upload(oy))
+    else:
+        Yd = Y
+        got = blaz.matmul_compressed(upload(ox), dev(Y))
+    torch.cuda.synchronize()
+    flips = assert_compressed_product(got, Xd, Yd, f"matmul_compressed {m}x{k}x{n}")
+    assert flips <= 1e-3 * (m // 8) * (n // 8) * 28
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("tile", [64, 128])
+def test_matmul_compressed_is_compress_of_matmul(prec, tile):
+    """Bit for bit the compression of the dense product, in every contraction
+    arithmetic and tile, with dense and compressed B."""
+    X = smooth_field(264, 4, 2.0, 1e-3, 442, cols=136)
+    Y = smooth_field(136, 4, 2.0, 1e-3, 443, cols=200)
+    gx, gy = blaz.compress(dev(X)), blaz.compress(dev(Y))
+    for b in (gy, dev(Y)):
+        got = blaz.matmul_compressed(gx, b, prec=prec, tile=tile)
+        want = blaz.compress(blaz.matmul(gx, b, prec=prec, tile=tile))
+        assert_same_compressed(host(got), host(want), f"matmul_compressed {prec} tile {tile}")
+
+
+def test_matmul_compressed_k0_and_workspace_reuse():
+    """k = 0 gives the compressed zero matrix; a second call with a smaller
+    product reuses the same workspace and output buffers."""
+    z = blaz.matmul_compressed(blaz.BlazMatrix.empty(16, 0), torch.empty((0, 24), dtype=torch.float64, device="cuda"))
+    assert_same_compressed(host(z), oracle_tuple(oracle.compress(np.zeros((16, 24)))), "k = 0")
+    X = smooth_field(128, 4, 2.0, 1e-3, 444)
+    gx = blaz.compress(dev(X))
+    ws = torch.empty(blaz.matmul_compressed_workspace_bytes(128, 128, 128, True), dtype=torch.uint8, device="cuda")
+    first = blaz.matmul_compressed(gx, gx, workspace=ws)
+    small = blaz.compress(dev(X[:64, :64]))
+    second = blaz.matmul_compressed(small, small, workspace=ws)
+    assert_same_compressed(host(second), host(blaz.compress(blaz.matmul(small, small))), "second call")
+    assert_same_compressed(host(first), host(blaz.compress(blaz.matmul(gx, gx))), "first call")
+
+
 def test_matmul_plain_64_workload():
     """64x64 partly-decompressed product of the two compressed fields."""
     A, B = workload_inputs("plain-64")

@@ -144,6 +144,24 @@ def test_matmul_validation(L):
     assert L.blaz_matmul(B(a), B(b), None, 8, 8, C, 8, 5, ws, need, None) == -5       # bad precision
 
 
+def test_matmul_compressed_validation(L):
+    a, b = mat(16, 24, 0x100000), mat(24, 8, 0x200000)
+    c, ws = mat(16, 8, 0x300000), 0x400000
+    need = L.blaz_matmul_compressed_workspace_bytes(16, 8, 24, 1, 0)
+    assert need >= L.blaz_matmul_workspace_bytes(16, 8, 24, 1, 0) + 8 * 16 * 8
+    assert L.blaz_matmul_compressed_workspace_bytes(16, 8, 20, 1, 0) == 0              # k not a multiple of 8
+    f = L.blaz_matmul_compressed
+    assert f(B(a), B(b), 0x500000, 8, 8, B(c), 0, ws, need, 0, None) == -5   # both B forms
+    assert f(B(a), None, None, 8, 8, B(c), 0, ws, need, 0, None) == -1       # no B
+    assert f(B(a), B(b), None, 8, 8, B(mat(8, 8, 0x300000)), 0, ws, need, 0, None) == -3   # c shape
+    assert f(B(a), B(b), None, 8, 8, B(c), 0, ws, need - 8, 0, None) == -7
+    assert f(B(a), B(b), None, 8, 8, B(c), 0, ws + 8, need, 0, None) == -4
+    assert f(B(a), B(b), None, 8, 8, B(c), 0, ws, need, 32, None) == -5      # tile
+    assert f(B(a), B(b), None, 8, 8, B(c), 7, ws, need, 0, None) == -5       # precision
+    assert f(B(a), B(b), None, 8, 8, B(mat(16, 8, ws + 256)), 0, ws, need, 0, None) == -5  # c inside ws
+    assert f(B(a), B(b), None, 8, 8, B(mat(16, 8, 0x100000)), 0, ws, need, 0, None) == -5  # c over a
+
+
 # --------------------------------------------------------------------------
 # The parity rules (tests/parity.py) catch what they should
 # --------------------------------------------------------------------------
