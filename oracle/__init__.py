@@ -22,6 +22,20 @@ NKEPT = 28
 KEPT = [(i, j) for i in range(8) for j in range(8) if i < 2 or j < 2]
 
 
+def kept_count(lines: int) -> int:
+    """Codes per block with L kept lines (rows and columns 0..L-1)."""
+    return 16 * lines - lines * lines
+
+
+def code_stride(lines: int) -> int:
+    """Bytes per block of the codes array: the codes padded to whole 32-bit words."""
+    return 4 * ((kept_count(lines) + 3) // 4)
+
+
+def kept_positions(lines: int):
+    return [(i, j) for i in range(8) for j in range(8) if i < lines or j < lines]
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no fast-math, no FP contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -58,6 +72,11 @@ def lib():
             "oracle_dot": ([P, P, P, P, I64, P, P, P, P, I64, P, P, I64, P], None),
             "oracle_dot_dense": ([P, P, P, P, I64, P, P, I64, I64, P], None),
             "oracle_gemm": ([P, I64, P, I64, P, I64, I64, I64, I64], None),
+            "oracle_kept_count": ([ctypes.c_int], ctypes.c_int),
+            "oracle_compress_lines": ([P, I64, I64, I64, ctypes.c_int, I64, P, P, P, P, P, P], None),
+            "oracle_decompress_lines": ([P, P, P, P, I64, I64, ctypes.c_int, I64, P, I64], None),
+            "oracle_add_codes": ([I64, ctypes.c_int, I64, P, P, P, P, P, P, P, P, P, P, P, P], None),
+            "oracle_scale_codes": ([I64, ctypes.c_int, I64, P, P, P, P, D, P, P, P, P], None),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -103,25 +122,27 @@ def compress_block(M) -> BlockTrace:
 
 
 class Compressed:
-    """Host-side compressed matrix: f, s, phi, codes (struct of arrays)."""
+    """Host-side compressed matrix: f, s, phi, codes (struct of arrays).
+    lines = kept lines L (2: the paper's 28 codes); codes is [nblk][code_stride(L)]."""
 
-    def __init__(self, rows, cols, f, s, phi, codes):
+    def __init__(self, rows, cols, f, s, phi, codes, lines=2):
         self.rows, self.cols = int(rows), int(cols)
         self.f, self.s, self.phi, self.codes = f, s, phi, codes
+        self.lines = int(lines)
 
     @property
     def nblk(self):
         return (self.rows // 8) * (self.cols // 8)
 
     @staticmethod
-    def empty(rows, cols):
+    def empty(rows, cols, lines=2):
         nb = (rows // 8) * (cols // 8)
         return Compressed(rows, cols, np.zeros(nb), np.zeros(nb), np.zeros(nb, np.uint8),
-                          np.zeros((nb, NKEPT), np.int8))
+                          np.zeros((nb, code_stride(lines)), np.int8), lines)
 
     def copy(self):
         return Compressed(self.rows, self.cols, self.f.copy(), self.s.copy(), self.phi.copy(),
-                          self.codes.copy())
+                          self.codes.copy(), self.lines)
 
 
 def compress(A, with_debug: bool = False):
@@ -164,9 +185,31 @@ def compress_blocks(A, blocks):
     return f, s, phi, codes, code_x, phi_x
 
 
+def compress_lines(A, lines: int, with_debug: bool = False):
+    """Compression keeping L lines of DCT coefficients (the tunable rate);
+    lines = 2 gives the paper's records.  With ``with_debug`` also returns
+    (code_x[nblk, 16L - L^2], phi_x[nblk])."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    rows, cols = A.shape
+    assert rows % 8 == 0 and cols % 8 == 0 and 1 <= lines <= 8
+    out = Compressed.empty(rows, cols, lines)
+    nb = out.nblk
+    code_x = np.zeros((nb, kept_count(lines))) if with_debug else None
+    phi_x = np.zeros(nb) if with_debug else None
+    lib().oracle_compress_lines(_p(A), rows, cols, cols, lines, code_stride(lines), _p(out.f), _p(out.s),
+                                _p(out.phi), _p(out.codes), _p(code_x), _p(phi_x))
+    if with_debug:
+        return out, (code_x, phi_x)
+    return out
+
+
 def decompress(c: Compressed):
     A = np.zeros((c.rows, c.cols))
-    lib().oracle_decompress(_p(c.f), _p(c.s), _p(c.phi), _p(c.codes), c.rows, c.cols, _p(A), c.cols)
+    if c.lines == 2:
+        lib().oracle_decompress(_p(c.f), _p(c.s), _p(c.phi), _p(c.codes), c.rows, c.cols, _p(A), c.cols)
+    else:
+        lib().oracle_decompress_lines(_p(c.f), _p(c.s), _p(c.phi), _p(c.codes), c.rows, c.cols, c.lines,
+                                      code_stride(c.lines), _p(A), c.cols)
     return A
 
 
@@ -192,17 +235,26 @@ def inverse_normalize(f, s, P):
 
 
 def add(x: Compressed, y: Compressed) -> Compressed:
-    assert (x.rows, x.cols) == (y.rows, y.cols)
-    z = Compressed.empty(x.rows, x.cols)
-    lib().oracle_add(x.nblk, _p(x.f), _p(x.s), _p(x.phi), _p(x.codes), _p(y.f), _p(y.s), _p(y.phi),
-                     _p(y.codes), _p(z.f), _p(z.s), _p(z.phi), _p(z.codes))
+    assert (x.rows, x.cols, x.lines) == (y.rows, y.cols, y.lines)
+    z = Compressed.empty(x.rows, x.cols, x.lines)
+    if x.lines == 2:
+        lib().oracle_add(x.nblk, _p(x.f), _p(x.s), _p(x.phi), _p(x.codes), _p(y.f), _p(y.s), _p(y.phi),
+                         _p(y.codes), _p(z.f), _p(z.s), _p(z.phi), _p(z.codes))
+    else:
+        lib().oracle_add_codes(x.nblk, kept_count(x.lines), code_stride(x.lines), _p(x.f), _p(x.s), _p(x.phi),
+                               _p(x.codes), _p(y.f), _p(y.s), _p(y.phi), _p(y.codes), _p(z.f), _p(z.s),
+                               _p(z.phi), _p(z.codes))
     return z
 
 
 def scale(x: Compressed, c: float) -> Compressed:
-    z = Compressed.empty(x.rows, x.cols)
-    lib().oracle_scale(x.nblk, _p(x.f), _p(x.s), _p(x.phi), _p(x.codes), float(c), _p(z.f), _p(z.s),
-                       _p(z.phi), _p(z.codes))
+    z = Compressed.empty(x.rows, x.cols, x.lines)
+    if x.lines == 2:
+        lib().oracle_scale(x.nblk, _p(x.f), _p(x.s), _p(x.phi), _p(x.codes), float(c), _p(z.f), _p(z.s),
+                           _p(z.phi), _p(z.codes))
+    else:
+        lib().oracle_scale_codes(x.nblk, kept_count(x.lines), code_stride(x.lines), _p(x.f), _p(x.s),
+                                 _p(x.phi), _p(x.codes), float(c), _p(z.f), _p(z.s), _p(z.phi), _p(z.codes))
     return z
 
 

@@ -18,6 +18,8 @@
  *   phi[nblk]      uint8, re-scaling factor
  *   codes[nblk*28] int8, the 28 kept DCT coefficients, kept positions
  *                  (rows 0-1 and columns 0-1) in row-major scan order
+ * (the tunable-rate functions *_lines / *_codes keep 16L - L^2 codes per
+ * block at a caller-given stride).
  * Block (I, J) of a rows x cols matrix has flat index I*(cols/8) + J.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math).
@@ -57,10 +59,13 @@ static double alpha(int i) { return i == 0 ? sqrt(1.0 / 8.0) : sqrt(1.0 / 4.0); 
 /* cos((2u+1) i pi / 16), the DCT-II kernel of Eq. eqdct. */
 static double dct_cos(int i, int u) { return cos((2.0 * u + 1.0) * i * M_PI / 16.0); }
 
-/* Is (i, j) one of the 28 coefficients kept by the quantization: the first
- * two lines and the first two columns (Section "Block Transform and
- * Quantization"). */
-static int kept(int i, int j) { return i < 2 || j < 2; }
+/* Is (i, j) one of the coefficients kept by the quantization.  The paper
+ * keeps the first two lines and the first two columns, 28 values (Section
+ * "Block Transform and Quantization").  The tunable rate its conclusion asks
+ * for is read as the number L of kept lines: rows 0..L-1 and columns
+ * 0..L-1, 16L - L^2 coefficients; L = 2 is the paper's scheme. */
+static int kept_lines(int i, int j, int lines) { return i < lines || j < lines; }
+int oracle_kept_count(int lines) { return 16 * lines - lines * lines; }
 
 /* ------------------------------------------------------------------------ */
 /* Compression stages for one 8x8 block (Section "Compression Scheme")       */
@@ -178,8 +183,18 @@ void oracle_dct(const double delta[64], double s, const double dprime[64], doubl
  * coefficients are truncated toward zero: C = trunc(phi * D) (Example 5:
  * 20 * D_01 = -51.996 is printed -51).  phi_x and code_x return the values
  * before truncation. */
+void oracle_quantize_lines(const double D[64], int lines, double *m_out, double *phi_x, int *phi_out,
+                           double *code_x, int8_t *codes);
+
 void oracle_quantize(const double D[64], double *m_out, double *phi_x, int *phi_out,
                      double code_x[NKEPT], int8_t codes[NKEPT])
+{
+    oracle_quantize_lines(D, 2, m_out, phi_x, phi_out, code_x, codes);
+}
+
+/* The same with the kept set of L lines (16L - L^2 codes, row-major scan). */
+void oracle_quantize_lines(const double D[64], int lines, double *m_out, double *phi_x, int *phi_out,
+                           double *code_x, int8_t *codes)
 {
     double m = 0.0;
     for (int e = 0; e < 64; ++e)
@@ -194,7 +209,7 @@ void oracle_quantize(const double D[64], double *m_out, double *phi_x, int *phi_
     int t = 0;
     for (int i = 0; i < NB; ++i)
         for (int j = 0; j < NB; ++j)
-            if (kept(i, j)) {
+            if (kept_lines(i, j, lines)) {
                 double x = (double)phi * D[i * NB + j];
                 code_x[t] = x;
                 codes[t] = (int8_t)trunc(x);
@@ -277,12 +292,16 @@ void oracle_inverse_normalize(double f, double s, const double P[64], double B[6
 
 /* Dequantization: the kept coefficients are C/phi, the discarded ones are
  * replaced by zeros (Section "Dot product", first paragraph). */
-void oracle_dequantize(int phi, const int8_t codes[NKEPT], double D[64])
+void oracle_dequantize_lines(int phi, int lines, const int8_t *codes, double D[64]);
+
+void oracle_dequantize(int phi, const int8_t codes[NKEPT], double D[64]) { oracle_dequantize_lines(phi, 2, codes, D); }
+
+void oracle_dequantize_lines(int phi, int lines, const int8_t *codes, double D[64])
 {
     int t = 0;
     for (int i = 0; i < NB; ++i)
         for (int j = 0; j < NB; ++j) {
-            if (kept(i, j)) {
+            if (kept_lines(i, j, lines)) {
                 D[i * NB + j] = (double)codes[t] / (double)phi;
                 ++t;
             } else {
@@ -292,12 +311,17 @@ void oracle_dequantize(int phi, const int8_t codes[NKEPT], double D[64])
 }
 
 /* Full decompression of one block: dequantize, IDCT, inverse normalization. */
-void oracle_decompress_block(double f, double s, int phi, const int8_t codes[NKEPT], double B[64])
+void oracle_decompress_block_lines(double f, double s, int phi, int lines, const int8_t *codes, double B[64])
 {
     double D[64], P[64];
-    oracle_dequantize(phi, codes, D);
+    oracle_dequantize_lines(phi, lines, codes, D);
     oracle_idct(D, P);
     oracle_inverse_normalize(f, s, P, B);
+}
+
+void oracle_decompress_block(double f, double s, int phi, const int8_t codes[NKEPT], double B[64])
+{
+    oracle_decompress_block_lines(f, s, phi, 2, codes, B);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -381,6 +405,53 @@ void oracle_decompress(const double *f, const double *s, const uint8_t *phi, con
         }
 }
 
+/* Tunable rate: compression and decompression with L kept lines.  The
+ * codes of block b start at byte b * cstride (cstride >= 16L - L^2; the
+ * bytes after the codes are left as the caller set them). */
+void oracle_compress_lines(const double *A, int64_t rows, int64_t cols, int64_t lda, int lines, int64_t cstride,
+                           double *f, double *s, uint8_t *phi, int8_t *codes, double *code_x, double *phi_x)
+{
+    int64_t nbc = cols / NB, nbr = rows / NB;
+    int n = oracle_kept_count(lines);
+    double M[64], delta[64], dprime[64], D[64], m, px, cx[64];
+    int K, p;
+    int8_t c[64];
+    for (int64_t I = 0; I < nbr; ++I)
+        for (int64_t J = 0; J < nbc; ++J) {
+            int64_t b = I * nbc + J;
+            double sb;
+            load_block(A, lda, I, J, M);
+            oracle_normalize(M, delta);
+            oracle_slope(delta, &K, &sb);
+            oracle_divide_by_slope(delta, sb, dprime);
+            oracle_dct(delta, sb, dprime, D);
+            oracle_quantize_lines(D, lines, &m, &px, &p, cx, c);
+            f[b] = M[0];
+            s[b] = sb;
+            phi[b] = (uint8_t)p;
+            memcpy(codes + b * cstride, c, (size_t)n);
+            if (code_x)
+                memcpy(code_x + b * n, cx, (size_t)n * sizeof(double));
+            if (phi_x)
+                phi_x[b] = px;
+        }
+}
+
+void oracle_decompress_lines(const double *f, const double *s, const uint8_t *phi, const int8_t *codes,
+                             int64_t rows, int64_t cols, int lines, int64_t cstride, double *A, int64_t lda)
+{
+    int64_t nbc = cols / NB, nbr = rows / NB;
+    double B[64];
+    for (int64_t I = 0; I < nbr; ++I)
+        for (int64_t J = 0; J < nbc; ++J) {
+            int64_t b = I * nbc + J;
+            oracle_decompress_block_lines(f[b], s[b], phi[b], lines, codes + b * cstride, B);
+            for (int i = 0; i < NB; ++i)
+                for (int j = 0; j < NB; ++j)
+                    A[(I * NB + i) * lda + J * NB + j] = B[i * NB + j];
+        }
+}
+
 /* Addition of compressed blocks, Algorithm 1, for nblk blocks.
  *   f = f1 + f2 ; s = s1 + s2
  *   phi = int8(phi1 phi2 / (phi1 + phi2))   (integer division, Eq. eq55)
@@ -390,10 +461,25 @@ void oracle_decompress(const double *f, const double *s, const uint8_t *phi, con
  * (|alpha_k| can exceed 1 when the slopes have opposite signs); phi is kept
  * at least 1 so that the result can be decompressed; when s1 + s2 = 0 the
  * alphas are undefined and the codes are 0 (the block is the constant f). */
+void oracle_add_codes(int64_t nblk, int ncodes, int64_t cstride,
+                      const double *f1, const double *s1, const uint8_t *phi1, const int8_t *c1,
+                      const double *f2, const double *s2, const uint8_t *phi2, const int8_t *c2,
+                      double *f, double *s, uint8_t *phi, int8_t *codes);
+
 void oracle_add(int64_t nblk,
                 const double *f1, const double *s1, const uint8_t *phi1, const int8_t *c1,
                 const double *f2, const double *s2, const uint8_t *phi2, const int8_t *c2,
                 double *f, double *s, uint8_t *phi, int8_t *codes)
+{
+    oracle_add_codes(nblk, NKEPT, NKEPT, f1, s1, phi1, c1, f2, s2, phi2, c2, f, s, phi, codes);
+}
+
+/* Algorithm 1 on blocks of ncodes codes stored cstride bytes apart (the
+ * tunable-rate records; Algorithm 1 treats every kept code the same way). */
+void oracle_add_codes(int64_t nblk, int ncodes, int64_t cstride,
+                      const double *f1, const double *s1, const uint8_t *phi1, const int8_t *c1,
+                      const double *f2, const double *s2, const uint8_t *phi2, const int8_t *c2,
+                      double *f, double *s, uint8_t *phi, int8_t *codes)
 {
     for (int64_t b = 0; b < nblk; ++b) {
         double fb = f1[b] + f2[b];
@@ -402,7 +488,7 @@ void oracle_add(int64_t nblk,
         int p = (p1 * p2) / (p1 + p2);
         if (p < 1)
             p = 1;
-        int8_t out[NKEPT];
+        int8_t out[64];
         if (sb == 0.0) {
             memset(out, 0, sizeof out);
         } else {
@@ -410,8 +496,8 @@ void oracle_add(int64_t nblk,
             double a2 = s2[b] / sb;
             double b1 = a1 / (double)p1 * (double)p;
             double b2 = a2 / (double)p2 * (double)p;
-            for (int t = 0; t < NKEPT; ++t) {
-                double x = b1 * (double)c1[b * NKEPT + t] + b2 * (double)c2[b * NKEPT + t];
+            for (int t = 0; t < ncodes; ++t) {
+                double x = b1 * (double)c1[b * cstride + t] + b2 * (double)c2[b * cstride + t];
                 double y = trunc(x);
                 if (y > 127.0)
                     y = 127.0;
@@ -423,21 +509,28 @@ void oracle_add(int64_t nblk,
         f[b] = fb;
         s[b] = sb;
         phi[b] = (uint8_t)p;
-        memcpy(codes + b * NKEPT, out, NKEPT);
+        memcpy(codes + b * cstride, out, (size_t)ncodes);
     }
 }
 
 /* Multiplication by a constant, Algorithm 2: f and s are multiplied by c,
  * phi and the codes are copied. */
-void oracle_scale(int64_t nblk, const double *f1, const double *s1, const uint8_t *phi1,
-                  const int8_t *c1, double c, double *f, double *s, uint8_t *phi, int8_t *codes)
+void oracle_scale_codes(int64_t nblk, int ncodes, int64_t cstride, const double *f1, const double *s1,
+                        const uint8_t *phi1, const int8_t *c1, double c, double *f, double *s, uint8_t *phi,
+                        int8_t *codes)
 {
     for (int64_t b = 0; b < nblk; ++b) {
         f[b] = f1[b] * c;
         s[b] = s1[b] * c;
         phi[b] = phi1[b];
-        memcpy(codes + b * NKEPT, c1 + b * NKEPT, NKEPT);
+        memcpy(codes + b * cstride, c1 + b * cstride, (size_t)ncodes);
     }
+}
+
+void oracle_scale(int64_t nblk, const double *f1, const double *s1, const uint8_t *phi1,
+                  const int8_t *c1, double c, double *f, double *s, uint8_t *phi, int8_t *codes)
+{
+    oracle_scale_codes(nblk, NKEPT, NKEPT, f1, s1, phi1, c1, c, f, s, phi, codes);
 }
 
 /* Decompress the listed rows of a compressed matrix into out[count][cols]
