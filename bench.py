@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=20000, help="requests of the serving mix (0 skips it)")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="HBM budget of the serving loop")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the 64x64 latency, cold-cache and 16384x16384 mixed-precision legs")
+                    help="skip the 64x64 latency, cold-cache, tunable-rate and 16384x16384 mixed-precision legs")
     return ap.parse_args()
 
 
@@ -304,6 +304,34 @@ def cold_ops_leg(blaz, torch, dA, dB, reps=20):
     return res
 
 
+def rates_leg(blaz, torch, dA, reps=10):
+    """The tunable rate on the first 8192^2 field: L kept lines of DCT
+    coefficients (L = 2 is the paper's scheme).  Per L: bits per block, the
+    median compress / decompress / add times, their GB/s over the bytes each
+    moves, and the relative Frobenius error of the decoded field."""
+    n = dA.shape[0]
+    norm = torch.linalg.norm(dA).item()
+    D = torch.empty_like(dA)
+    res = {}
+    for L in range(1, 9):
+        rec = 17 + blaz.code_stride(L)
+        x = blaz.compress(dA, lines=L)
+        z = blaz.BlazMatrix.empty(n, n, lines=L)
+        nblk = x.nblk
+        tc = median(timed_each(torch, lambda: blaz.compress(dA, out=x), reps))
+        td = median(timed_each(torch, lambda: blaz.decompress(x, out=D), reps))
+        ta = median(timed_each(torch, lambda: blaz.add(x, x, out=z), reps))
+        err = torch.linalg.norm(D - dA).item() / norm
+        res[str(L)] = {"bits_per_block": 8 * rec, "ratio": round(4096 / (8 * rec), 3),
+                       "compress_ms": round(tc, 4), "compress_GBps": round((BLOCK + rec) * nblk / tc / 1e6, 1),
+                       "decompress_ms": round(td, 4), "decompress_GBps": round((BLOCK + rec) * nblk / td / 1e6, 1),
+                       "add_ms": round(ta, 4), "add_GBps": round(3 * rec * nblk / ta / 1e6, 1),
+                       "rel_err": float(f"{err:.4e}")}
+        del x, z
+    del D
+    return res
+
+
 def mixed_leg(blaz, torch, workload_inputs, reps=10):
     """The 16384x16384 field compressed with the transform in FP64, FP32 and
     BF16x3.  Codes and phi are compared with the FP64 path's; errors of the
@@ -526,6 +554,9 @@ def main():
     if not args.no_extra:
         print("# cold/warm single-op leg", file=sys.stderr, flush=True)
         result["ops_single_launch"] = cold_ops_leg(blaz, torch, dA, dB)
+    if not args.no_extra:
+        print("# tunable-rate leg", file=sys.stderr, flush=True)
+        result["rates_8192"] = rates_leg(blaz, torch, dA)
     if args.serve_requests > 0:
         result["serving"] = serving_leg(torch, dA, dB, args.serve_requests, args.serve_budget_gib)
     del dA, dB

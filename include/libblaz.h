@@ -73,6 +73,15 @@ typedef enum {
  *               positions of the first two lines and first two columns in
  *               row-major order: (0,0..7), (1,0..7), (2,0), (2,1), ...,
  *               (7,0), (7,1).
+ * lines: the tunable rate the paper's conclusion asks for, as the number L
+ *   of kept lines (1..8): rows and columns 0..L-1 of the DCT, 16L - L^2
+ *   codes in row-major scan order, stored blaz_code_stride(L) bytes apart
+ *   (padded with zeros to whole 32-bit words).  0 means 2, the paper's
+ *   scheme above, so a zero-initialized descriptor is the paper's format.
+ *   Compression, decompression, add, sub, scale and matmul take any L (all
+ *   operands of one call share it); the dot products, the low-precision
+ *   transforms, the prediction side output and batching take L = 2 only
+ *   (BLAZ_ERR_UNSUPPORTED otherwise).
  * The caller owns the four arrays (device memory): f and s 8-byte aligned,
  * codes 4-byte aligned. */
 typedef struct blaz_matrix {
@@ -82,6 +91,7 @@ typedef struct blaz_matrix {
     double *s;
     uint8_t *phi;
     int8_t *codes;
+    int64_t lines;
 } blaz_matrix;
 
 /* Number of 8x8 blocks of a rows x cols matrix, or a negative blaz_status
@@ -90,6 +100,15 @@ int64_t blaz_block_count(int64_t rows, int64_t cols);
 
 /* Bytes of the compressed form (45 per block), 0 for an invalid shape. */
 size_t blaz_compressed_bytes(int64_t rows, int64_t cols);
+
+/* Bytes of the codes of one block with L kept lines (0 = 2):
+ * 4 * ceil((16L - L^2) / 4), i.e. 16, 28, 40, 48, 56, 60, 64, 64 for
+ * L = 1..8; a negative blaz_status for L outside 0..8. */
+int64_t blaz_code_stride(int64_t lines);
+
+/* Bytes of the compressed form with L kept lines: (17 + code stride) per
+ * block; 0 for an invalid shape or L. */
+size_t blaz_compressed_bytes_lines(int64_t rows, int64_t cols, int64_t lines);
 
 /* Compression (Section "Compression Scheme"): block splitting, normalization
  * (Eq. eqnorm), mean slope (Eqs. eqslope, eqslope2), prediction (Eq.

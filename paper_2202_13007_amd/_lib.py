@@ -21,7 +21,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 # Every symbol include/libblaz.h declares.
 EXPORTS = (
-    "blaz_block_count", "blaz_compressed_bytes", "blaz_compress", "blaz_decompress", "blaz_add",
+    "blaz_block_count", "blaz_compressed_bytes", "blaz_code_stride", "blaz_compressed_bytes_lines", "blaz_compress", "blaz_decompress", "blaz_add",
     "blaz_sub", "blaz_scale", "blaz_dot", "blaz_dot_dense", "blaz_matmul_workspace_bytes",
     "blaz_matmul", "blaz_matmul_tiled", "blaz_matmul_compressed_workspace_bytes", "blaz_matmul_compressed",
     "blaz_status_string", "blaz_batch_plan_bytes", "blaz_batch_plan", "blaz_batch_run",
@@ -29,7 +29,7 @@ EXPORTS = (
 
 
 class BlazMatrixC(ctypes.Structure):
-    """Mirror of ``blaz_matrix``: shape plus four device pointers."""
+    """Mirror of ``blaz_matrix``: shape, four device pointers, kept lines (0 = 2)."""
     _fields_ = [
         ("rows", ctypes.c_int64),
         ("cols", ctypes.c_int64),
@@ -37,6 +37,7 @@ class BlazMatrixC(ctypes.Structure):
         ("s", ctypes.c_void_p),
         ("phi", ctypes.c_void_p),
         ("codes", ctypes.c_void_p),
+        ("lines", ctypes.c_int64),
     ]
 
 
@@ -91,6 +92,8 @@ def lib():
     sig = {
         "blaz_block_count": ([I64, I64], I64),
         "blaz_compressed_bytes": ([I64, I64], ctypes.c_size_t),
+        "blaz_code_stride": ([I64], I64),
+        "blaz_compressed_bytes_lines": ([I64, I64, I64], ctypes.c_size_t),
         "blaz_compress": ([P, I64, M, I, P, P], I),
         "blaz_decompress": ([M, P, I64, P], I),
         "blaz_add": ([M, M, M, P], I),

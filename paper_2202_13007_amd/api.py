@@ -26,12 +26,21 @@ def _ptr(t: torch.Tensor | None):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def code_stride(lines: int = 2) -> int:
+    """Bytes of codes per block with L kept lines (28 for the paper's L = 2)."""
+    v = int(_lib.lib().blaz_code_stride(lines))
+    if v < 0:
+        raise _lib.BlazError(v, f"code_stride({lines})")
+    return v
+
+
 @dataclass
 class BlazMatrix:
     """A compressed rows x cols matrix on the device (45 bytes per 8x8 block).
 
-    f, s: float64 [nblk]; phi: uint8 [nblk]; codes: int8 [nblk, 28].
-    Block (I, J) is entry I*(cols/8) + J.
+    f, s: float64 [nblk]; phi: uint8 [nblk]; codes: int8 [nblk, code_stride(lines)]
+    (28 for the paper's scheme).  Block (I, J) is entry I*(cols/8) + J.
+    lines: kept lines L of DCT coefficients, the tunable rate (2: the paper's).
     """
     rows: int
     cols: int
@@ -39,6 +48,7 @@ class BlazMatrix:
     s: torch.Tensor
     phi: torch.Tensor
     codes: torch.Tensor
+    lines: int = 2
 
     @property
     def nblk(self) -> int:
@@ -49,7 +59,7 @@ class BlazMatrix:
         return self.f.nbytes + self.s.nbytes + self.phi.nbytes + self.codes.nbytes
 
     @staticmethod
-    def empty(rows: int, cols: int, device=None) -> "BlazMatrix":
+    def empty(rows: int, cols: int, device=None, lines: int = 2) -> "BlazMatrix":
         n = _lib.lib().blaz_block_count(rows, cols)
         if n < 0:
             raise _lib.BlazError(int(n), f"BlazMatrix.empty({rows}, {cols})")
@@ -58,11 +68,11 @@ class BlazMatrix:
                           torch.empty(n, dtype=torch.float64, device=dev),
                           torch.empty(n, dtype=torch.float64, device=dev),
                           torch.empty(n, dtype=torch.uint8, device=dev),
-                          torch.empty((n, NKEPT), dtype=torch.int8, device=dev))
+                          torch.empty((n, code_stride(lines)), dtype=torch.int8, device=dev), lines)
 
     def c(self) -> BlazMatrixC:
         return BlazMatrixC(self.rows, self.cols, self.f.data_ptr(), self.s.data_ptr(),
-                           self.phi.data_ptr(), self.codes.data_ptr())
+                           self.phi.data_ptr(), self.codes.data_ptr(), self.lines)
 
     def to_host(self):
         """(f, s, phi, codes) as numpy arrays (synchronizes)."""
@@ -70,13 +80,14 @@ class BlazMatrix:
                 self.codes.cpu().numpy())
 
     @staticmethod
-    def from_host(rows, cols, f, s, phi, codes, device=None) -> "BlazMatrix":
+    def from_host(rows, cols, f, s, phi, codes, device=None, lines: int = 2) -> "BlazMatrix":
         dev = torch.device("cuda") if device is None else torch.device(device)
         return BlazMatrix(rows, cols,
                           torch.as_tensor(f, dtype=torch.float64).to(dev).contiguous(),
                           torch.as_tensor(s, dtype=torch.float64).to(dev).contiguous(),
                           torch.as_tensor(phi, dtype=torch.uint8).to(dev).contiguous(),
-                          torch.as_tensor(codes, dtype=torch.int8).reshape(-1, NKEPT).to(dev).contiguous())
+                          torch.as_tensor(codes, dtype=torch.int8).reshape(-1, code_stride(lines)).to(dev)
+                          .contiguous(), lines)
 
 
 def _check_dense(A: torch.Tensor, what: str):
@@ -85,12 +96,13 @@ def _check_dense(A: torch.Tensor, what: str):
 
 
 def compress(A: torch.Tensor, out: BlazMatrix | None = None, prec: str = "fp64",
-             psi: torch.Tensor | None = None) -> BlazMatrix:
-    """Compress a float64 matrix (rows, cols multiples of 8)."""
+             psi: torch.Tensor | None = None, lines: int = 2) -> BlazMatrix:
+    """Compress a float64 matrix (rows, cols multiples of 8); ``lines`` sets
+    the rate of a new output (ignored when ``out`` is given)."""
     _check_dense(A, "compress")
     rows, cols = A.shape
     if out is None:
-        out = BlazMatrix.empty(rows, cols, A.device)
+        out = BlazMatrix.empty(rows, cols, A.device, lines)
     m = out.c()
     check(_lib.lib().blaz_compress(_ptr(A), A.stride(0), ctypes.byref(m), _lib.PREC[prec], _ptr(psi),
                                    _stream()), "blaz_compress")
@@ -107,14 +119,14 @@ def decompress(x: BlazMatrix, out: torch.Tensor | None = None) -> torch.Tensor:
 
 
 def add(x: BlazMatrix, y: BlazMatrix, out: BlazMatrix | None = None) -> BlazMatrix:
-    out = BlazMatrix.empty(x.rows, x.cols, x.f.device) if out is None else out
+    out = BlazMatrix.empty(x.rows, x.cols, x.f.device, x.lines) if out is None else out
     mx, my, mz = x.c(), y.c(), out.c()
     check(_lib.lib().blaz_add(ctypes.byref(mx), ctypes.byref(my), ctypes.byref(mz), _stream()), "blaz_add")
     return out
 
 
 def sub(x: BlazMatrix, y: BlazMatrix, out: BlazMatrix | None = None) -> BlazMatrix:
-    out = BlazMatrix.empty(x.rows, x.cols, x.f.device) if out is None else out
+    out = BlazMatrix.empty(x.rows, x.cols, x.f.device, x.lines) if out is None else out
     mx, my, mz = x.c(), y.c(), out.c()
     check(_lib.lib().blaz_sub(ctypes.byref(mx), ctypes.byref(my), ctypes.byref(mz), _stream()), "blaz_sub")
     return out
@@ -122,7 +134,7 @@ def sub(x: BlazMatrix, y: BlazMatrix, out: BlazMatrix | None = None) -> BlazMatr
 
 def scale(x: BlazMatrix, c: float, out: BlazMatrix | None = None) -> BlazMatrix:
     """out = c * x; pass out=x for the in-place form."""
-    out = BlazMatrix.empty(x.rows, x.cols, x.f.device) if out is None else out
+    out = BlazMatrix.empty(x.rows, x.cols, x.f.device, x.lines) if out is None else out
     mx, mz = x.c(), out.c()
     check(_lib.lib().blaz_scale(ctypes.byref(mx), float(c), ctypes.byref(mz), _stream()), "blaz_scale")
     return out

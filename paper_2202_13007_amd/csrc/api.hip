@@ -26,6 +26,18 @@ BLAZ_API size_t blaz_compressed_bytes(int64_t rows, int64_t cols)
     return (size_t)((rows / 8) * (cols / 8) * kRecordBytes);
 }
 
+BLAZ_API int64_t blaz_code_stride(int64_t lines)
+{
+    if (!valid_lines(lines)) return BLAZ_ERR_ARG;
+    return code_stride(lines == 0 ? 2 : (int)lines);
+}
+
+BLAZ_API size_t blaz_compressed_bytes_lines(int64_t rows, int64_t cols, int64_t lines)
+{
+    if (check_shape(rows, cols) != BLAZ_OK || !valid_lines(lines)) return 0;
+    return (size_t)((rows / 8) * (cols / 8) * (17 + code_stride(lines == 0 ? 2 : (int)lines)));
+}
+
 BLAZ_API blaz_status blaz_compress(const double* A, int64_t lda, const blaz_matrix* out, blaz_precision prec,
                                    uint8_t* psi, hipStream_t stream)
 {

@@ -216,6 +216,13 @@ BLAZ_API blaz_status blaz_batch_plan(const blaz_batch_item* items, int64_t n_ite
             default:
                 st = BLAZ_ERR_ARG;
         }
+        // batches carry the paper's records (two kept lines) only
+        if (st == BLAZ_OK && !empty) {
+            const bool uses_y = it.op == BLAZ_OP_ADD || it.op == BLAZ_OP_SUB || it.op == BLAZ_OP_DOT;
+            const bool uses_z = it.op == BLAZ_OP_ADD || it.op == BLAZ_OP_SUB || it.op == BLAZ_OP_SCALE;
+            if (lines_of(it.x) != 2 || (uses_y && lines_of(it.y) != 2) || (uses_z && lines_of(it.z) != 2))
+                st = BLAZ_ERR_UNSUPPORTED;
+        }
         // batched compress / decompress use the LDS-staged row path only
         if (st == BLAZ_OK && !empty && (it.op == BLAZ_OP_COMPRESS || it.op == BLAZ_OP_DECOMPRESS) &&
             (!aligned(it.dense, 16) || it.ld % 2 != 0))

@@ -254,6 +254,48 @@ __device__ __forceinline__ void quantize_store(const double D[64], const SlopeOu
     }
 }
 
+// quantize_store for L kept lines: the same phi and truncations, the codes
+// of the L-line mask, KeptLines<L>::kWords dwords per block.
+template <int L>
+__device__ __forceinline__ void quantize_store_lines(const double D[64], const SlopeOut& so_, int64_t nblk,
+                                                     int64_t wave_base, int lane, void* tile, double* fo,
+                                                     double* so, uint8_t* phio, uint32_t* codes)
+{
+    using K = KeptLines<L>;
+    double m = 0.0;
+#pragma unroll
+    for (int e = 0; e < 64; ++e) m = fmax(m, fabs(D[e]));
+    const double px = 127.0 / m;  // +inf when m == 0
+    const int phi = px < 255.0 ? (int)px : 255;
+    const double phid = (double)phi;
+    uint32_t w[K::kWords];
+#pragma unroll
+    for (int q = 0; q < K::kWords; ++q) w[q] = 0;
+#pragma unroll
+    for (int t = 0; t < K::kCount; ++t) {
+        const int c = (int)(phid * D[K::pos(t)]);  // truncation toward zero
+        w[t / 4] |= ((uint32_t)c & 0xffu) << (8 * (t % 4));
+    }
+    const int64_t b = wave_base + lane;
+    if (b < nblk) {
+        fo[b] = so_.f;
+        so[b] = so_.s;
+        phio[b] = (uint8_t)phi;
+    }
+    uint32_t* ct = reinterpret_cast<uint32_t*>(tile);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K::kWords; ++q) ct[lane * K::kWords + q] = w[q];
+    __syncthreads();
+    const int64_t nwords = (nblk - wave_base < kWave ? nblk - wave_base : kWave) * K::kWords;
+    uint32_t* cdst = codes + wave_base * K::kWords;
+#pragma unroll
+    for (int k = 0; k < K::kWords; ++k) {
+        const int idx = lane + kWave * k;
+        if (idx < nwords) cdst[idx] = ct[idx];
+    }
+}
+
 // Output forms of the decompression: binary64 (the plain method), and the
 // operand forms of the low-precision contractions in blaz_matmul: FP32, or
 // BF16 hi + lo with hi = bf16(x), lo = bf16(x - hi).
@@ -294,7 +336,7 @@ struct OutBF16Split {
 
 // Compression (all stages binary64) of the blocks wave_base .. wave_base+63
 // (one per lane) of A; tile is the wave's LDS staging area.
-template <bool kVec, bool kPsi>
+template <bool kVec, bool kPsi, int L = 2>
 __device__ __forceinline__ void compress_wave(const double* __restrict__ A, int64_t lda, int64_t nbc, int64_t nblk,
                                               double* __restrict__ fo, double* __restrict__ so,
                                               uint8_t* __restrict__ phio, uint32_t* __restrict__ codes,
@@ -313,13 +355,16 @@ __device__ __forceinline__ void compress_wave(const double* __restrict__ A, int6
     for (int v = 0; v < 8; ++v) dct8<8, 8>(x + v, x + v);
     x[0] = so_.dc;
 
-    quantize_store(x, so_, nblk, wave_base, lane, tile, fo, so, phio, codes);
+    if constexpr (L == 2)
+        quantize_store(x, so_, nblk, wave_base, lane, tile, fo, so, phio, codes);
+    else
+        quantize_store_lines<L>(x, so_, nblk, wave_base, lane, tile, fo, so, phio, codes);
 }
 
 // Decompression of the blocks wave_base .. wave_base+63 (one per lane) of a
 // compressed matrix into `out` (leading dimension lda); tile is the wave's
 // LDS staging area (kWave * kSlot doubles).
-template <bool kVec, typename Out>
+template <bool kVec, typename Out, int L = 2>
 __device__ __forceinline__ void decompress_wave(const double* __restrict__ f, const double* __restrict__ s,
                                                 const uint8_t* __restrict__ phi, const uint32_t* __restrict__ codes,
                                                 int64_t nbc, int64_t nblk, Out out, int64_t lda, int64_t wave_base,
@@ -328,19 +373,21 @@ __device__ __forceinline__ void decompress_wave(const double* __restrict__ f, co
     const int64_t b = wave_base + lane;
     const bool valid = b < nblk;
 
-    // The wave's codes: consecutive dwords into LDS, then each lane's 7.
+    // The wave's codes: consecutive dwords into LDS, then each lane's own
+    // (7 for the paper's scheme, KeptLines<L>::kWords in general).
+    constexpr int kW = KeptLines<L>::kWords;
     uint32_t* ct = reinterpret_cast<uint32_t*>(tile);
-    const int64_t nwords = (nblk - wave_base < kWave ? nblk - wave_base : kWave) * kCodeWords;
-    const uint32_t* csrc = codes + wave_base * kCodeWords;
+    const int64_t nwords = (nblk - wave_base < kWave ? nblk - wave_base : kWave) * kW;
+    const uint32_t* csrc = codes + wave_base * kW;
 #pragma unroll
-    for (int k = 0; k < kCodeWords; ++k) {
+    for (int k = 0; k < kW; ++k) {
         const int idx = lane + kWave * k;
         if (idx < nwords) ct[idx] = csrc[idx];
     }
     __syncthreads();
-    uint32_t w[kCodeWords];
+    uint32_t w[kW];
 #pragma unroll
-    for (int q = 0; q < kCodeWords; ++q) w[q] = ct[lane * kCodeWords + q];
+    for (int q = 0; q < kW; ++q) w[q] = ct[lane * kW + q];
     __syncthreads();
 
     const double fb = valid ? f[b] : 0.0;
@@ -348,10 +395,16 @@ __device__ __forceinline__ void decompress_wave(const double* __restrict__ f, co
     const double pb = valid ? (double)phi[b] : 1.0;
     // Dhat = C / phi at the kept positions (zero elsewhere); the slope factor
     // of Eq. eqbbb is folded in by linearity of the inverse DCT.
-    double coef[kKept];
-    unpack_codes(w, sb / pb, coef);
     double x[64];
-    inverse_transform(coef, x);
+    if constexpr (L == 2) {
+        double coef[kKept];
+        unpack_codes(w, sb / pb, coef);
+        inverse_transform(coef, x);
+    } else {
+        double coef[KeptLines<L>::kCount];
+        unpack_codes_lines<L>(w, sb / pb, coef);
+        inverse_transform_lines<L>(coef, x);
+    }
     inverse_normalize(fb, x);
 
     if constexpr (kVec) {

@@ -122,6 +122,27 @@ __host__ __device__ constexpr int kept_index(int i, int j)
     return i < 2 ? i * 8 + j : (j < 2 ? 16 + (i - 2) * 2 + j : -1);
 }
 
+// The tunable rate: L kept lines (rows and columns 0..L-1 of the DCT),
+// 16L - L^2 codes in row-major scan order, padded to whole dwords.  L = 2 is
+// the paper's scheme (kKept, kCodeWords, kept_row/kept_col/kept_index).
+template <int L>
+struct KeptLines {
+    static_assert(L >= 1 && L <= 8, "1 to 8 kept lines");
+    static constexpr int kCount = 16 * L - L * L;
+    static constexpr int kWords = (kCount + 3) / 4;
+    // Position i*8+j of kept coefficient t: rows 0..L-1 are whole (8 each),
+    // the rows below keep their first L columns.
+    __host__ __device__ static constexpr int pos(int t)
+    {
+        return t < 8 * L ? t : (L + (t - 8 * L) / L) * 8 + (t - 8 * L) % L;
+    }
+    // Index t of position (i, j), or -1 if it is discarded.
+    __host__ __device__ static constexpr int index(int i, int j)
+    {
+        return i < L ? i * 8 + j : (j < L ? 8 * L + (i - L) * L + j : -1);
+    }
+};
+
 // Dequantized coefficients of one block, already multiplied by the slope:
 // coef[t] = codes[t] * (s / phi).  The 28 codes arrive as 7 little-endian dwords.
 __device__ __forceinline__ void unpack_codes(const uint32_t w[kCodeWords], double scale, double coef[kKept])
@@ -129,6 +150,16 @@ __device__ __forceinline__ void unpack_codes(const uint32_t w[kCodeWords], doubl
 #pragma unroll
     for (int t = 0; t < kKept; ++t) {
         const int32_t c = (int32_t)(w[t / 4] << (24 - 8 * (t % 4))) >> 24;  // sign-extend byte t%4
+        coef[t] = (double)c * scale;
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void unpack_codes_lines(const uint32_t* w, double scale, double* coef)
+{
+#pragma unroll
+    for (int t = 0; t < KeptLines<L>::kCount; ++t) {
+        const int32_t c = (int32_t)(w[t / 4] << (24 - 8 * (t % 4))) >> 24;
         coef[t] = (double)c * scale;
     }
 }
@@ -153,6 +184,34 @@ __device__ __forceinline__ void inverse_transform(const double coef[kKept], doub
     }
 #pragma unroll
     for (int j = 2; j < 8; ++j) idct8_two<8>(coef[kept_index(0, j)], coef[kept_index(1, j)], out + j);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) idct8<1, 1>(out + u * 8, out + u * 8);
+}
+
+// The same for L kept lines: columns 0..L-1 hold 8 coefficients each, the
+// other columns only their first L rows.
+template <int L>
+__device__ __forceinline__ void inverse_transform_lines(const double* coef, double out[64])
+{
+    using K = KeptLines<L>;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        double col[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) col[i] = K::index(i, j) >= 0 ? coef[K::index(i, j)] : 0.0;
+        if (j < L) {
+            idct8<1, 8>(col, out + j);
+        } else {
+#pragma clang fp contract(fast)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                double acc = 0.0;
+#pragma unroll
+                for (int i = 0; i < L; ++i) acc += dct_t(i, u) * col[i];
+                out[u * 8 + j] = acc;
+            }
+        }
+    }
 #pragma unroll
     for (int u = 0; u < 8; ++u) idct8<1, 1>(out + u * 8, out + u * 8);
 }

@@ -5,10 +5,30 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "libblaz.h"
 
 namespace blaz {
 namespace detail {
+
+// Calls f(std::integral_constant<int, L>) for the kept lines L of a
+// descriptor (0 stands for the paper's 2), so that every rate gets its own
+// kernel instance.
+template <typename F>
+inline hipError_t dispatch_lines(const blaz_matrix& m, F&& f)
+{
+    switch (m.lines) {
+        case 1: return f(std::integral_constant<int, 1>{});
+        case 3: return f(std::integral_constant<int, 3>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 5: return f(std::integral_constant<int, 5>{});
+        case 6: return f(std::integral_constant<int, 6>{});
+        case 7: return f(std::integral_constant<int, 7>{});
+        case 8: return f(std::integral_constant<int, 8>{});
+        default: return f(std::integral_constant<int, 2>{});
+    }
+}
 
 // Compute units of the current device (cached per device; 0 on error).
 int device_cu_count();

@@ -12,7 +12,9 @@
 namespace blaz {
 
 // z = x + y (or x - y) for block b.  z may alias x or y: every input of the
-// block is read before it is written.
+// block is read before it is written.  L: kept lines of the records (the
+// paper's 2 by default); pad bytes of the result are zero.
+template <int L = 2>
 __device__ __forceinline__ void add_block(int64_t b, bool neg_y, const double* f1, const double* s1,
                                           const uint8_t* phi1, const uint32_t* c1, const double* f2,
                                           const double* s2, const uint8_t* phi2, const uint32_t* c2, double* fo,
@@ -31,11 +33,12 @@ __device__ __forceinline__ void add_block(int64_t b, bool neg_y, const double* f
     int p = p1 + p2 > 0 ? (p1 * p2) / (p1 + p2) : 1;
     p = p < 1 ? 1 : p;
 
-    uint32_t wx[kCodeWords], wy[kCodeWords], wo[kCodeWords];
+    constexpr int kW = KeptLines<L>::kWords, kN = KeptLines<L>::kCount;
+    uint32_t wx[kW], wy[kW], wo[kW];
 #pragma unroll
-    for (int q = 0; q < kCodeWords; ++q) {
-        wx[q] = c1[b * kCodeWords + q];
-        wy[q] = c2[b * kCodeWords + q];
+    for (int q = 0; q < kW; ++q) {
+        wx[q] = c1[b * kW + q];
+        wy[q] = c2[b * kW + q];
         wo[q] = 0;
     }
     if (s != 0.0) {
@@ -48,7 +51,7 @@ __device__ __forceinline__ void add_block(int64_t b, bool neg_y, const double* f
         // Two products then one sum, never fused (the library is built with
         // -ffp-contract=off), so the result is reproducible bit for bit.
 #pragma unroll
-        for (int t = 0; t < kKept; ++t) {
+        for (int t = 0; t < kN; ++t) {
             const int32_t cx = (int32_t)(wx[t / 4] << (24 - 8 * (t % 4))) >> 24;
             const int32_t cy = (int32_t)(wy[t / 4] << (24 - 8 * (t % 4))) >> 24;
             const double v = b1 * (double)cx + b2 * (double)cy;
@@ -60,7 +63,7 @@ __device__ __forceinline__ void add_block(int64_t b, bool neg_y, const double* f
     so[b] = s;
     phio[b] = (uint8_t)p;
 #pragma unroll
-    for (int q = 0; q < kCodeWords; ++q) co[b * kCodeWords + q] = wo[q];
+    for (int q = 0; q < kW; ++q) co[b * kW + q] = wo[q];
 }
 
 // z = c x for block b (Algorithm 2): f and s scaled, phi and codes copied

@@ -10,7 +10,7 @@
 namespace blaz {
 namespace validate {
 
-constexpr int64_t kRecordBytes = 45;  // f (8) + s (8) + phi (1) + 28 codes
+constexpr int64_t kRecordBytes = 45;  // f (8) + s (8) + phi (1) + 28 codes (two kept lines)
 constexpr int64_t kMaxDots = int64_t(1) << 32;  // eight dot products per workgroup: grid < 2^32
 
 inline bool aligned(const void* p, uintptr_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
@@ -26,11 +26,18 @@ inline blaz_status check_shape(int64_t rows, int64_t cols)
 
 inline int64_t nblocks(const blaz_matrix& m) { return (m.rows / 8) * (m.cols / 8); }
 
-// A descriptor is valid if its shape is and, when it holds blocks, its four
-// arrays are present and aligned.
+// Kept lines L of a descriptor (0 stands for the paper's 2) and the bytes of
+// codes per block: 16L - L^2 codes padded to whole dwords.
+inline int lines_of(const blaz_matrix& m) { return m.lines == 0 ? 2 : (int)m.lines; }
+inline bool valid_lines(int64_t lines) { return lines >= 0 && lines <= 8; }
+inline int64_t code_stride(int lines) { return 4 * ((16 * lines - lines * lines + 3) / 4); }
+
+// A descriptor is valid if its shape and kept lines are and, when it holds
+// blocks, its four arrays are present and aligned.
 inline blaz_status check_matrix(const blaz_matrix* m)
 {
     if (!m) return BLAZ_ERR_NULL;
+    if (!valid_lines(m->lines)) return BLAZ_ERR_ARG;
     if (blaz_status st = check_shape(m->rows, m->cols)) return st;
     if (nblocks(*m) == 0) return BLAZ_OK;
     if (!m->f || !m->s || !m->phi || !m->codes) return BLAZ_ERR_NULL;
@@ -55,7 +62,7 @@ inline void ranges(const blaz_matrix& m, Range r[4])
     r[0] = span(m.f, 8 * n);
     r[1] = span(m.s, 8 * n);
     r[2] = span(m.phi, n);
-    r[3] = span(m.codes, 28 * n);
+    r[3] = span(m.codes, code_stride(lines_of(m)) * n);
 }
 
 inline bool overlaps_matrix(Range a, const blaz_matrix& m)
@@ -97,6 +104,7 @@ inline blaz_status validate_compress(const double* A, int64_t lda, const blaz_ma
     *empty = true;
     if (blaz_status st = check_matrix(out)) return st;
     if (prec != BLAZ_PREC_FP64 && prec != BLAZ_PREC_FP32 && prec != BLAZ_PREC_BF16X3) return BLAZ_ERR_ARG;
+    if (lines_of(*out) != 2 && (prec != BLAZ_PREC_FP64 || psi)) return BLAZ_ERR_UNSUPPORTED;
     const int64_t nblk = nblocks(*out);
     if (nblk == 0) return BLAZ_OK;
     if (!A) return BLAZ_ERR_NULL;
@@ -127,7 +135,8 @@ inline blaz_status validate_add(const blaz_matrix* x, const blaz_matrix* y, cons
     *empty = true;
     for (const blaz_matrix* m : {x, y, z})
         if (blaz_status st = check_matrix(m)) return st;
-    if (x->rows != y->rows || x->cols != y->cols || x->rows != z->rows || x->cols != z->cols)
+    if (x->rows != y->rows || x->cols != y->cols || x->rows != z->rows || x->cols != z->cols ||
+        lines_of(*x) != lines_of(*y) || lines_of(*x) != lines_of(*z))
         return BLAZ_ERR_MISMATCH;
     if (nblocks(*x) == 0) return BLAZ_OK;
     if (!same_or_disjoint(*z, *x) || !same_or_disjoint(*z, *y)) return BLAZ_ERR_ARG;
@@ -140,7 +149,7 @@ inline blaz_status validate_scale(const blaz_matrix* x, const blaz_matrix* z, bo
     *empty = true;
     for (const blaz_matrix* m : {x, z})
         if (blaz_status st = check_matrix(m)) return st;
-    if (x->rows != z->rows || x->cols != z->cols) return BLAZ_ERR_MISMATCH;
+    if (x->rows != z->rows || x->cols != z->cols || lines_of(*x) != lines_of(*z)) return BLAZ_ERR_MISMATCH;
     if (nblocks(*x) == 0) return BLAZ_OK;
     if (!same_or_disjoint(*z, *x)) return BLAZ_ERR_ARG;
     *empty = false;
@@ -154,6 +163,7 @@ inline blaz_status validate_dot(const blaz_matrix* x, const int64_t* xrow, const
     for (const blaz_matrix* m : {x, y})
         if (blaz_status st = check_matrix(m)) return st;
     if (x->cols != y->rows) return BLAZ_ERR_MISMATCH;
+    if (lines_of(*x) != 2 || lines_of(*y) != 2) return BLAZ_ERR_UNSUPPORTED;
     if (count < 0 || count > kMaxDots) return BLAZ_ERR_ARG;
     if (count == 0) return BLAZ_OK;
     if (!xrow || !ycol || !out) return BLAZ_ERR_NULL;
@@ -168,6 +178,7 @@ inline blaz_status validate_dot_dense(const blaz_matrix* x, const int64_t* xrow,
 {
     *empty = true;
     if (blaz_status st = check_matrix(x)) return st;
+    if (lines_of(*x) != 2) return BLAZ_ERR_UNSUPPORTED;
     if (count < 0 || count > kMaxDots || ldv < 0) return BLAZ_ERR_ARG;
     if (ldv != 0 && ldv < x->cols) return BLAZ_ERR_SHAPE;
     if (count == 0) return BLAZ_OK;

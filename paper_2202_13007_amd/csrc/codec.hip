@@ -15,7 +15,7 @@
 
 namespace blaz {
 
-template <bool kVec, bool kPsi>
+template <bool kVec, bool kPsi, int L = 2>
 __global__ __launch_bounds__(kWave) void compress_f64_kernel(const double* __restrict__ A, int64_t lda,
                                                              int64_t nbc, int64_t nblk, double* __restrict__ fo,
                                                              double* __restrict__ so, uint8_t* __restrict__ phio,
@@ -23,18 +23,19 @@ __global__ __launch_bounds__(kWave) void compress_f64_kernel(const double* __res
                                                              uint8_t* __restrict__ psi)
 {
     __shared__ __align__(16) double tile[kWave * kSlot];
-    compress_wave<kVec, kPsi>(A, lda, nbc, nblk, fo, so, phio, codes, psi, (int64_t)blockIdx.x * kWave,
-                              (int)threadIdx.x, tile);
+    compress_wave<kVec, kPsi, L>(A, lda, nbc, nblk, fo, so, phio, codes, psi, (int64_t)blockIdx.x * kWave,
+                                 (int)threadIdx.x, tile);
 }
 
-template <bool kVec, typename Out>
+template <bool kVec, typename Out, int L = 2>
 __global__ __launch_bounds__(kWave) void decompress_kernel(const double* __restrict__ f, const double* __restrict__ s,
                                                            const uint8_t* __restrict__ phi,
                                                            const uint32_t* __restrict__ codes, int64_t nbc,
                                                            int64_t nblk, Out out, int64_t lda)
 {
     __shared__ __align__(16) double tile[kWave * kSlot];
-    decompress_wave<kVec>(f, s, phi, codes, nbc, nblk, out, lda, (int64_t)blockIdx.x * kWave, (int)threadIdx.x, tile);
+    decompress_wave<kVec, Out, L>(f, s, phi, codes, nbc, nblk, out, lda, (int64_t)blockIdx.x * kWave,
+                                  (int)threadIdx.x, tile);
 }
 
 namespace detail {
@@ -48,6 +49,17 @@ hipError_t launch_compress_f64(const double* A, int64_t lda, const blaz_matrix& 
     const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % 2 == 0);
     const unsigned grid = grid_for(nblk);
     auto* cw = reinterpret_cast<uint32_t*>(m.codes);
+    if (m.lines != 0 && m.lines != 2)  // other rates: no prediction side output (rejected before)
+        return dispatch_lines(m, [&](auto lc) {
+            constexpr int L = decltype(lc)::value;
+            if (vec)
+                compress_f64_kernel<true, false, L><<<grid, kWave, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw,
+                                                                           nullptr);
+            else
+                compress_f64_kernel<false, false, L><<<grid, kWave, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi,
+                                                                            cw, nullptr);
+            return hipGetLastError();
+        });
     if (vec && psi)
         compress_f64_kernel<true, true><<<grid, kWave, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw, psi);
     else if (vec)
@@ -66,11 +78,14 @@ static hipError_t launch_decompress_to(const blaz_matrix& m, Out out, bool vec, 
     const int64_t nblk = (m.rows / 8) * nbc;
     const unsigned grid = grid_for(nblk);
     const auto* cw = reinterpret_cast<const uint32_t*>(m.codes);
-    if (vec)
-        decompress_kernel<true><<<grid, kWave, 0, st>>>(m.f, m.s, m.phi, cw, nbc, nblk, out, lda);
-    else
-        decompress_kernel<false><<<grid, kWave, 0, st>>>(m.f, m.s, m.phi, cw, nbc, nblk, out, lda);
-    return hipGetLastError();
+    return dispatch_lines(m, [&](auto lc) {
+        constexpr int L = decltype(lc)::value;
+        if (vec)
+            decompress_kernel<true, Out, L><<<grid, kWave, 0, st>>>(m.f, m.s, m.phi, cw, nbc, nblk, out, lda);
+        else
+            decompress_kernel<false, Out, L><<<grid, kWave, 0, st>>>(m.f, m.s, m.phi, cw, nbc, nblk, out, lda);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_decompress(const blaz_matrix& m, double* A, int64_t lda, hipStream_t st)

@@ -14,7 +14,7 @@
 
 namespace blaz {
 
-template <bool kNegY>
+template <bool kNegY, int L>
 __global__ __launch_bounds__(256) void add_kernel(const double* f1, const double* s1, const uint8_t* phi1,
                                                   const uint32_t* c1, const double* f2, const double* s2,
                                                   const uint8_t* phi2, const uint32_t* c2, int64_t nblk, double* fo,
@@ -22,7 +22,7 @@ __global__ __launch_bounds__(256) void add_kernel(const double* f1, const double
 {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nblk) return;
-    add_block(b, kNegY, f1, s1, phi1, c1, f2, s2, phi2, c2, fo, so, phio, co);
+    add_block<L>(b, kNegY, f1, s1, phi1, c1, f2, s2, phi2, c2, fo, so, phio, co);
 }
 
 // Algorithm 2 in place: only f and s change.
@@ -34,7 +34,9 @@ __global__ __launch_bounds__(256) void scale_inplace_kernel(double* f, double* s
     s[b] = s[b] * c;
 }
 
-// Algorithm 2 out of place: f and s times c, phi and the codes copied.
+// Algorithm 2 out of place: f and s times c, phi and the codes copied
+// (kW dwords of codes per block).
+template <int kW>
 __global__ __launch_bounds__(256) void scale_kernel(const double* __restrict__ f1, const double* __restrict__ s1,
                                                     const uint8_t* phi1,
                                                     const uint32_t* __restrict__ c1, double c, int64_t nblk,
@@ -47,12 +49,12 @@ __global__ __launch_bounds__(256) void scale_kernel(const double* __restrict__ f
         so[b] = s1[b] * c;
         phio[b] = phi1[b];
     }
-    // The codes are copied as one flat dword stream (7 dwords per block) so
+    // The codes are copied as one flat dword stream (kW dwords per block) so
     // that consecutive lanes touch consecutive dwords.
-    const int64_t total = nblk * kCodeWords;
-    const int64_t base = (int64_t)blockIdx.x * blockDim.x * kCodeWords + threadIdx.x;
+    const int64_t total = nblk * kW;
+    const int64_t base = (int64_t)blockIdx.x * blockDim.x * kW + threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < kCodeWords; ++q) {
+    for (int q = 0; q < kW; ++q) {
         const int64_t i = base + (int64_t)q * blockDim.x;
         if (i < total) co[i] = c1[i];
     }
@@ -66,13 +68,16 @@ hipError_t launch_add(const blaz_matrix& x, const blaz_matrix& y, const blaz_mat
     const int64_t nblk = (x.rows / 8) * (x.cols / 8);
     const unsigned grid = (unsigned)((nblk + 255) / 256);
     auto cw = [](const blaz_matrix& m) { return reinterpret_cast<uint32_t*>(m.codes); };
-    if (negate_y)
-        add_kernel<true><<<grid, 256, 0, st>>>(x.f, x.s, x.phi, cw(x), y.f, y.s, y.phi, cw(y), nblk, z.f, z.s,
-                                               z.phi, cw(z));
-    else
-        add_kernel<false><<<grid, 256, 0, st>>>(x.f, x.s, x.phi, cw(x), y.f, y.s, y.phi, cw(y), nblk, z.f, z.s,
-                                                z.phi, cw(z));
-    return hipGetLastError();
+    return dispatch_lines(x, [&](auto lc) {
+        constexpr int L = decltype(lc)::value;
+        if (negate_y)
+            add_kernel<true, L><<<grid, 256, 0, st>>>(x.f, x.s, x.phi, cw(x), y.f, y.s, y.phi, cw(y), nblk, z.f,
+                                                      z.s, z.phi, cw(z));
+        else
+            add_kernel<false, L><<<grid, 256, 0, st>>>(x.f, x.s, x.phi, cw(x), y.f, y.s, y.phi, cw(y), nblk, z.f,
+                                                       z.s, z.phi, cw(z));
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_scale(const blaz_matrix& x, double c, const blaz_matrix& z, hipStream_t st)
@@ -82,8 +87,12 @@ hipError_t launch_scale(const blaz_matrix& x, double c, const blaz_matrix& z, hi
     if (z.f == x.f && z.s == x.s && z.phi == x.phi && z.codes == x.codes)
         scale_inplace_kernel<<<grid, 256, 0, st>>>(z.f, z.s, c, nblk);
     else
-        scale_kernel<<<grid, 256, 0, st>>>(x.f, x.s, x.phi, reinterpret_cast<const uint32_t*>(x.codes), c, nblk,
-                                           z.f, z.s, z.phi, reinterpret_cast<uint32_t*>(z.codes));
+        return dispatch_lines(x, [&](auto lc) {
+            scale_kernel<KeptLines<decltype(lc)::value>::kWords><<<grid, 256, 0, st>>>(
+                x.f, x.s, x.phi, reinterpret_cast<const uint32_t*>(x.codes), c, nblk, z.f, z.s, z.phi,
+                reinterpret_cast<uint32_t*>(z.codes));
+            return hipGetLastError();
+        });
     return hipGetLastError();
 }
 

@@ -30,7 +30,10 @@ def compare_compressed(gpu, orc, code_x, phi_x, what="compress"):
     gf, gs, gphi, gcodes = gpu
     of, os_, ophi, ocodes = orc
     nb = len(of)
-    assert gcodes.shape == ocodes.shape == (nb, 28)
+    n = code_x.shape[1]  # codes per block: 28, or 16L - L^2 for L kept lines
+    assert gcodes.shape == ocodes.shape and gcodes.shape[0] == nb and gcodes.shape[1] >= n
+    assert not gcodes[:, n:].any(), f"{what}: pad bytes after the codes are not zero"
+    gcodes, ocodes = gcodes[:, :n], ocodes[:, :n]
     bad_f = np.flatnonzero(gf.view(np.uint64) != of.view(np.uint64))
     assert bad_f.size == 0, f"{what}: f differs at blocks {bad_f[:10]}"
     bad_s = np.flatnonzero(gs.view(np.uint64) != os_.view(np.uint64))

@@ -85,6 +85,14 @@ def test_plan_rejects_invalid_item_and_reports_its_index(bad, status):
     assert st == status and n_plan == 1 and total == 0
 
 
+def test_plan_rejects_other_rates():
+    x = fake_matrix(8, 64, 0x2000000)
+    z = fake_matrix(8, 64, 0x3000000)
+    x.lines = z.lines = 3
+    st, n_plan, _ = plan([item("scale", x=x, z=z, c=2.0)])
+    assert st == -6 and n_plan == 0
+
+
 def test_plan_rejects_partial_overlap():
     x = fake_matrix(8, 64, 0x2000000)
     z = fake_matrix(8, 64, 0x2000000 + 8)

@@ -162,6 +162,30 @@ def test_matmul_compressed_validation(L):
     assert f(B(a), B(b), None, 8, 8, B(mat(16, 8, 0x100000)), 0, ws, need, 0, None) == -5  # c over a
 
 
+def test_kept_lines_validation(L):
+    """The tunable rate: code strides, sizes, and which calls take L != 2."""
+    assert [L.blaz_code_stride(k) for k in range(0, 9)] == [28, 16, 28, 40, 48, 56, 60, 64, 64]
+    assert L.blaz_code_stride(9) == -5 and L.blaz_code_stride(-1) == -5
+    assert L.blaz_compressed_bytes_lines(16, 16, 3) == 4 * (17 + 40)
+    assert L.blaz_compressed_bytes_lines(16, 16, 0) == L.blaz_compressed_bytes(16, 16) == 4 * 45
+
+    def m3(rows, cols, base, lines=3):
+        x = mat(rows, cols, base)
+        x.lines = lines
+        return x
+    out = 0x700000
+    assert L.blaz_decompress(B(m3(8, 8, 0x100000, 9)), out, 8, None) == -5               # L out of range
+    assert L.blaz_decompress(B(m3(8, 8, 0x100000, -1)), out, 8, None) == -5
+    x3, y2 = m3(8, 8, 0x100000), mat(8, 8, 0x200000)
+    assert L.blaz_add(B(x3), B(y2), B(m3(8, 8, 0x300000)), None) == -3                  # rates differ
+    assert L.blaz_scale(B(x3), 2.0, B(mat(8, 8, 0x300000)), None) == -3
+    assert L.blaz_compress(0x400000, 8, B(m3(8, 8, 0x100000)), 1, None, None) == -6      # FP32 transform
+    assert L.blaz_compress(0x400000, 8, B(m3(8, 8, 0x100000)), 0, 0x500000, None) == -6  # prediction output
+    idx = 0x600000
+    assert L.blaz_dot(B(x3), idx, B(m3(8, 8, 0x200000)), idx, 1, out, None) == -6
+    assert L.blaz_dot_dense(B(x3), idx, 0x500000, 0, 1, out, None) == -6
+
+
 # --------------------------------------------------------------------------
 # The parity rules (tests/parity.py) catch what they should
 # --------------------------------------------------------------------------
