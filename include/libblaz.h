@@ -22,7 +22,8 @@
  *  - A launch failure reported by the HIP runtime returns BLAZ_ERR_HIP.
  *  - Data conditions are not errors: saturated codes in an addition, phi
  *    clamps, constant blocks.  Non-finite inputs give unspecified contents
- *    in the affected blocks.
+ *    in the affected blocks.  blaz_diagnose counts them in a compressed
+ *    matrix.
  *  - Matrices are row-major binary64 with a leading dimension (elements)
  *    >= cols.  rows and cols must be multiples of 8 (the paper splits into
  *    8x8 blocks and gives no padding rule); 0 is allowed and gives an empty
@@ -217,6 +218,19 @@ size_t blaz_matmul_compressed_workspace_bytes(int64_t m, int64_t n, int64_t k, i
 blaz_status blaz_matmul_compressed(const blaz_matrix *a, const blaz_matrix *b, const double *bdense, int64_t n,
                                    int64_t ldb, blaz_matrix *c, blaz_precision prec, void *workspace,
                                    size_t ws_bytes, int32_t tile, hipStream_t stream);
+
+/* Counts of the data conditions in a compressed matrix, added (atomically,
+ * so several calls may accumulate into the same array) to counters[0..3],
+ * a device array of 4 uint64 the caller zeroes:
+ *   [0] constant blocks: s == 0 (K = 0 in Eq. eqslope2; they decode to f)
+ *   [1] phi clamps: blocks with s != 0 and phi == 255 (127/m >= 255, few
+ *       non-zero slopes; reading of Eq. eqphi's 8-bit storage)
+ *   [2] codes at +-127: the saturation bound of an addition (Algorithm 1),
+ *       also reached without saturation when phi * m == 127 exactly
+ *   [3] non-finite records: f or s is not finite
+ * Reads the matrix only; the kept lines of any rate are counted.  counters
+ * 8-byte aligned, not overlapping the matrix. */
+blaz_status blaz_diagnose(const blaz_matrix *x, uint64_t *counters, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Batching: many operations, on matrices of any sizes, in one persistent

@@ -24,7 +24,7 @@ EXPORTS = (
     "blaz_block_count", "blaz_compressed_bytes", "blaz_code_stride", "blaz_compressed_bytes_lines", "blaz_compress", "blaz_decompress", "blaz_add",
     "blaz_sub", "blaz_scale", "blaz_dot", "blaz_dot_dense", "blaz_matmul_workspace_bytes",
     "blaz_matmul", "blaz_matmul_tiled", "blaz_matmul_compressed_workspace_bytes", "blaz_matmul_compressed",
-    "blaz_status_string", "blaz_batch_plan_bytes", "blaz_batch_plan", "blaz_batch_run",
+    "blaz_diagnose", "blaz_status_string", "blaz_batch_plan_bytes", "blaz_batch_plan", "blaz_batch_run",
 )
 
 
@@ -99,6 +99,7 @@ def lib():
         "blaz_add": ([M, M, M, P], I),
         "blaz_sub": ([M, M, M, P], I),
         "blaz_scale": ([M, D, M, P], I),
+        "blaz_diagnose": ([M, P, P], I),
         "blaz_dot": ([M, P, M, P, I64, P, P], I),
         "blaz_dot_dense": ([M, P, P, I64, I64, P, P], I),
         "blaz_matmul_workspace_bytes": ([I64, I64, I64, I, I], ctypes.c_size_t),

@@ -140,6 +140,21 @@ def scale(x: BlazMatrix, c: float, out: BlazMatrix | None = None) -> BlazMatrix:
     return out
 
 
+DIAGNOSE_FIELDS = ("constant_blocks", "phi_clamps", "codes_at_127", "nonfinite_records")
+
+
+def diagnose(x: BlazMatrix, counters: torch.Tensor | None = None) -> torch.Tensor:
+    """Data-condition counts of x (int64 [4], see DIAGNOSE_FIELDS), added to
+    ``counters`` when given (zeroed otherwise)."""
+    if counters is None:
+        counters = torch.zeros(4, dtype=torch.int64, device=x.f.device)
+    if counters.dtype != torch.int64 or counters.numel() < 4 or not counters.is_contiguous():
+        raise ValueError("diagnose: counters must be a contiguous int64 tensor of 4 entries")
+    m = x.c()
+    check(_lib.lib().blaz_diagnose(ctypes.byref(m), _ptr(counters), _stream()), "blaz_diagnose")
+    return counters
+
+
 def dot(x: BlazMatrix, xrow: torch.Tensor, y: BlazMatrix, ycol: torch.Tensor,
         out: torch.Tensor | None = None) -> torch.Tensor:
     """out[q] = <line xrow[q] of x, column ycol[q] of y> (int64 device index tensors)."""

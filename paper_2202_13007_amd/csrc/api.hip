@@ -83,6 +83,16 @@ BLAZ_API blaz_status blaz_scale(const blaz_matrix* x, double c, const blaz_matri
     return hip_status(blaz::detail::launch_scale(*x, c, *z, stream));
 }
 
+BLAZ_API blaz_status blaz_diagnose(const blaz_matrix* x, uint64_t* counters, hipStream_t stream)
+{
+    if (blaz_status st = check_matrix(x)) return st;
+    if (nblocks(*x) == 0) return BLAZ_OK;
+    if (!counters) return BLAZ_ERR_NULL;
+    if (!aligned(counters, 8)) return BLAZ_ERR_ALIGN;
+    if (overlaps_matrix(span(counters, 32), *x)) return BLAZ_ERR_ARG;
+    return hip_status(blaz::detail::launch_diagnose(*x, counters, stream));
+}
+
 BLAZ_API blaz_status blaz_dot(const blaz_matrix* x, const int64_t* xrow, const blaz_matrix* y, const int64_t* ycol,
                               int64_t count, double* out, hipStream_t stream)
 {

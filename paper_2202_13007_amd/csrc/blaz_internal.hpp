@@ -44,6 +44,8 @@ hipError_t launch_decompress_bf16_split(const blaz_matrix& m, __bf16* hi, __bf16
 hipError_t launch_add(const blaz_matrix& x, const blaz_matrix& y, const blaz_matrix& z, bool negate_y,
                       hipStream_t st);
 hipError_t launch_scale(const blaz_matrix& x, double c, const blaz_matrix& z, hipStream_t st);
+// Data-condition counts of a compressed matrix, added to counters[0..3].
+hipError_t launch_diagnose(const blaz_matrix& x, uint64_t* counters, hipStream_t st);
 hipError_t launch_dot(const blaz_matrix& x, const int64_t* xrow, const blaz_matrix& y, const int64_t* ycol,
                       int64_t count, double* out, hipStream_t st);
 hipError_t launch_dot_dense(const blaz_matrix& x, const int64_t* xrow, const double* v, int64_t ldv,

@@ -60,7 +60,54 @@ __global__ __launch_bounds__(256) void scale_kernel(const double* __restrict__ f
     }
 }
 
+// Data conditions of a compressed matrix (see blaz_diagnose): one lane per
+// block, the wave's counts summed across lanes and added by lane 0.
+template <int L>
+__global__ __launch_bounds__(256) void diagnose_kernel(const double* __restrict__ f, const double* __restrict__ s,
+                                                       const uint8_t* __restrict__ phi,
+                                                       const uint32_t* __restrict__ codes, int64_t nblk,
+                                                       unsigned long long* __restrict__ counters)
+{
+    constexpr int kW = KeptLines<L>::kWords, kN = KeptLines<L>::kCount;
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int c[4] = {0, 0, 0, 0};
+    if (b < nblk) {
+        const double fb = f[b], sb = s[b];
+        c[0] = sb == 0.0;
+        c[1] = sb != 0.0 && phi[b] == 255;
+        c[3] = !(__builtin_isfinite(fb) && __builtin_isfinite(sb));
+#pragma unroll
+        for (int t = 0; t < kN; ++t) {
+            const int32_t v = (int32_t)(codes[b * kW + t / 4] << (24 - 8 * (t % 4))) >> 24;
+            c[2] += v >= 127 || v <= -127;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int off = 32; off >= 1; off /= 2) c[k] += __shfl_xor(c[k], off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (c[k]) atomicAdd(counters + k, (unsigned long long)c[k]);
+    }
+}
+
 namespace detail {
+
+hipError_t launch_diagnose(const blaz_matrix& x, uint64_t* counters, hipStream_t st)
+{
+    const int64_t nblk = (x.rows / 8) * (x.cols / 8);
+    const unsigned grid = (unsigned)((nblk + 255) / 256);
+    return dispatch_lines(x, [&](auto lc) {
+        diagnose_kernel<decltype(lc)::value><<<grid, 256, 0, st>>>(
+            x.f, x.s, x.phi, reinterpret_cast<const uint32_t*>(x.codes), nblk,
+            reinterpret_cast<unsigned long long*>(counters));
+        return hipGetLastError();
+    });
+}
+
 
 hipError_t launch_add(const blaz_matrix& x, const blaz_matrix& y, const blaz_matrix& z, bool negate_y,
                       hipStream_t st)

@@ -415,6 +415,41 @@ def test_dot_equals_matmul_element():
 
 
 # --------------------------------------------------------------------------
+# Data-condition counts
+# --------------------------------------------------------------------------
+
+def condition_counts(c: oracle.Compressed):
+    """The four counts of blaz_diagnose, from their definitions."""
+    n = oracle.kept_count(c.lines)
+    codes = c.codes[:, :n].astype(int)
+    return np.array([(c.s == 0).sum(), ((c.s != 0) & (c.phi == 255)).sum(), (np.abs(codes) >= 127).sum(),
+                     (~(np.isfinite(c.f) & np.isfinite(c.s))).sum()], dtype=np.int64)
+
+
+def test_diagnose_counts_conditions():
+    special = oracle.compress(special_blocks())         # constant, zero and clamping blocks
+    x = random_records(64, 64, 7)
+    y = random_records(64, 64, 8)
+    y.s = -0.9 * x.s                                     # opposite slopes: |alpha| > 1, saturation
+    summed = oracle.add(x, y)
+    bad = random_records(16, 64, 9)
+    bad.f[3] = np.nan
+    bad.s[5] = np.inf
+    three = oracle.compress_lines(special_blocks(), 3)
+    for c in (special, summed, bad, three):
+        want = condition_counts(c)
+        got = blaz.diagnose(blaz.BlazMatrix.from_host(c.rows, c.cols, c.f, c.s, c.phi, c.codes, lines=c.lines))
+        assert np.array_equal(got.cpu().numpy(), want), (got, want)
+    assert condition_counts(special)[[0, 1]].min() >= 1 and condition_counts(summed)[2] > 0
+    # counts accumulate into a caller's array
+    acc = torch.zeros(4, dtype=torch.int64, device="cuda")
+    g = upload(summed)
+    blaz.diagnose(g, acc)
+    blaz.diagnose(g, acc)
+    assert np.array_equal(acc.cpu().numpy(), 2 * condition_counts(summed))
+
+
+# --------------------------------------------------------------------------
 # Matmul with a compressed result
 # --------------------------------------------------------------------------
 

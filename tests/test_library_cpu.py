@@ -162,6 +162,14 @@ def test_matmul_compressed_validation(L):
     assert f(B(a), B(b), None, 8, 8, B(mat(16, 8, 0x100000)), 0, ws, need, 0, None) == -5  # c over a
 
 
+def test_diagnose_validation(L):
+    x = mat(16, 16, 0x100000)
+    assert L.blaz_diagnose(B(x), None, None) == -1
+    assert L.blaz_diagnose(B(x), 0x500004, None) == -4
+    assert L.blaz_diagnose(B(x), 0x100000, None) == -5                    # counters inside f
+    assert L.blaz_diagnose(B(mat(0, 16, 0)), None, None) == 0             # nothing to count
+
+
 def test_kept_lines_validation(L):
     """The tunable rate: code strides, sizes, and which calls take L != 2."""
     assert [L.blaz_code_stride(k) for k in range(0, 9)] == [28, 16, 28, 40, 48, 56, 60, 64, 64]
