@@ -30,7 +30,14 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kPad = 16;  // elements of padding per LDS row (see the bank notes at each use)
+// Elements of padding per LDS row of the FP64/FP32 operand tiles.  FP64: 2
+// doubles, so a 130-double row starts 4 banks after the previous one; the
+// transposed A stores (8 lanes writing rows k, k+2, ..., k+14 of one column)
+// then land on distinct banks, and the operand reads conflict at most
+// 2-way.  (A 16-double pad puts those 8 stores on one bank: measured 12 %
+// slower at 4096^3.)  FP32: 16 floats.
+template <typename T>
+constexpr int kPadOf = sizeof(T) == 8 ? 2 : 16;
 
 // Tile (tm, tn) for workgroup `wg` of `nwg`: contiguous ranges per XCD, then
 // groups of 8 tile rows walked column by column for L2 reuse.
@@ -70,9 +77,8 @@ struct Mfma16x16x4<float> {
 };
 
 // C = A B with A (M x K, lda) and B (K x N, ldb) row-major in T; C binary64.
-// LDS rows hold kBM + kPad elements (144 or 80 doubles, 144 or 80 floats),
-// which puts the four k rows read by one MFMA operand fetch on different
-// banks.
+// LDS rows hold kBM + kPadOf<T> elements (130 or 66 doubles, 144 or 80
+// floats).
 template <typename T, int kBM>
 __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
                                                    int64_t ldb, double* __restrict__ C, int64_t ldc, int64_t M,
@@ -90,6 +96,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
     constexpr int RV = kBM * AV / 256;    // vectors of A (and of B) per thread
     static_assert(kBM * AV == BK * BV && RV * 256 == kBM * AV, "whole vectors per thread");
 
+    constexpr int kPad = kPadOf<T>;
     __shared__ T As[2][BK][kBM + kPad];  // A tiles stored k-major (transposed), double-buffered
     __shared__ T Bs[2][BK][kBN + kPad];
 
