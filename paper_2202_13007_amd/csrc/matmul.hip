@@ -35,9 +35,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // transposed A stores (8 lanes writing rows k, k+2, ..., k+14 of one column)
 // then land on distinct banks, and the operand reads conflict at most
 // 2-way.  (A 16-double pad puts those 8 stores on one bank: measured 12 %
-// slower at 4096^3.)  FP32: 16 floats.
+// slower at 4096^3.)  FP32: 4 floats (measured against 0, 8, 12, 16, 20:
+// 4 is fastest, +6 % over 16 on the 128 tile, +10 % on the 64 tile).
 template <typename T>
-constexpr int kPadOf = sizeof(T) == 8 ? 2 : 16;
+constexpr int kPadOf = sizeof(T) == 8 ? 2 : 4;
 
 // Tile (tm, tn) for workgroup `wg` of `nwg`: contiguous ranges per XCD, then
 // groups of 8 tile rows walked column by column for L2 reuse.
@@ -77,7 +78,7 @@ struct Mfma16x16x4<float> {
 };
 
 // C = A B with A (M x K, lda) and B (K x N, ldb) row-major in T; C binary64.
-// LDS rows hold kBM + kPadOf<T> elements (130 or 66 doubles, 144 or 80
+// LDS rows hold kBM + kPadOf<T> elements (130 or 66 doubles, 132 or 68
 // floats).
 template <typename T, int kBM>
 __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
