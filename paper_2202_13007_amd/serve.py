@@ -10,8 +10,10 @@ device (and, for compress, dense matrices resident in HBM).  Two forms:
   their outputs (and workspaces) fit an HBM budget, and on every tick turns
   the newly admitted block-level requests (compress, add, scale, dot) into
   one batch -- one persistent launch over a flat chunk queue -- on one
-  stream, and launches the admitted matmuls round-robin on a few more
-  streams, so the batch and the contractions overlap on the device.  Ticks do not wait for each other: up
+  stream, and launches the admitted matmuls on a few more streams (those
+  that fill the GPU alone in order on one of them, the small ones
+  round-robin on the others), so the batch and the contractions overlap on
+  the device.  Ticks do not wait for each other: up
   to ``max_inflight`` ticks run at once, and requests arriving meanwhile are
   admitted into the next tick as memory frees up.  The matmul contraction
   may run in FP64, FP32 or BF16x3 (``matmul_prec``).
@@ -106,10 +108,14 @@ class Server:
         self.tuner = tuner
         self.keep = keep_results
         self.s_block = torch.cuda.Stream()
-        # matmuls go round-robin over a few streams so that small contractions
-        # (a handful of workgroups each) run side by side
-        self.s_mm = [torch.cuda.Stream() for _ in range(max(1, matmul_streams))]
+        # Contractions that fill the GPU on their own (at least one 128 x 128
+        # output tile per compute unit) run in order on the first matmul
+        # stream -- side by side they would only contend; smaller ones go
+        # round-robin over the others so that a handful of workgroups each
+        # can share the GPU.
+        self.s_mm = [torch.cuda.Stream() for _ in range(max(2, matmul_streams))]
         self._next_mm = 0
+        self.cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
 
     # -- per-request work ------------------------------------------------------
     def _alloc(self, r: Request):
@@ -258,8 +264,11 @@ class Server:
                 ev.record(self.s_block)
             units.append((ev, blocks, [plan]))
         for r in mms:
-            st = self.s_mm[self._next_mm % len(self.s_mm)]
-            self._next_mm += 1
+            if ((r.n + 127) // 128) ** 2 >= self.cus:
+                st = self.s_mm[0]
+            else:
+                st = self.s_mm[1 + self._next_mm % (len(self.s_mm) - 1)]
+                self._next_mm += 1
             with torch.cuda.stream(st):
                 self._standalone(r)
                 ev = torch.cuda.Event(enable_timing=True)
