@@ -762,6 +762,30 @@ def test_matmul_tiles_give_identical_results(prec, m, k, n):
         blaz.matmul(x, dB, prec=prec, tile=96)
 
 
+def test_non_finite_input_is_contained_and_counted():
+    """Non-finite inputs give unspecified contents in the affected blocks only:
+    the kernels run, every other block is the oracle's, and blaz_diagnose
+    counts the affected records."""
+    A = smooth_field(32, 4, 2.0, 1e-3, 450, cols=48)
+    A[3, 5] = np.nan      # block (0, 0): s becomes NaN
+    A[17, 40] = np.inf    # block (2, 5)
+    A[8, 8] = np.inf      # first element of block (1, 1): f is inf
+    g = blaz.compress(dev(A))
+    torch.cuda.synchronize()
+    bad = {0, 2 * 6 + 5, 1 * 6 + 1}
+    want, (_, cx, px) = oracle.compress(np.where(np.isfinite(A), A, 0.0), with_debug=True)
+    got = host(g)
+    keep = np.array([b not in bad for b in range(want.nblk)])
+    sub = tuple(a[keep] for a in got)
+    compare_compressed(sub, (want.f[keep], want.s[keep], want.phi[keep], want.codes[keep]), cx[keep], px[keep],
+                       "finite blocks next to non-finite ones")
+    counts = blaz.diagnose(g).cpu().numpy()
+    assert counts[3] == 3
+    D = blaz.decompress(g).cpu().numpy()  # runs; finite blocks decode as usual
+    ok = np.isfinite(D).reshape(4, 8, 6, 8).all(axis=(1, 3)).ravel()
+    assert all(ok[b] for b in range(want.nblk) if b not in bad)
+
+
 def test_empty_and_k0():
     z = blaz.BlazMatrix.empty(0, 16)
     blaz.compress(torch.empty((0, 16), dtype=torch.float64, device="cuda"), out=z)

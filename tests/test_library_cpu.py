@@ -54,6 +54,16 @@ def test_block_count_and_bytes(L):
     assert L.blaz_compressed_bytes(7, 8) == 0
 
 
+def test_shape_limits(L):
+    """Shapes must be non-negative multiples of 8 with at most 2^38 blocks
+    (the one-lane-per-block grids stay well inside 2^31 workgroups)."""
+    assert L.blaz_block_count(8 << 19, 8 << 19) == 1 << 38          # exactly the limit
+    assert L.blaz_block_count((8 << 19) + 8, 8 << 19) == -2          # one block row more
+    assert L.blaz_block_count(-8, 8) == -2 and L.blaz_block_count(12, 8) == -2
+    assert L.blaz_compressed_bytes((8 << 19) + 8, 8 << 19) == 0
+    assert L.blaz_matmul_workspace_bytes(8, 8, 12, 0, 0) == 0
+
+
 def test_status_strings(L):
     for st in range(-8, 1):
         assert len(L.blaz_status_string(st)) > 5
