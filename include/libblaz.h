@@ -79,8 +79,9 @@ typedef enum {
  *   codes in row-major scan order, stored blaz_code_stride(L) bytes apart
  *   (padded with zeros to whole 32-bit words).  0 means 2, the paper's
  *   scheme above, so a zero-initialized descriptor is the paper's format.
- *   Compression, decompression, add, sub, scale and matmul take any L (all
- *   operands of one call share it); the dot products, the low-precision
+ *   Compression, decompression, add, sub, scale and matmul take any L (the
+ *   operands of add, sub and scale share it, else BLAZ_ERR_MISMATCH; the two
+ *   factors of a product may differ); the dot products, the low-precision
  *   transforms, the prediction side output and batching take L = 2 only
  *   (BLAZ_ERR_UNSUPPORTED otherwise).
  * The caller owns the four arrays (device memory): f and s 8-byte aligned,
@@ -139,8 +140,8 @@ blaz_status blaz_decompress(const blaz_matrix *in, double *A, int64_t lda, hipSt
  * f = f1 + f2; s = s1 + s2; phi = max(1, floor(phi1 phi2 / (phi1 + phi2)));
  * alpha_k = s_k / s; beta_k = (alpha_k / phi_k) * phi;
  * C = trunc(beta1 C1 + beta2 C2) saturated to [-127, 127]; C = 0 when s = 0.
- * All three descriptors must have the same shape; z may be x or y (in
- * place), otherwise it must not overlap them. */
+ * All three descriptors must have the same shape and kept lines; z may be x
+ * or y (in place), otherwise it must not overlap them. */
 blaz_status blaz_add(const blaz_matrix *x, const blaz_matrix *y, const blaz_matrix *z, hipStream_t stream);
 
 /* Subtraction z = x - y, which the paper says works like the addition:
@@ -158,7 +159,10 @@ blaz_status blaz_scale(const blaz_matrix *x, double c, const blaz_matrix *z, hip
  * for q = 0..count-1.  Only the lines 0..(xrow mod 8) of the blocks of X and
  * the columns 0..(ycol mod 8) of the blocks of Y that the product needs are
  * rebuilt.  x->cols must equal y->rows.  xrow and ycol are device arrays of
- * count int64; an index outside its matrix yields out[q] = NaN. */
+ * count int64; an index outside its matrix yields out[q] = NaN.  Queries are
+ * taken 8 at a time: 8 consecutive queries on the lines 8I..8I+7 in order
+ * (and the columns 8J..8J+7 of Y in order) rebuild each block once for the 8;
+ * every query gets the same bits either way. */
 blaz_status blaz_dot(const blaz_matrix *x, const int64_t *xrow, const blaz_matrix *y, const int64_t *ycol,
                      int64_t count, double *out, hipStream_t stream);
 
