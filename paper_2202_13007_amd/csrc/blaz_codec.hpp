@@ -372,6 +372,11 @@ __device__ __forceinline__ void decompress_wave(const double* __restrict__ f, co
 {
     const int64_t b = wave_base + lane;
     const bool valid = b < nblk;
+    // f, s and phi are loaded first, so that their latency overlaps the
+    // staging of the codes instead of following it.
+    const double fb = valid ? f[b] : 0.0;
+    const double sb = valid ? s[b] : 0.0;
+    const double pb = valid ? (double)phi[b] : 1.0;
 
     // The wave's codes: consecutive dwords into LDS, then each lane's own
     // (7 for the paper's scheme, KeptLines<L>::kWords in general).
@@ -389,10 +394,6 @@ __device__ __forceinline__ void decompress_wave(const double* __restrict__ f, co
 #pragma unroll
     for (int q = 0; q < kW; ++q) w[q] = ct[lane * kW + q];
     __syncthreads();
-
-    const double fb = valid ? f[b] : 0.0;
-    const double sb = valid ? s[b] : 0.0;
-    const double pb = valid ? (double)phi[b] : 1.0;
     // Dhat = C / phi at the kept positions (zero elsewhere); the slope factor
     // of Eq. eqbbb is folded in by linearity of the inverse DCT.
     double x[64];
