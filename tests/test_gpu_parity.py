@@ -512,6 +512,54 @@ def test_matmul_compressed_against_oracle(m, k, n, bform):
     assert flips <= 1e-3 * (m // 8) * (n // 8) * 28
 
 
+def test_matmul_compressed_full_size_4096_sampled():
+    """The 4096^3 product of the compressed field and the compressed U[-1, 1]
+    matrix, recompressed: a grid of sampled output blocks against the oracle's
+    compression of the oracle's product of the decompressed block row and
+    block column, under the perturbation band of the smaller cases."""
+    A, B, _ = workload_inputs("linalg-4096")
+    ga, gb = blaz.compress(dev(A)), blaz.compress(dev(B))
+    got = host(blaz.matmul_compressed(ga, gb))
+    oa, ob = oracle.Compressed(4096, 4096, *host(ga)), oracle.Compressed(4096, 4096, *host(gb))
+    nbc = 512
+    rng = np.random.default_rng(5)
+    Is = np.unique(np.concatenate([[0, nbc - 1], rng.choice(nbc, 12, replace=False)]))
+    Js = np.unique(np.concatenate([[0, nbc - 1], rng.choice(nbc, 12, replace=False)]))
+    sample = np.array([I * nbc + J for I in Is for J in Js])
+    rows = {}
+    cols = {}
+    Pb, mag = [], []
+    for b in sample:
+        I, J = divmod(int(b), nbc)
+        if I not in rows:
+            band = oracle.Compressed(8, 4096, oa.f[I * nbc:(I + 1) * nbc], oa.s[I * nbc:(I + 1) * nbc],
+                                     oa.phi[I * nbc:(I + 1) * nbc], oa.codes[I * nbc:(I + 1) * nbc])
+            rows[I] = oracle.decompress(band)
+        if J not in cols:
+            idx = np.arange(J, nbc * nbc, nbc)
+            band = oracle.Compressed(4096, 8, ob.f[idx], ob.s[idx], ob.phi[idx], ob.codes[idx])
+            cols[J] = oracle.decompress(band)
+        Pb.append(oracle.gemm(rows[I], cols[J]))
+        mag.append(np.abs(rows[I]) @ np.abs(cols[J]))
+    P = np.hstack(Pb)
+    M = np.hstack(mag)
+    o, (_, code_x, phi_x) = oracle.compress(P, with_debug=True)
+    e = blocks_max(2.0 * 4096 * 2.0 ** -53 * M)
+    gf, gs, gphi, gcodes = (a[sample] for a in got)
+    slack = 2.0 ** -40
+    assert np.all(np.abs(gf - o.f) <= e + slack * np.abs(o.f))
+    assert np.all(np.abs(gs - o.s) <= 128 * e + slack * np.abs(o.s))
+    dD = 64.0 * e / np.where(o.s != 0, o.s, np.inf)
+    dphi = gphi.astype(int) - o.phi.astype(int)
+    near_phi = np.abs(phi_x - np.round(phi_x)) <= 127.0 * dD * (phi_x / 127.0) ** 2 + slack * np.maximum(1, phi_x)
+    assert np.all((dphi == 0) | ((np.abs(dphi) == 1) & near_phi))
+    same = dphi == 0
+    band = (o.phi.astype(float) * dD)[:, None] + slack * np.maximum(1.0, np.abs(code_x))
+    dc = gcodes.astype(int) - o.codes.astype(int)
+    ok = (dc == 0) | ((np.abs(dc) == 1) & (np.abs(code_x - np.round(code_x)) <= band))
+    assert np.all(ok[same])
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("tile", [64, 128])
 def test_matmul_compressed_is_compress_of_matmul(prec, tile):

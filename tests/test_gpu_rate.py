@@ -107,3 +107,25 @@ def test_dot_and_batch_refuse_other_rates():
     assert e.value.status == -6
     with pytest.raises(blaz.BlazError):
         blaz.Batch().scale(gx, 2.0, blaz.BlazMatrix.empty(16, 16, lines=3)).plan()
+
+
+def strip_of_blocks(A, blocks):
+    """The listed 8x8 blocks of A side by side in one 8-row strip (blocks are
+    compressed independently, so the strip's records are theirs)."""
+    nbc = A.shape[1] // 8
+    return np.hstack([A[8 * (b // nbc):8 * (b // nbc) + 8, 8 * (b % nbc):8 * (b % nbc) + 8] for b in blocks])
+
+
+@pytest.mark.parametrize("lines", [1, 3, 8])
+def test_compress_lines_full_size_8192_sampled(lines):
+    """The 8192^2 field at other rates: every block on the GPU, 1500 sampled
+    blocks on the oracle."""
+    A, _ = workload_inputs("plain-8192")
+    g = blaz.compress(dev(A), lines=lines)
+    gf, gs, gphi, gcodes = host(g)
+    rng = np.random.default_rng(lines)
+    sample = np.unique(np.concatenate([[0, 1023, 1024, len(gf) - 1], rng.integers(0, len(gf), 1500)]))
+    want, (cx, px) = oracle.compress_lines(strip_of_blocks(A, sample), lines, with_debug=True)
+    ties = compare_compressed((gf[sample], gs[sample], gphi[sample], gcodes[sample]),
+                              (want.f, want.s, want.phi, want.codes), cx, px, f"8192 L={lines} sampled")
+    assert ties <= 2
