@@ -30,15 +30,23 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// Elements of padding per LDS row of the FP64/FP32 operand tiles.  FP64: 2
-// doubles, so a 130-double row starts 4 banks after the previous one; the
-// transposed A stores (8 lanes writing rows k, k+2, ..., k+14 of one column)
-// then land on distinct banks, and the operand reads conflict at most
-// 2-way.  (A 16-double pad puts those 8 stores on one bank: measured 12 %
-// slower at 4096^3.)  FP32: 4 floats (measured against 0, 8, 12, 16, 20:
-// 4 is fastest, +6 % over 16 on the 128 tile, +10 % on the 64 tile).
+// Elements of padding per LDS row of the FP64/FP32 operand tiles.  gfx950's
+// LDS serves 128 B per clock from 32 four-byte banks, 64-bit accesses in
+// groups of 16 lanes and 32-bit ones in groups of 32 (this model reproduces
+// the measured conflict counts of every layout tried).  FP64: a 16-lane group
+// of the transposed A store writes column m, m+1 of rows k, k+2, ..., k+14;
+// with a 131-double row (3 doubles of padding) those rows start 12 banks
+// apart and all 16 stores hit distinct banks (counted: 0 conflicts; a
+// 130-double row gives 2-way conflicts on them, 0.8 % slower at 4096^3).
+// B rows take even padding so that their 16-byte stores stay aligned; the
+// fragment reads (16 consecutive doubles of one row per group) never
+// conflict.  FP32: 4 floats (measured against 0, 8, 12, 16, 20: 4 is
+// fastest, +6 % over 16 on the 128 tile, +10 % on the 64 tile; a
+// conflict-free XOR layout was no faster, the kernel is not LDS-bound).
 template <typename T>
-constexpr int kPadOf = sizeof(T) == 8 ? 2 : 4;
+constexpr int kPadAOf = sizeof(T) == 8 ? 3 : 4;
+template <typename T>
+constexpr int kPadBOf = sizeof(T) == 8 ? 2 : 4;
 
 // Tile (tm, tn) for workgroup `wg` of `nwg`: contiguous ranges per XCD, then
 // groups of 8 tile rows walked column by column for L2 reuse.
@@ -78,8 +86,7 @@ struct Mfma16x16x4<float> {
 };
 
 // C = A B with A (M x K, lda) and B (K x N, ldb) row-major in T; C binary64.
-// LDS rows hold kBM + kPadOf<T> elements (130 or 66 doubles, 132 or 68
-// floats).
+// LDS rows hold kBM + kPadAOf<T> (A) and kBN + kPadBOf<T> (B) elements.
 template <typename T, int kBM>
 __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
                                                    int64_t ldb, double* __restrict__ C, int64_t ldc, int64_t M,
@@ -97,9 +104,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
     constexpr int RV = kBM * AV / 256;    // vectors of A (and of B) per thread
     static_assert(kBM * AV == BK * BV && RV * 256 == kBM * AV, "whole vectors per thread");
 
-    constexpr int kPad = kPadOf<T>;
-    __shared__ T As[2][BK][kBM + kPad];  // A tiles stored k-major (transposed), double-buffered
-    __shared__ T Bs[2][BK][kBN + kPad];
+    __shared__ __align__(16) T As[2][BK][kBM + kPadAOf<T>];  // A tiles stored k-major (transposed), double-buffered
+    __shared__ __align__(16) T Bs[2][BK][kBN + kPadBOf<T>];  // 16-byte row stores
+    static_assert((kBN + kPadBOf<T>) * sizeof(T) % 16 == 0, "B rows keep 16-byte alignment");
 
     const int ntm = (int)((M + kBM - 1) / kBM);
     const int ntn = (int)((N + kBN - 1) / kBN);
@@ -188,10 +195,19 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
 
 // BF16x3: A hi/lo (M x K, lda) and B^T hi/lo (N x K, ldbt), all with k
 // contiguous, so that one 16-byte load gives an MFMA lane its 8 k-values.
-// K advances in steps of 32.  LDS rows hold 32 + 8 bf16 (80 B): the 16 rows
-// read by one 16-lane group then start on 16 distinct 4-bank groups.
+// K advances in steps of 32.  An LDS tile row is the row's 32 bf16 (64 B, no
+// padding) as four 16-byte chunks; chunk c of row r sits in slot
+// c ^ ((r >> 1) & 3).  Both the tile stores (4 lanes per row) and the
+// fragment reads (one chunk of 16 consecutive rows per 16 lanes) are then
+// free of bank conflicts on gfx950 (counted: 0, against 2 conflict cycles
+// per access cycle with 80-byte padded rows).
 constexpr int kBKb = 32;
-constexpr int kRowB = kBKb + 8;
+constexpr int kRowB = kBKb;
+
+__device__ __forceinline__ int bf16_tile_slot(int row, int chunk)
+{
+    return row * kRowB + ((chunk ^ ((row >> 1) & 3)) << 3);
+}
 
 template <int kBM>
 __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restrict__ Ahi, const __bf16* __restrict__ Alo,
@@ -238,7 +254,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
 #pragma unroll
         for (int r = 0; r < RC; ++r) {
             const int q = tid + 256 * r;
-            const int off = (q >> 2) * kRowB + (q & 3) * 8;
+            const int off = bf16_tile_slot(q >> 2, q & 3);
             *reinterpret_cast<uint4*>(&Ash[buf][off]) = rah[r];
             *reinterpret_cast<uint4*>(&Asl[buf][off]) = ral[r];
             *reinterpret_cast<uint4*>(&Bsh[buf][off]) = rbh[r];
@@ -265,17 +281,16 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
         // 8*(l/16) .. 8*(l/16)+7 of row (A) or column (B) l%16; any fixed
         // assignment of k to (lane group, element) works as long as A and B
         // use the same one.
-        const int koff = 8 * (lane >> 4);
         bf16x8 ah[TW], al[TW], bh[TW], bl[TW];
 #pragma unroll
         for (int i = 0; i < TW; ++i) {
-            const int off = (wm * (kBM / 2) + i * 16 + (lane & 15)) * kRowB + koff;
+            const int off = bf16_tile_slot(wm * (kBM / 2) + i * 16 + (lane & 15), lane >> 4);
             ah[i] = *reinterpret_cast<const bf16x8*>(&Ash[cur][off]);
             al[i] = *reinterpret_cast<const bf16x8*>(&Asl[cur][off]);
         }
 #pragma unroll
         for (int j = 0; j < TW; ++j) {
-            const int off = (wn * (kBN / 2) + j * 16 + (lane & 15)) * kRowB + koff;
+            const int off = bf16_tile_slot(wn * (kBN / 2) + j * 16 + (lane & 15), lane >> 4);
             bh[j] = *reinterpret_cast<const bf16x8*>(&Bsh[cur][off]);
             bl[j] = *reinterpret_cast<const bf16x8*>(&Bsl[cur][off]);
         }
