@@ -44,7 +44,9 @@ extern "C" {
 typedef enum {
     BLAZ_OK = 0,
     BLAZ_ERR_NULL = -1,        /* a required pointer is NULL                          */
-    BLAZ_ERR_SHAPE = -2,       /* rows/cols negative or not a multiple of 8, or ld < cols */
+    BLAZ_ERR_SHAPE = -2,       /* rows/cols negative or not a multiple of 8, more than
+                                  2^38 blocks, ld < cols, or a dense operand whose last
+                                  element lies 2^60 or more elements past its first   */
     BLAZ_ERR_MISMATCH = -3,    /* operand shapes do not agree                         */
     BLAZ_ERR_ALIGN = -4,       /* a pointer is not aligned to its element type         */
     BLAZ_ERR_ARG = -5,         /* another invalid argument (count < 0, bad enum, overlap) */

@@ -8,7 +8,7 @@ synchronizing.
 from __future__ import annotations
 
 import ctypes
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 
 import torch
 
@@ -18,8 +18,11 @@ from ._lib import BlazMatrixC, check
 NKEPT = 28
 
 
-def _stream():
-    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+def _stream_dev():
+    """The current stream (as a C pointer) and the index of its device: the
+    library enqueues there, so every tensor must live on that device."""
+    st = torch.cuda.current_stream()
+    return ctypes.c_void_p(st.cuda_stream), st.device_index
 
 
 def _ptr(t: torch.Tensor | None):
@@ -49,6 +52,13 @@ class BlazMatrix:
     phi: torch.Tensor
     codes: torch.Tensor
     lines: int = 2
+    _desc: object = field(default=None, init=False, repr=False, compare=False)
+
+    def __setattr__(self, name, value):
+        # a reassigned field invalidates the checked descriptor
+        if name != "_desc":
+            object.__setattr__(self, "_desc", None)
+        object.__setattr__(self, name, value)
 
     @property
     def nblk(self) -> int:
@@ -70,9 +80,26 @@ class BlazMatrix:
                           torch.empty(n, dtype=torch.uint8, device=dev),
                           torch.empty((n, code_stride(lines)), dtype=torch.int8, device=dev), lines)
 
-    def c(self) -> BlazMatrixC:
-        return BlazMatrixC(self.rows, self.cols, self.f.data_ptr(), self.s.data_ptr(),
-                           self.phi.data_ptr(), self.codes.data_ptr(), self.lines)
+    def c(self, dev: int | None = None) -> BlazMatrixC:
+        """The C descriptor, after checking that the four arrays are
+        contiguous CUDA tensors on device ``dev`` (default: the current one)
+        holding at least nblk records: the library sees only pointers and the
+        shape.  The checked descriptor is kept until a field is reassigned
+        (the arrays must not be resized in place meanwhile)."""
+        if dev is None:
+            dev = torch.cuda.current_device()
+        d = self._desc
+        if d is not None and d[0] == dev:
+            return d[1]
+        n = self.nblk
+        _check_tensor(self.f, "BlazMatrix.f", torch.float64, n, dev)
+        _check_tensor(self.s, "BlazMatrix.s", torch.float64, n, dev)
+        _check_tensor(self.phi, "BlazMatrix.phi", torch.uint8, n, dev)
+        _check_tensor(self.codes, "BlazMatrix.codes", torch.int8, n * code_stride(self.lines), dev)
+        m = BlazMatrixC(self.rows, self.cols, self.f.data_ptr(), self.s.data_ptr(),
+                        self.phi.data_ptr(), self.codes.data_ptr(), self.lines)
+        object.__setattr__(self, "_desc", (dev, m))
+        return m
 
     def to_host(self):
         """(f, s, phi, codes) as numpy arrays (synchronizes)."""
@@ -90,53 +117,87 @@ class BlazMatrix:
                           .contiguous(), lines)
 
 
-def _check_dense(A: torch.Tensor, what: str):
-    if A.dtype != torch.float64 or A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
-        raise ValueError(f"{what}: expected a 2-D float64 CUDA tensor with unit column stride")
+def _on_device(t, dev: int) -> bool:
+    return isinstance(t, torch.Tensor) and t.is_cuda and t.get_device() == dev
+
+
+def _check_tensor(t, what: str, dtype: torch.dtype, numel: int, dev: int):
+    """A contiguous CUDA tensor of ``dtype`` on device ``dev`` with at least
+    ``numel`` elements: the library reads and writes that many."""
+    if not _on_device(t, dev):
+        raise ValueError(f"{what}: expected a CUDA tensor on device {dev}")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{what}: expected a contiguous {dtype} tensor, got {t.dtype}")
+    if t.numel() < numel:
+        raise ValueError(f"{what}: {t.numel()} elements, {numel} needed")
+
+
+def _check_dense(A: torch.Tensor, what: str, dev: int, shape=None):
+    """A 2-D float64 CUDA tensor on device ``dev`` with unit column stride
+    (rows may be strided), of exactly ``shape`` when given."""
+    if not _on_device(A, dev) or A.dtype != torch.float64 or A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError(f"{what}: expected a 2-D float64 CUDA tensor on device {dev} with unit column stride")
+    if shape is not None and tuple(A.shape) != tuple(shape):
+        raise ValueError(f"{what}: shape {tuple(A.shape)}, expected {tuple(shape)}")
+
+
+def _check_index(t, what: str, count: int, dev: int):
+    _check_tensor(t, what, torch.int64, count, dev)
+    if t.numel() != count:
+        raise ValueError(f"{what}: {t.numel()} indices, expected {count}")
 
 
 def compress(A: torch.Tensor, out: BlazMatrix | None = None, prec: str = "fp64",
              psi: torch.Tensor | None = None, lines: int = 2) -> BlazMatrix:
     """Compress a float64 matrix (rows, cols multiples of 8); ``lines`` sets
     the rate of a new output (ignored when ``out`` is given)."""
-    _check_dense(A, "compress")
+    stream, dev = _stream_dev()
+    _check_dense(A, "compress", dev)
     rows, cols = A.shape
     if out is None:
         out = BlazMatrix.empty(rows, cols, A.device, lines)
-    m = out.c()
+    elif (out.rows, out.cols) != (rows, cols):
+        raise ValueError(f"compress: out is {out.rows} x {out.cols}, A is {rows} x {cols}")
+    if psi is not None:
+        _check_tensor(psi, "compress psi", torch.uint8, 64 * out.nblk, dev)
+    m = out.c(dev)
     check(_lib.lib().blaz_compress(_ptr(A), A.stride(0), ctypes.byref(m), _lib.PREC[prec], _ptr(psi),
-                                   _stream()), "blaz_compress")
+                                   stream), "blaz_compress")
     return out
 
 
 def decompress(x: BlazMatrix, out: torch.Tensor | None = None) -> torch.Tensor:
+    stream, dev = _stream_dev()
     if out is None:
         out = torch.empty((x.rows, x.cols), dtype=torch.float64, device=x.f.device)
-    _check_dense(out, "decompress")
-    m = x.c()
-    check(_lib.lib().blaz_decompress(ctypes.byref(m), _ptr(out), out.stride(0), _stream()), "blaz_decompress")
+    _check_dense(out, "decompress", dev, (x.rows, x.cols))
+    m = x.c(dev)
+    check(_lib.lib().blaz_decompress(ctypes.byref(m), _ptr(out), out.stride(0), stream), "blaz_decompress")
     return out
 
 
 def add(x: BlazMatrix, y: BlazMatrix, out: BlazMatrix | None = None) -> BlazMatrix:
+    stream, dev = _stream_dev()
     out = BlazMatrix.empty(x.rows, x.cols, x.f.device, x.lines) if out is None else out
-    mx, my, mz = x.c(), y.c(), out.c()
-    check(_lib.lib().blaz_add(ctypes.byref(mx), ctypes.byref(my), ctypes.byref(mz), _stream()), "blaz_add")
+    mx, my, mz = x.c(dev), y.c(dev), out.c(dev)
+    check(_lib.lib().blaz_add(ctypes.byref(mx), ctypes.byref(my), ctypes.byref(mz), stream), "blaz_add")
     return out
 
 
 def sub(x: BlazMatrix, y: BlazMatrix, out: BlazMatrix | None = None) -> BlazMatrix:
+    stream, dev = _stream_dev()
     out = BlazMatrix.empty(x.rows, x.cols, x.f.device, x.lines) if out is None else out
-    mx, my, mz = x.c(), y.c(), out.c()
-    check(_lib.lib().blaz_sub(ctypes.byref(mx), ctypes.byref(my), ctypes.byref(mz), _stream()), "blaz_sub")
+    mx, my, mz = x.c(dev), y.c(dev), out.c(dev)
+    check(_lib.lib().blaz_sub(ctypes.byref(mx), ctypes.byref(my), ctypes.byref(mz), stream), "blaz_sub")
     return out
 
 
 def scale(x: BlazMatrix, c: float, out: BlazMatrix | None = None) -> BlazMatrix:
     """out = c * x; pass out=x for the in-place form."""
+    stream, dev = _stream_dev()
     out = BlazMatrix.empty(x.rows, x.cols, x.f.device, x.lines) if out is None else out
-    mx, mz = x.c(), out.c()
-    check(_lib.lib().blaz_scale(ctypes.byref(mx), float(c), ctypes.byref(mz), _stream()), "blaz_scale")
+    mx, mz = x.c(dev), out.c(dev)
+    check(_lib.lib().blaz_scale(ctypes.byref(mx), float(c), ctypes.byref(mz), stream), "blaz_scale")
     return out
 
 
@@ -146,43 +207,57 @@ DIAGNOSE_FIELDS = ("constant_blocks", "phi_clamps", "codes_at_127", "nonfinite_r
 def diagnose(x: BlazMatrix, counters: torch.Tensor | None = None) -> torch.Tensor:
     """Data-condition counts of x (int64 [4], see DIAGNOSE_FIELDS), added to
     ``counters`` when given (zeroed otherwise)."""
+    stream, dev = _stream_dev()
     if counters is None:
         counters = torch.zeros(4, dtype=torch.int64, device=x.f.device)
-    if counters.dtype != torch.int64 or counters.numel() < 4 or not counters.is_contiguous():
-        raise ValueError("diagnose: counters must be a contiguous int64 tensor of 4 entries")
-    m = x.c()
-    check(_lib.lib().blaz_diagnose(ctypes.byref(m), _ptr(counters), _stream()), "blaz_diagnose")
+    _check_tensor(counters, "diagnose counters", torch.int64, 4, dev)
+    m = x.c(dev)
+    check(_lib.lib().blaz_diagnose(ctypes.byref(m), _ptr(counters), stream), "blaz_diagnose")
     return counters
 
 
 def dot(x: BlazMatrix, xrow: torch.Tensor, y: BlazMatrix, ycol: torch.Tensor,
         out: torch.Tensor | None = None) -> torch.Tensor:
     """out[q] = <line xrow[q] of x, column ycol[q] of y> (int64 device index tensors)."""
+    stream, dev = _stream_dev()
     count = xrow.numel()
-    if ycol.numel() != count or xrow.dtype != torch.int64 or ycol.dtype != torch.int64:
-        raise ValueError("dot: xrow and ycol must be int64 tensors of one length")
+    xrow, ycol = xrow.contiguous(), ycol.contiguous()
+    _check_index(xrow, "dot xrow", count, dev)
+    _check_index(ycol, "dot ycol", count, dev)
     out = torch.empty(count, dtype=torch.float64, device=x.f.device) if out is None else out
-    mx, my = x.c(), y.c()
-    check(_lib.lib().blaz_dot(ctypes.byref(mx), _ptr(xrow.contiguous()), ctypes.byref(my),
-                              _ptr(ycol.contiguous()), count, _ptr(out), _stream()), "blaz_dot")
+    _check_tensor(out, "dot out", torch.float64, count, dev)
+    mx, my = x.c(dev), y.c(dev)
+    check(_lib.lib().blaz_dot(ctypes.byref(mx), _ptr(xrow), ctypes.byref(my), _ptr(ycol), count, _ptr(out),
+                              stream), "blaz_dot")
     return out
+
+
+def _dense_vectors(v: torch.Tensor, cols: int, count: int, what: str, dev: int) -> int:
+    """ldv of the vectors of a dense dot: 0 for one shared 1-D vector of at
+    least ``cols`` entries, else the row stride of a [count, >= cols] matrix."""
+    if not _on_device(v, dev) or v.dtype != torch.float64:
+        raise ValueError(f"{what}: expected a float64 CUDA tensor on device {dev}")
+    if v.dim() == 1:
+        if v.stride(0) != 1 or v.numel() < cols:
+            raise ValueError(f"{what}: a shared vector needs {cols} contiguous entries")
+        return 0
+    if v.dim() != 2 or v.stride(1) != 1 or v.shape[0] != count or v.shape[1] < cols:
+        raise ValueError(f"{what}: expected [{count}, >= {cols}] with unit column stride")
+    return v.stride(0)
 
 
 def dot_dense(x: BlazMatrix, xrow: torch.Tensor, v: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
     """out[q] = <line xrow[q] of x, v[q]> (v 2-D [count, >= cols]) or with one shared 1-D v."""
+    stream, dev = _stream_dev()
     count = xrow.numel()
-    if xrow.dtype != torch.int64:
-        raise ValueError("dot_dense: xrow must be int64")
-    if v.dim() == 1:
-        ldv = 0
-    else:
-        if v.stride(1) != 1 or v.shape[0] != count:
-            raise ValueError("dot_dense: v must be [count, >= cols] with unit column stride")
-        ldv = v.stride(0)
+    xrow = xrow.contiguous()
+    _check_index(xrow, "dot_dense xrow", count, dev)
+    ldv = _dense_vectors(v, x.cols, count, "dot_dense v", dev)
     out = torch.empty(count, dtype=torch.float64, device=x.f.device) if out is None else out
-    mx = x.c()
-    check(_lib.lib().blaz_dot_dense(ctypes.byref(mx), _ptr(xrow.contiguous()), _ptr(v), ldv, count, _ptr(out),
-                                    _stream()), "blaz_dot_dense")
+    _check_tensor(out, "dot_dense out", torch.float64, count, dev)
+    mx = x.c(dev)
+    check(_lib.lib().blaz_dot_dense(ctypes.byref(mx), _ptr(xrow), _ptr(v), ldv, count, _ptr(out), stream),
+          "blaz_dot_dense")
     return out
 
 
@@ -190,26 +265,38 @@ def matmul_workspace_bytes(m: int, n: int, k: int, b_compressed: bool, prec: str
     return int(_lib.lib().blaz_matmul_workspace_bytes(m, n, k, int(b_compressed), _lib.PREC[prec]))
 
 
+def _operand_b(a: BlazMatrix, b, what: str, dev: int) -> int:
+    """n of the product A B: B compressed (its descriptor carries the shape
+    the library checks) or a dense float64 a.cols x n tensor."""
+    if isinstance(b, BlazMatrix):
+        return b.cols
+    _check_dense(b, what, dev)
+    if b.shape[0] != a.cols:
+        raise ValueError(f"{what}: {b.shape[0]} rows, A has {a.cols} columns")
+    return b.shape[1]
+
+
 def matmul(a: BlazMatrix, b: BlazMatrix | torch.Tensor, out: torch.Tensor | None = None, prec: str = "fp64",
            workspace: torch.Tensor | None = None, tile: int = 0) -> torch.Tensor:
     """C = A B with A compressed and B compressed or dense float64; C dense float64.
 
     tile: output tile of the contraction (64 or 128); 0 = the library's choice."""
+    stream, dev = _stream_dev()
     compressed_b = isinstance(b, BlazMatrix)
-    n = b.cols if compressed_b else b.shape[1]
-    if not compressed_b:
-        _check_dense(b, "matmul B")
+    n = _operand_b(a, b, "matmul B", dev)
     if out is None:
         out = torch.empty((a.rows, n), dtype=torch.float64, device=a.f.device)
-    need = matmul_workspace_bytes(a.rows, n, a.cols, compressed_b, prec)
+    _check_dense(out, "matmul out", dev, (a.rows, n))
     if workspace is None:
+        need = matmul_workspace_bytes(a.rows, n, a.cols, compressed_b, prec)
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=a.f.device)
-    ma = a.c()
-    mb = b.c() if compressed_b else None
+    _check_tensor(workspace, "matmul workspace", torch.uint8, 0, dev)
+    ma = a.c(dev)
+    mb = b.c(dev) if compressed_b else None
     check(_lib.lib().blaz_matmul_tiled(ctypes.byref(ma), ctypes.byref(mb) if compressed_b else None,
                                        None if compressed_b else _ptr(b), n, 0 if compressed_b else b.stride(0),
                                        _ptr(out), out.stride(0), _lib.PREC[prec], _ptr(workspace),
-                                       workspace.numel(), int(tile), _stream()), "blaz_matmul")
+                                       workspace.numel(), int(tile), stream), "blaz_matmul")
     return out
 
 
@@ -220,22 +307,22 @@ def matmul_compressed_workspace_bytes(m: int, n: int, k: int, b_compressed: bool
 def matmul_compressed(a: BlazMatrix, b: BlazMatrix | torch.Tensor, out: BlazMatrix | None = None,
                       prec: str = "fp64", workspace: torch.Tensor | None = None, tile: int = 0) -> BlazMatrix:
     """C = A B compressed (the compression of ``matmul(a, b, prec=prec)``)."""
+    stream, dev = _stream_dev()
     compressed_b = isinstance(b, BlazMatrix)
-    n = b.cols if compressed_b else b.shape[1]
-    if not compressed_b:
-        _check_dense(b, "matmul B")
+    n = _operand_b(a, b, "matmul_compressed B", dev)
     if out is None:
         out = BlazMatrix.empty(a.rows, n, a.f.device)
-    need = matmul_compressed_workspace_bytes(a.rows, n, a.cols, compressed_b, prec)
     if workspace is None:
+        need = matmul_compressed_workspace_bytes(a.rows, n, a.cols, compressed_b, prec)
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=a.f.device)
-    ma, mc = a.c(), out.c()
-    mb = b.c() if compressed_b else None
+    _check_tensor(workspace, "matmul_compressed workspace", torch.uint8, 0, dev)
+    ma, mc = a.c(dev), out.c(dev)
+    mb = b.c(dev) if compressed_b else None
     check(_lib.lib().blaz_matmul_compressed(ctypes.byref(ma), ctypes.byref(mb) if compressed_b else None,
                                             None if compressed_b else _ptr(b), n,
                                             0 if compressed_b else b.stride(0), ctypes.byref(mc),
                                             _lib.PREC[prec], _ptr(workspace), workspace.numel(), int(tile),
-                                            _stream()), "blaz_matmul_compressed")
+                                            stream), "blaz_matmul_compressed")
     return out
 
 
@@ -247,7 +334,9 @@ class Batch:
     """Collects operations; ``plan()`` validates them and uploads the plan.
 
     Items run concurrently: no item may use another item's output.  Tensors
-    referenced by the items are kept alive by the batch and its plans."""
+    referenced by the items are kept alive by the batch and its plans; they
+    must live on the device that is current when they are added, the device
+    the plan is run on."""
 
     def __init__(self):
         self.items = []
@@ -258,9 +347,10 @@ class Batch:
         it.op = _lib.OPS[op]
         it.reserved = 0
         empty = BlazMatrixC(0, 0, None, None, None, None)
-        it.x = x.c() if x is not None else empty
-        it.y = y.c() if y is not None else empty
-        it.z = z.c() if z is not None else empty
+        dev = torch.cuda.current_device()
+        it.x = x.c(dev) if x is not None else empty
+        it.y = y.c(dev) if y is not None else empty
+        it.z = z.c(dev) if z is not None else empty
         it.dense = None if dense is None else dense.data_ptr()
         it.ld = ld
         it.c = float(c)
@@ -273,11 +363,11 @@ class Batch:
         return self
 
     def compress(self, A: torch.Tensor, out: BlazMatrix):
-        _check_dense(A, "batch compress")
+        _check_dense(A, "batch compress", torch.cuda.current_device(), (out.rows, out.cols))
         return self._add("compress", x=out, dense=A, ld=A.stride(0))
 
     def decompress(self, x: BlazMatrix, out: torch.Tensor):
-        _check_dense(out, "batch decompress")
+        _check_dense(out, "batch decompress", torch.cuda.current_device(), (x.rows, x.cols))
         return self._add("decompress", x=x, dense=out, ld=out.stride(0))
 
     def add(self, x: BlazMatrix, y: BlazMatrix, out: BlazMatrix):
@@ -290,11 +380,18 @@ class Batch:
         return self._add("scale", x=x, z=out, c=c)
 
     def dot(self, x: BlazMatrix, xrow: torch.Tensor, y: BlazMatrix, ycol: torch.Tensor, out: torch.Tensor):
-        return self._add("dot", x=x, y=y, xrow=xrow, ycol=ycol, count=xrow.numel(), out=out)
+        count, dev = xrow.numel(), torch.cuda.current_device()
+        _check_index(xrow, "batch dot xrow", count, dev)
+        _check_index(ycol, "batch dot ycol", count, dev)
+        _check_tensor(out, "batch dot out", torch.float64, count, dev)
+        return self._add("dot", x=x, y=y, xrow=xrow, ycol=ycol, count=count, out=out)
 
     def dot_dense(self, x: BlazMatrix, xrow: torch.Tensor, v: torch.Tensor, out: torch.Tensor):
-        ld = 0 if v.dim() == 1 else v.stride(0)
-        return self._add("dot_dense", x=x, dense=v, ld=ld, xrow=xrow, count=xrow.numel(), out=out)
+        count, dev = xrow.numel(), torch.cuda.current_device()
+        _check_index(xrow, "batch dot_dense xrow", count, dev)
+        ld = _dense_vectors(v, x.cols, count, "batch dot_dense v", dev)
+        _check_tensor(out, "batch dot_dense out", torch.float64, count, dev)
+        return self._add("dot_dense", x=x, dense=v, ld=ld, xrow=xrow, count=count, out=out)
 
     def plan(self, device=None) -> "BatchPlan":
         n = len(self.items)
@@ -323,5 +420,9 @@ class BatchPlan:
         self._keep = keep
 
     def run(self, workgroups: int = 0):
+        stream, dev = _stream_dev()
+        if not _on_device(self.plan_dev, dev):
+            raise ValueError(f"BatchPlan.run: the plan lives on {self.plan_dev.device}, the current stream on "
+                             f"device {dev}")
         check(_lib.lib().blaz_batch_run(_ptr(self.plan_dev), self.n_plan, self.total_chunks, _ptr(self.counter),
-                                        int(workgroups), _stream()), "blaz_batch_run")
+                                        int(workgroups), stream), "blaz_batch_run")

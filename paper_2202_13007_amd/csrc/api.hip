@@ -200,10 +200,10 @@ static blaz_status matmul_impl(const blaz_matrix* a, const blaz_matrix* b, const
     if (check_shape(k, n) != BLAZ_OK) return BLAZ_ERR_SHAPE;
     if (m == 0 || n == 0) return BLAZ_OK;
     if (!c) return BLAZ_ERR_NULL;
-    if (ldc < n) return BLAZ_ERR_SHAPE;
+    if (blaz_status st = check_dense(m, n, ldc)) return st;
     if (!aligned(c, 8)) return BLAZ_ERR_ALIGN;
     if (!b && k > 0) {
-        if (ldb < n) return BLAZ_ERR_SHAPE;
+        if (blaz_status st = check_dense(k, n, ldb)) return st;
         if (!aligned(bdense, 16) || ldb % 2 != 0) return BLAZ_ERR_ALIGN;
     }
     const MatmulWorkspace wl = matmul_workspace(m, n, k, b != nullptr, prec);
@@ -312,7 +312,7 @@ BLAZ_API blaz_status blaz_matmul_compressed(const blaz_matrix* a, const blaz_mat
     if (c->rows != m || c->cols != n) return BLAZ_ERR_MISMATCH;
     if (m == 0 || n == 0) return BLAZ_OK;
     if (!b && k > 0) {
-        if (ldb < n) return BLAZ_ERR_SHAPE;
+        if (blaz_status st = check_dense(k, n, ldb)) return st;
         if (!aligned(bdense, 16) || ldb % 2 != 0) return BLAZ_ERR_ALIGN;
     }
     const size_t mm = matmul_workspace(m, n, k, b != nullptr, prec).total();

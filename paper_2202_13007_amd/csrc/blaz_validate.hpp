@@ -85,8 +85,20 @@ inline bool same_or_disjoint(const blaz_matrix& z, const blaz_matrix& x)
     return true;
 }
 
-// Bytes spanned by a rows x cols row-major matrix with leading dimension ld.
+// Bytes spanned by a rows x cols row-major matrix with leading dimension ld
+// (one that passed check_dense, so the product cannot overflow).
 inline int64_t dense_span(int64_t rows, int64_t cols, int64_t ld) { return rows == 0 ? 0 : ((rows - 1) * ld + cols) * 8; }
+
+// A dense rows x cols operand with leading dimension ld: ld >= cols, and the
+// offset of its last element below 2^60 elements, so that every element
+// offset the kernels form (and every byte span above) fits in int64.
+constexpr int64_t kMaxDenseElems = int64_t(1) << 60;
+inline blaz_status check_dense(int64_t rows, int64_t cols, int64_t ld)
+{
+    if (ld < cols) return BLAZ_ERR_SHAPE;
+    if (rows > 1 && ld > (kMaxDenseElems - cols) / (rows - 1)) return BLAZ_ERR_SHAPE;
+    return BLAZ_OK;
+}
 
 inline blaz_status hip_status(hipError_t e) { return e == hipSuccess ? BLAZ_OK : BLAZ_ERR_HIP; }
 
@@ -108,7 +120,7 @@ inline blaz_status validate_compress(const double* A, int64_t lda, const blaz_ma
     const int64_t nblk = nblocks(*out);
     if (nblk == 0) return BLAZ_OK;
     if (!A) return BLAZ_ERR_NULL;
-    if (lda < out->cols) return BLAZ_ERR_SHAPE;
+    if (blaz_status st = check_dense(out->rows, out->cols, lda)) return st;
     if (!aligned(A, 8) || (psi && !aligned(psi, 16))) return BLAZ_ERR_ALIGN;
     const Range ra = span(A, dense_span(out->rows, out->cols, lda));
     if (overlaps_matrix(ra, *out)) return BLAZ_ERR_ARG;
@@ -123,7 +135,7 @@ inline blaz_status validate_decompress(const blaz_matrix* in, const double* A, i
     if (blaz_status st = check_matrix(in)) return st;
     if (nblocks(*in) == 0) return BLAZ_OK;
     if (!A) return BLAZ_ERR_NULL;
-    if (lda < in->cols) return BLAZ_ERR_SHAPE;
+    if (blaz_status st = check_dense(in->rows, in->cols, lda)) return st;
     if (!aligned(A, 8)) return BLAZ_ERR_ALIGN;
     if (overlaps_matrix(span(A, dense_span(in->rows, in->cols, lda)), *in)) return BLAZ_ERR_ARG;
     *empty = false;
@@ -180,7 +192,8 @@ inline blaz_status validate_dot_dense(const blaz_matrix* x, const int64_t* xrow,
     if (blaz_status st = check_matrix(x)) return st;
     if (lines_of(*x) != 2) return BLAZ_ERR_UNSUPPORTED;
     if (count < 0 || count > kMaxDots || ldv < 0) return BLAZ_ERR_ARG;
-    if (ldv != 0 && ldv < x->cols) return BLAZ_ERR_SHAPE;
+    if (ldv != 0)
+        if (blaz_status st = check_dense(count, x->cols, ldv)) return st;
     if (count == 0) return BLAZ_OK;
     if (!xrow || !v || !out) return BLAZ_ERR_NULL;
     if (!aligned(xrow, 8) || !aligned(out, 8) || !aligned(v, 16) || ldv % 2 != 0) return BLAZ_ERR_ALIGN;

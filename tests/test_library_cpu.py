@@ -64,6 +64,45 @@ def test_shape_limits(L):
     assert L.blaz_matmul_workspace_bytes(8, 8, 12, 0, 0) == 0
 
 
+def test_leading_dimension_limit(L):
+    """A dense operand's last element must lie less than 2^60 elements past
+    its first, so that element offsets and byte spans fit in int64; a larger
+    ld is a shape error, not a wrapped overlap test."""
+    x = mat(16, 16, 0x100000)
+    big = (1 << 60) // 15 + 8                  # (rows - 1) * ld just over 2^60
+    ok = ((1 << 60) - 16) // 15 // 2 * 2       # the largest even ld allowed for 16 rows
+    A = 0x200000
+    assert L.blaz_compress(A, big, B(x), 0, None, None) == -2
+    assert L.blaz_decompress(B(x), A, big, None) == -2
+    assert L.blaz_compress(A, 1 << 62, B(x), 0, None, None) == -2   # (rows - 1) * ld would wrap
+    assert L.blaz_dot_dense(B(x), 0x300000, 0x500000, 1 << 62, 4, 0x400000, None) == -2
+    a, b = mat(16, 24, 0x100000), mat(24, 8, 0x200000)
+    need = L.blaz_matmul_workspace_bytes(16, 8, 24, 0, 0)
+    assert L.blaz_matmul(B(a), None, 0x500000, 8, 1 << 62, 0x300000, 8, 0, 0x400000, need, None) == -2
+    assert L.blaz_matmul(B(a), B(b), None, 8, 8, 0x300000, 1 << 62, 0, 0x400000, need, None) == -2
+    c = mat(16, 8, 0x300000)
+    needc = L.blaz_matmul_compressed_workspace_bytes(16, 8, 24, 0, 0)
+    assert L.blaz_matmul_compressed(B(a), None, 0x500000, 8, 1 << 62, B(c), 0, 0x400000, needc, 0, None) == -2
+    # at the bound the shape passes: the misaligned psi is the first error
+    assert L.blaz_compress(A, ok, B(x), 0, 0x300008, None) == -4
+
+
+def test_binding_rejects_host_tensors(L):
+    """The binding passes only CUDA tensors on the current device to the
+    library; a host tensor is refused before any call (no GPU needed)."""
+    import torch
+    import paper_2202_13007_amd as blaz
+    from paper_2202_13007_amd import api
+    with pytest.raises(ValueError):
+        api._check_dense(torch.zeros((16, 16), dtype=torch.float64), "A", 0)
+    with pytest.raises(ValueError):
+        api._check_index(torch.zeros(4, dtype=torch.int64), "xrow", 4, 0)
+    x = blaz.BlazMatrix(16, 16, torch.zeros(4, dtype=torch.float64), torch.zeros(4, dtype=torch.float64),
+                        torch.zeros(4, dtype=torch.uint8), torch.zeros((4, 28), dtype=torch.int8))
+    with pytest.raises(ValueError):
+        x.c(0)
+
+
 def test_status_strings(L):
     for st in range(-8, 1):
         assert len(L.blaz_status_string(st)) > 5
