@@ -60,12 +60,16 @@ def lib():
         sig = {
             "oracle_trace_size": ([], ctypes.c_size_t),
             "oracle_compress_block": ([P, P], None),
+            "oracle_compress_block_predicted": ([P, P], None),
+            "oracle_predicted_slopes": ([P, D, P, P], None),
+            "oracle_dct_of": ([P, P], None),
             "oracle_normalize": ([P, P], None),
             "oracle_idct": ([P, P], None),
             "oracle_inverse_normalize": ([D, D, P, P], None),
             "oracle_decompress_block": ([D, D, ctypes.c_int, P, P], None),
             "oracle_compress": ([P, I64, I64, I64, P, P, P, P, P, P, P], None),
-            "oracle_compress_blocks": ([P, I64, I64, P, I64, P, P, P, P, P, P], None),
+            "oracle_compress_predicted": ([P, I64, I64, I64, P, P, P, P, P, P, P], None),
+            "oracle_compress_blocks": ([P, I64, I64, P, I64, P, P, P, P, P, P, ctypes.c_int], None),
             "oracle_decompress": ([P, P, P, P, I64, I64, P, I64], None),
             "oracle_add": ([I64, P, P, P, P, P, P, P, P, P, P, P, P], None),
             "oracle_scale": ([I64, P, P, P, P, D, P, P, P, P], None),
@@ -111,14 +115,33 @@ class BlockTrace(ctypes.Structure):
         return np.array(getattr(self, name)).reshape(shape)
 
 
-def compress_block(M) -> BlockTrace:
-    """All five stages on one 8x8 block; returns the full trace."""
+def compress_block(M, predicted: bool = False) -> BlockTrace:
+    """All five stages on one 8x8 block; returns the full trace.  With
+    ``predicted`` the transform takes the predicted slopes (reading B)."""
     L = lib()
     assert L.oracle_trace_size() == ctypes.sizeof(BlockTrace)
     M = np.ascontiguousarray(M, dtype=np.float64).reshape(64)
     tr = BlockTrace()
-    L.oracle_compress_block(_p(M), ctypes.cast(ctypes.byref(tr), ctypes.c_void_p))
+    fn = L.oracle_compress_block_predicted if predicted else L.oracle_compress_block
+    fn(_p(M), ctypes.cast(ctypes.byref(tr), ctypes.c_void_p))
     return tr
+
+
+def predicted_slopes(dprime, s, psi):
+    """The grid points Eq. eqpredict selects, (s - s_max) + Psi * (2 s_max / 256)."""
+    dprime = np.ascontiguousarray(dprime, dtype=np.float64).reshape(64)
+    psi = np.ascontiguousarray(psi, dtype=np.uint8).reshape(64)
+    sp = np.zeros(64)
+    lib().oracle_predicted_slopes(_p(dprime), float(s), _p(psi), _p(sp))
+    return sp.reshape(8, 8)
+
+
+def dct_of(x):
+    """Eq. eqdct of an 8x8 input, D_00 summed in the fixed pairwise order."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(64)
+    D = np.zeros(64)
+    lib().oracle_dct_of(_p(x), _p(D))
+    return D.reshape(8, 8)
 
 
 class Compressed:
@@ -145,11 +168,12 @@ class Compressed:
                           self.codes.copy(), self.lines)
 
 
-def compress(A, with_debug: bool = False):
+def compress(A, with_debug: bool = False, predicted: bool = False):
     """Compress a rows x cols FP64 matrix (multiples of 8).
 
     With ``with_debug`` also returns (psi[nblk,64], code_x[nblk,28], phi_x[nblk]):
-    Psi and the values before truncation."""
+    Psi and the values before truncation.  ``predicted`` selects reading B
+    of the transform's input (the DCT of the predicted slopes)."""
     A = np.ascontiguousarray(A, dtype=np.float64)
     rows, cols = A.shape
     assert rows % 8 == 0 and cols % 8 == 0
@@ -160,14 +184,14 @@ def compress(A, with_debug: bool = False):
         psi = np.zeros((nb, 64), np.uint8)
         code_x = np.zeros((nb, NKEPT))
         phi_x = np.zeros(nb)
-    lib().oracle_compress(_p(A), rows, cols, cols, _p(out.f), _p(out.s), _p(out.phi), _p(out.codes),
-                          _p(psi), _p(code_x), _p(phi_x))
+    fn = lib().oracle_compress_predicted if predicted else lib().oracle_compress
+    fn(_p(A), rows, cols, cols, _p(out.f), _p(out.s), _p(out.phi), _p(out.codes), _p(psi), _p(code_x), _p(phi_x))
     if with_debug:
         return out, (psi, code_x, phi_x)
     return out
 
 
-def compress_blocks(A, blocks):
+def compress_blocks(A, blocks, predicted: bool = False):
     """Compress only the listed flat block indices of A (sampled comparison).
 
     Returns (f, s, phi, codes, code_x, phi_x) for those blocks."""
@@ -181,7 +205,7 @@ def compress_blocks(A, blocks):
     code_x = np.zeros((n, NKEPT))
     phi_x = np.zeros(n)
     lib().oracle_compress_blocks(_p(A), cols, cols, _p(blocks), n, _p(f), _p(s), _p(phi), _p(codes),
-                                 _p(code_x), _p(phi_x))
+                                 _p(code_x), _p(phi_x), int(predicted))
     return f, s, phi, codes, code_x, phi_x
 
 

@@ -176,6 +176,44 @@ void oracle_dct(const double delta[64], double s, const double dprime[64], doubl
     D[0] = s != 0.0 ? 0.125 * (pairwise64(delta) / s) : 0.0;
 }
 
+/* Reading B of the transform's input.  The paragraph on the transform names
+ * the normalized block, Eq. eqdct and Example 5 name Psi; read literally as
+ * "the slopes Psi predicts", the DCT takes the grid points Eq. eqpredict
+ * selects, sp_ij = (s - s_max) + Psi_ij * (2 s_max / 256), instead of
+ * Delta'.  (The default, reading A, takes Delta' and reproduces all 64
+ * printed values of Example 5; reading B reproduces 62, giving -52 for the
+ * printed -51 at (0,1) and (1,0).)  The grid points are evaluated as in
+ * oracle_predict.  With s_max = 0 every sp_ij is s, which is then 0. */
+void oracle_predicted_slopes(const double dprime[64], double s, const uint8_t psi[64], double sp[64])
+{
+    double smax = 0.0;
+    for (int e = 0; e < 64; ++e)
+        if (fabs(dprime[e]) > smax)
+            smax = fabs(dprime[e]);
+    double lo = s - smax;
+    double step = 2.0 * smax / 256.0;
+    for (int e = 0; e < 64; ++e)
+        sp[e] = lo + psi[e] * step;
+}
+
+/* Eq. eqdct of an arbitrary 8x8 input x: the 63 non-DC coefficients by the
+ * direct double sum, D_00 = alpha_0^2 sum x = 0.125 * pairwise(x), the fixed
+ * order the GPU reproduces. */
+void oracle_dct_of(const double x[64], double D[64])
+{
+    for (int i = 0; i < NB; ++i)
+        for (int j = 0; j < NB; ++j) {
+            if (i == 0 && j == 0)
+                continue;
+            double acc = 0.0;
+            for (int u = 0; u < NB; ++u)
+                for (int v = 0; v < NB; ++v)
+                    acc += x[u * NB + v] * dct_cos(i, u) * dct_cos(j, v);
+            D[i * NB + j] = alpha(i) * alpha(j) * acc;
+        }
+    D[0] = 0.125 * pairwise64(x);
+}
+
 /* Quantization (Section "Block Transform and Quantization", Eq. eqphi).
  * m = max |D_ij| over the whole 8x8 matrix D; phi = 127/m stored in 8 bits:
  * truncated (Example 5: 127/6.125 = 20.73 gives 20), clamped to 255 (phi can
@@ -250,6 +288,23 @@ void oracle_compress_block(const double M[64], oracle_block_trace *tr)
     oracle_dct(tr->delta, tr->s, tr->dprime, tr->D);
     oracle_quantize(tr->D, &tr->m, &tr->phi_x, &tr->phi, tr->code_x, tr->codes);
 }
+
+/* The same stages with the DCT of the predicted slopes (reading B); the
+ * trace's D holds that transform. */
+void oracle_compress_block_predicted(const double M[64], oracle_block_trace *tr)
+{
+    double sp[64];
+    tr->f = M[0];
+    oracle_normalize(M, tr->delta);
+    oracle_slope(tr->delta, &tr->K, &tr->s);
+    oracle_divide_by_slope(tr->delta, tr->s, tr->dprime);
+    oracle_predict(tr->dprime, tr->s, tr->psi);
+    oracle_predicted_slopes(tr->dprime, tr->s, tr->psi, sp);
+    oracle_dct_of(sp, tr->D);
+    oracle_quantize(tr->D, &tr->m, &tr->phi_x, &tr->phi, tr->code_x, tr->codes);
+}
+
+typedef void (*block_fn)(const double M[64], oracle_block_trace *tr);
 
 /* ------------------------------------------------------------------------ */
 /* Decompression (Section "Dot product", Eqs. eqbbb0 and eqbbb)              */
@@ -340,9 +395,9 @@ static void load_block(const double *A, int64_t lda, int64_t I, int64_t J, doubl
  * code_x and phi_x are optional (NULL) debug outputs: Psi per element
  * ([nblk][64]), phi*D before truncation ([nblk][28]) and 127/m
  * ([nblk]). */
-void oracle_compress(const double *A, int64_t rows, int64_t cols, int64_t lda,
-                     double *f, double *s, uint8_t *phi, int8_t *codes,
-                     uint8_t *psi, double *code_x, double *phi_x)
+static void compress_with(block_fn block, const double *A, int64_t rows, int64_t cols, int64_t lda,
+                          double *f, double *s, uint8_t *phi, int8_t *codes,
+                          uint8_t *psi, double *code_x, double *phi_x)
 {
     int64_t nbc = cols / NB, nbr = rows / NB;
     double M[64];
@@ -351,7 +406,7 @@ void oracle_compress(const double *A, int64_t rows, int64_t cols, int64_t lda,
         for (int64_t J = 0; J < nbc; ++J) {
             int64_t b = I * nbc + J;
             load_block(A, lda, I, J, M);
-            oracle_compress_block(M, &tr);
+            block(M, &tr);
             f[b] = tr.f;
             s[b] = tr.s;
             phi[b] = (uint8_t)tr.phi;
@@ -365,20 +420,37 @@ void oracle_compress(const double *A, int64_t rows, int64_t cols, int64_t lda,
         }
 }
 
+void oracle_compress(const double *A, int64_t rows, int64_t cols, int64_t lda,
+                     double *f, double *s, uint8_t *phi, int8_t *codes,
+                     uint8_t *psi, double *code_x, double *phi_x)
+{
+    compress_with(oracle_compress_block, A, rows, cols, lda, f, s, phi, codes, psi, code_x, phi_x);
+}
+
+/* Reading B (DCT of the predicted slopes), same outputs. */
+void oracle_compress_predicted(const double *A, int64_t rows, int64_t cols, int64_t lda,
+                               double *f, double *s, uint8_t *phi, int8_t *codes,
+                               uint8_t *psi, double *code_x, double *phi_x)
+{
+    compress_with(oracle_compress_block_predicted, A, rows, cols, lda, f, s, phi, codes, psi, code_x, phi_x);
+}
+
 /* Compress only the listed blocks (flat indices), for sampled comparisons at
- * sizes where compressing everything on the CPU would take too long. */
+ * sizes where compressing everything on the CPU would take too long;
+ * predicted != 0 selects reading B of the transform's input. */
 void oracle_compress_blocks(const double *A, int64_t cols, int64_t lda,
                             const int64_t *blocks, int64_t count,
                             double *f, double *s, uint8_t *phi, int8_t *codes,
-                            double *code_x, double *phi_x)
+                            double *code_x, double *phi_x, int predicted)
 {
     int64_t nbc = cols / NB;
     double M[64];
     oracle_block_trace tr;
+    block_fn block = predicted ? oracle_compress_block_predicted : oracle_compress_block;
     for (int64_t q = 0; q < count; ++q) {
         int64_t b = blocks[q];
         load_block(A, lda, b / nbc, b % nbc, M);
-        oracle_compress_block(M, &tr);
+        block(M, &tr);
         f[q] = tr.f;
         s[q] = tr.s;
         phi[q] = (uint8_t)tr.phi;
