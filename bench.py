@@ -332,6 +332,34 @@ def rates_leg(blaz, torch, dA, reps=10):
     return res
 
 
+def transform_input_leg(blaz, torch, dA, reps=10):
+    """The two readings of the transform's input on the first 8192^2 field:
+    the DCT of Delta' (the library's default) and the DCT of the predicted
+    slopes (Psi's grid points).  Median times and GB/s of 557 B per block,
+    the relative Frobenius error of each decoded field, the share of codes
+    that differ between the readings, and compress with the Psi side output."""
+    n = dA.shape[0]
+    norm = torch.linalg.norm(dA).item()
+    D = torch.empty_like(dA)
+    xa, xb = blaz.BlazMatrix.empty(n, n), blaz.BlazMatrix.empty(n, n)
+    psi = torch.empty((xa.nblk, 64), dtype=torch.uint8, device="cuda")
+    nblk = xa.nblk
+    res = {}
+    for name, fn, out in (("delta_prime", lambda: blaz.compress(dA, out=xa), xa),
+                          ("predicted_slopes", lambda: blaz.compress_predicted(dA, out=xb), xb)):
+        t = median(timed_each(torch, fn, reps))
+        blaz.decompress(out, out=D)
+        err = torch.linalg.norm(D - dA).item() / norm
+        res[name] = {"compress_ms": round(t, 4), "compress_GBps": round((BLOCK + 45) * nblk / t / 1e6, 1),
+                     "rel_err": float(f"{err:.4e}")}
+    tp = median(timed_each(torch, lambda: blaz.compress(dA, out=xa, psi=psi), reps))
+    res["delta_prime"]["with_psi_ms"] = round(tp, 4)
+    res["codes_differing"] = float(f"{(xa.codes != xb.codes).float().mean().item():.4e}")
+    res["phi_differing"] = float(f"{(xa.phi != xb.phi).float().mean().item():.4e}")
+    del D, xa, xb, psi
+    return res
+
+
 def mixed_leg(blaz, torch, workload_inputs, reps=10):
     """The 16384x16384 field compressed with the transform in FP64, FP32 and
     BF16x3.  Codes and phi are compared with the FP64 path's; errors of the
@@ -566,6 +594,8 @@ def main():
     if not args.no_extra:
         print("# tunable-rate leg", file=sys.stderr, flush=True)
         result["rates_8192"] = rates_leg(blaz, torch, dA)
+        print("# transform-input leg", file=sys.stderr, flush=True)
+        result["transform_input_8192"] = transform_input_leg(blaz, torch, dA)
     if args.serve_requests > 0:
         result["serving"] = serving_leg(torch, dA, dB, args.serve_requests, args.serve_budget_gib)
     del dA, dB

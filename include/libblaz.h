@@ -120,16 +120,34 @@ size_t blaz_compressed_bytes_lines(int64_t rows, int64_t cols, int64_t lines);
  * 8x8 block of A (out->rows x out->cols, leading dimension lda >= cols,
  * 8-byte aligned) into *out.
  * psi: optional ([nblk][64] uint8, row-major within the block) receives the
- *   prediction indexes Psi of Eq. eqpredict.  They are not part of the stored
- *   stream: the transform is applied to the normalized block (the reading
- *   under which Example 5 is reproduced), so Psi is a side output.  NULL
- *   skips it.
+ *   prediction indexes Psi of Eq. eqpredict: for each element the first index
+ *   of the grid point nearest to Delta'_ij = Delta_ij / s, as a search over
+ *   all 256 points in increasing order finds it.  They are not part of the
+ *   stored stream: the transform is applied to the normalized block (the
+ *   reading under which Example 5 is reproduced), so Psi is a side output
+ *   and the record does not depend on whether it is requested.  NULL skips
+ *   it.
  * prec: BLAZ_PREC_FP64 runs every stage in binary64.  BLAZ_PREC_FP32 and
  *   BLAZ_PREC_BF16X3 run the 63 non-DC DCT coefficients in that arithmetic on
  *   MFMA; normalization, slope, DC term, phi and truncation stay binary64.
  * A and the output arrays must not overlap. */
 blaz_status blaz_compress(const double *A, int64_t lda, const blaz_matrix *out, blaz_precision prec,
                           uint8_t *psi, hipStream_t stream);
+
+/* Compression under the other reading of the transform's input (Section
+ * "Compression Scheme", paragraph "Block Transform and Quantization": the
+ * text names the normalized block, Eq. eqdct and Example 5 name Psi).  Here
+ * the DCT-II takes the predicted slopes, the grid points
+ * (s - s_max) + Psi_ij * (2 s_max / 256) of Eq. eqpredict that Psi selects,
+ * with D_00 = 0.125 * (their sum in the pairwise order of the slope);
+ * everything else, the record format and blaz_decompress are those of
+ * blaz_compress (binary64).  On Example 5 this reading gives 62 of the 64
+ * printed values (-52 for the printed -51 at (0,1) and (1,0)).
+ * psi: optional side output as in blaz_compress.  out must hold two kept
+ * lines (lines 0 or 2), else BLAZ_ERR_UNSUPPORTED; other arguments and
+ * errors as blaz_compress with BLAZ_PREC_FP64. */
+blaz_status blaz_compress_predicted(const double *A, int64_t lda, const blaz_matrix *out, uint8_t *psi,
+                                    hipStream_t stream);
 
 /* Decompression: dequantize (C/phi at the kept positions, zero elsewhere;
  * Section "Dot product"), inverse DCT, and the inverse of the normalization

@@ -21,7 +21,8 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 # Every symbol include/libblaz.h declares.
 EXPORTS = (
-    "blaz_block_count", "blaz_compressed_bytes", "blaz_code_stride", "blaz_compressed_bytes_lines", "blaz_compress", "blaz_decompress", "blaz_add",
+    "blaz_block_count", "blaz_compressed_bytes", "blaz_code_stride", "blaz_compressed_bytes_lines", "blaz_compress", "blaz_compress_predicted",
+    "blaz_decompress", "blaz_add",
     "blaz_sub", "blaz_scale", "blaz_dot", "blaz_dot_dense", "blaz_matmul_workspace_bytes",
     "blaz_matmul", "blaz_matmul_tiled", "blaz_matmul_compressed_workspace_bytes", "blaz_matmul_compressed",
     "blaz_diagnose", "blaz_status_string", "blaz_batch_plan_bytes", "blaz_batch_plan", "blaz_batch_run",
@@ -95,6 +96,7 @@ def lib():
         "blaz_code_stride": ([I64], I64),
         "blaz_compressed_bytes_lines": ([I64, I64, I64], ctypes.c_size_t),
         "blaz_compress": ([P, I64, M, I, P, P], I),
+        "blaz_compress_predicted": ([P, I64, M, P, P], I),
         "blaz_decompress": ([M, P, I64, P], I),
         "blaz_add": ([M, M, M, P], I),
         "blaz_sub": ([M, M, M, P], I),

@@ -166,6 +166,26 @@ def compress(A: torch.Tensor, out: BlazMatrix | None = None, prec: str = "fp64",
     return out
 
 
+def compress_predicted(A: torch.Tensor, out: BlazMatrix | None = None,
+                       psi: torch.Tensor | None = None) -> BlazMatrix:
+    """Compression whose DCT takes the predicted slopes of Eq. eqpredict
+    instead of the normalized block (the other reading of the transform's
+    input); same record format, decompressed by ``decompress``."""
+    stream, dev = _stream_dev()
+    _check_dense(A, "compress_predicted", dev)
+    rows, cols = A.shape
+    if out is None:
+        out = BlazMatrix.empty(rows, cols, A.device)
+    elif (out.rows, out.cols) != (rows, cols):
+        raise ValueError(f"compress_predicted: out is {out.rows} x {out.cols}, A is {rows} x {cols}")
+    if psi is not None:
+        _check_tensor(psi, "compress_predicted psi", torch.uint8, 64 * out.nblk, dev)
+    m = out.c(dev)
+    check(_lib.lib().blaz_compress_predicted(_ptr(A), A.stride(0), ctypes.byref(m), _ptr(psi), stream),
+          "blaz_compress_predicted")
+    return out
+
+
 def decompress(x: BlazMatrix, out: torch.Tensor | None = None) -> torch.Tensor:
     stream, dev = _stream_dev()
     if out is None:

@@ -48,6 +48,16 @@ BLAZ_API blaz_status blaz_compress(const double* A, int64_t lda, const blaz_matr
     return hip_status(blaz::detail::launch_compress_mixed(A, lda, *out, psi, prec, stream));
 }
 
+BLAZ_API blaz_status blaz_compress_predicted(const double* A, int64_t lda, const blaz_matrix* out, uint8_t* psi,
+                                             hipStream_t stream)
+{
+    bool empty;
+    if (blaz_status st = validate_compress(A, lda, out, BLAZ_PREC_FP64, psi, &empty)) return st;
+    if (lines_of(*out) != 2) return BLAZ_ERR_UNSUPPORTED;
+    if (empty) return BLAZ_OK;
+    return hip_status(blaz::detail::launch_compress_predicted(A, lda, *out, psi, stream));
+}
+
 BLAZ_API blaz_status blaz_decompress(const blaz_matrix* in, double* A, int64_t lda, hipStream_t stream)
 {
     bool empty;

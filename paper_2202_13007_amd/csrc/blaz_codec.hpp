@@ -156,8 +156,8 @@ struct SlopeOut {
 };
 
 // Normalization (Eq. eqnorm) and mean slope (Eqs. eqslope, eqslope2), all
-// binary64: x holds the block on entry and Delta' = Delta / s on exit.
-__device__ __forceinline__ SlopeOut normalize_and_slope(double x[64])
+// binary64: x holds the block on entry and Delta on exit.
+__device__ __forceinline__ SlopeOut slope_of(double x[64])
 {
     SlopeOut o;
     o.f = x[0];
@@ -170,41 +170,83 @@ __device__ __forceinline__ SlopeOut normalize_and_slope(double x[64])
     o.s = K > 0 ? S1 / (double)K : 0.0;
     // D_00 = alpha_0^2 sum Delta' = 0.125 (sum Delta / s), the fixed order.
     o.dc = o.s != 0.0 ? 0.125 * (S / o.s) : 0.0;
-    // Delta' = Delta / s.  The reciprocal is exact enough for the 63 other
-    // coefficients; a slope so small that 1/s overflows falls back to division.
-    if (o.s != 0.0 && fabs(o.s) >= 0x1p-1020) {
-        const double r = 1.0 / o.s;
-#pragma unroll
-        for (int e = 0; e < 64; ++e) x[e] *= r;
-    } else if (o.s != 0.0) {
-#pragma unroll
-        for (int e = 0; e < 64; ++e) x[e] = x[e] / o.s;
-    }
     return o;
 }
 
-// Prediction, Eq. eqpredict: index of the nearest of 256 points
-// s - smax + k * (2 smax / 256), the smaller index on a tie; written to
-// psi[b][64] (a side output, not part of the stream).
-__device__ __forceinline__ void predict_store(const double x[64], double s, uint8_t* psi, int64_t b, bool valid)
+// Delta' = Delta / s in place.  The reciprocal is exact enough for the 63
+// non-DC coefficients; a slope so small that 1/s overflows falls back to
+// division.
+__device__ __forceinline__ void divide_by_slope(double x[64], double s)
 {
-    double smax = 0.0;
+    if (s != 0.0 && fabs(s) >= 0x1p-1020) {
+        const double r = 1.0 / s;
 #pragma unroll
-    for (int e = 0; e < 64; ++e) smax = fmax(smax, fabs(x[e]));
+        for (int e = 0; e < 64; ++e) x[e] *= r;
+    } else if (s != 0.0) {
+#pragma unroll
+        for (int e = 0; e < 64; ++e) x[e] = x[e] / s;
+    }
+}
+
+// Prediction, Eq. eqpredict, of a block from Delta (x on entry, as slope_of
+// leaves it).  Psi_e is the index of the grid point
+// g(k) = (s - s_max) + k * (2 s_max / 256), k = 0..255, nearest to
+// Delta'_e = Delta_e / s, as a search over all 256 points in increasing k
+// finds it: the first index of the smallest computed distance |Delta' - g(k)|.
+// s_max = max |Delta'| = max |Delta| / s (division rounds monotonically; s is
+// a mean of absolute values, so s >= 0).
+//
+// Where the grid points are well apart in binary64 (|lo| <= 2^30 step,
+// lo = s - s_max) every computed distance is within 2^-22 step of the exact
+// one.  So when Delta''s position (Delta' - lo) / step lies more than 1e-6
+// from a half-way point, the nearest point is the unambiguous answer
+// (Delta * (1/s) is close enough for this test); otherwise the answer is the
+// nearer of the two points around the half-way point by their computed
+// distances from Delta_e / s, the lower one on a tie.  With the grid not
+// well apart, lo > 2^23 s_max lies above every Delta', whose distances then
+// grow with k: index 0.  Non-finite slopes give index 0, as the search
+// does.
+//
+// kStore: write Psi to psi[b][64] (a side output, not part of the stream).
+// kReplace: replace x by the predicted slopes g(Psi_e) and o.dc by their DC
+// term 0.125 * (pairwise sum), the transform's input under the reading that
+// the DCT takes the predicted slopes; otherwise x keeps Delta.
+template <bool kStore, bool kReplace>
+__device__ __forceinline__ void predict_block(double x[64], SlopeOut& o, uint8_t* psi, int64_t b, bool valid)
+{
+    double amax = 0.0;
+#pragma unroll
+    for (int e = 0; e < 64; ++e) amax = fmax(amax, fabs(x[e]));
+    const double smax = o.s != 0.0 ? amax / fabs(o.s) : 0.0;
+    const double lo = o.s - smax;
+    const double step = 2.0 * smax / 256.0;
+    const double inv_step = 128.0 / smax;
+    const double r = 1.0 / o.s;
+    const bool by_division = !isfinite(r);  // a subnormal slope
+    const bool wide = smax != 0.0 && isfinite(step) && fabs(lo) <= 0x1p30 * step;  // false for NaN
     uint32_t w[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) w[q] = 0;
-    if (smax != 0.0) {
-        const double lo = s - smax;
-        const double inv_step = 128.0 / smax;
 #pragma unroll
-        for (int e = 0; e < 64; ++e) {
-            double k = ceil((x[e] - lo) * inv_step - 0.5);
-            k = fmin(fmax(k, 0.0), 255.0);
-            w[e / 4] |= (uint32_t)k << (8 * (e % 4));
+    for (int e = 0; e < 64; ++e) {
+        int k = 0;
+        if (wide) {
+            const double pos = ((by_division ? x[e] / o.s : x[e] * r) - lo) * inv_step;
+            double kd = rint(pos);
+            if (!(fabs(pos - kd) < 0.5 - 1e-6)) {  // near a half-way point
+                const double lower = floor(pos);
+                const double xe = x[e] / o.s;
+                const double d0 = fabs(xe - (lo + lower * step));
+                const double d1 = fabs(xe - (lo + (lower + 1.0) * step));
+                kd = d1 < d0 ? lower + 1.0 : lower;
+            }
+            k = (int)fmin(fmax(kd, 0.0), 255.0);
         }
+        w[e / 4] |= (uint32_t)k << (8 * (e % 4));
+        if constexpr (kReplace) x[e] = lo + (double)k * step;
     }
-    if (valid) {
+    if constexpr (kReplace) o.dc = 0.125 * pairwise64([&](int e) { return x[e]; });
+    if (kStore && valid) {
         uint4* dst = reinterpret_cast<uint4*>(psi + b * 64);
 #pragma unroll
         for (int q = 0; q < 4; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
@@ -336,7 +378,9 @@ struct OutBF16Split {
 
 // Compression (all stages binary64) of the blocks wave_base .. wave_base+63
 // (one per lane) of A; tile is the wave's LDS staging area.
-template <bool kVec, bool kPsi, int L = 2>
+// kPred: the transform takes the predicted slopes instead of Delta' (the
+// other reading of the transform's input; the stream format is the same).
+template <bool kVec, bool kPsi, int L = 2, bool kPred = false>
 __device__ __forceinline__ void compress_wave(const double* __restrict__ A, int64_t lda, int64_t nbc, int64_t nblk,
                                               double* __restrict__ fo, double* __restrict__ so,
                                               uint8_t* __restrict__ phio, uint32_t* __restrict__ codes,
@@ -344,11 +388,14 @@ __device__ __forceinline__ void compress_wave(const double* __restrict__ A, int6
 {
     double x[64];
     load_blocks<kVec>(A, lda, nbc, nblk, wave_base, lane, tile, x);
-    const SlopeOut so_ = normalize_and_slope(x);
-    if constexpr (kPsi) predict_store(x, so_.s, psi, wave_base + lane, wave_base + lane < nblk);
+    SlopeOut so_ = slope_of(x);
+    if constexpr (kPsi || kPred)
+        predict_block<kPsi, kPred>(x, so_, psi, wave_base + lane, wave_base + lane < nblk);
+    if constexpr (!kPred) divide_by_slope(x, so_.s);
 
-    // Two-dimensional DCT-II (Eq. eqdct) of Delta': rows, then columns, in
-    // place; the DC term is the fixed-order binary64 value.
+    // Two-dimensional DCT-II (Eq. eqdct) of Delta' (or of the predicted
+    // slopes): rows, then columns, in place; the DC term is the fixed-order
+    // binary64 value.
 #pragma unroll
     for (int u = 0; u < 8; ++u) dct8<1, 1>(x + u * 8, x + u * 8);
 #pragma unroll

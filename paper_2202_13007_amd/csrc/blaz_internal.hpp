@@ -34,6 +34,9 @@ inline hipError_t dispatch_lines(const blaz_matrix& m, F&& f)
 int device_cu_count();
 
 hipError_t launch_compress_f64(const double* A, int64_t lda, const blaz_matrix& m, uint8_t* psi, hipStream_t st);
+// Compression whose transform takes the predicted slopes (two kept lines).
+hipError_t launch_compress_predicted(const double* A, int64_t lda, const blaz_matrix& m, uint8_t* psi,
+                                     hipStream_t st);
 // Compression with the transform stage in FP32 or BF16x3 on MFMA.
 hipError_t launch_compress_mixed(const double* A, int64_t lda, const blaz_matrix& m, uint8_t* psi,
                                  blaz_precision prec, hipStream_t st);

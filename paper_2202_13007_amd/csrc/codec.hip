@@ -15,7 +15,7 @@
 
 namespace blaz {
 
-template <bool kVec, bool kPsi, int L = 2>
+template <bool kVec, bool kPsi, int L = 2, bool kPred = false>
 __global__ __launch_bounds__(kWave) void compress_f64_kernel(const double* __restrict__ A, int64_t lda,
                                                              int64_t nbc, int64_t nblk, double* __restrict__ fo,
                                                              double* __restrict__ so, uint8_t* __restrict__ phio,
@@ -23,8 +23,8 @@ __global__ __launch_bounds__(kWave) void compress_f64_kernel(const double* __res
                                                              uint8_t* __restrict__ psi)
 {
     __shared__ __align__(16) double tile[kWave * kSlot];
-    compress_wave<kVec, kPsi, L>(A, lda, nbc, nblk, fo, so, phio, codes, psi, (int64_t)blockIdx.x * kWave,
-                                 (int)threadIdx.x, tile);
+    compress_wave<kVec, kPsi, L, kPred>(A, lda, nbc, nblk, fo, so, phio, codes, psi, (int64_t)blockIdx.x * kWave,
+                                        (int)threadIdx.x, tile);
 }
 
 template <bool kVec, typename Out, int L = 2>
@@ -68,6 +68,28 @@ hipError_t launch_compress_f64(const double* A, int64_t lda, const blaz_matrix& 
         compress_f64_kernel<false, true><<<grid, kWave, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw, psi);
     else
         compress_f64_kernel<false, false><<<grid, kWave, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw, psi);
+    return hipGetLastError();
+}
+
+hipError_t launch_compress_predicted(const double* A, int64_t lda, const blaz_matrix& m, uint8_t* psi,
+                                     hipStream_t st)
+{
+    const int64_t nbc = m.cols / 8;
+    const int64_t nblk = (m.rows / 8) * nbc;
+    const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % 2 == 0);
+    const unsigned grid = grid_for(nblk);
+    auto* cw = reinterpret_cast<uint32_t*>(m.codes);
+    if (vec && psi)
+        compress_f64_kernel<true, true, 2, true><<<grid, kWave, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw, psi);
+    else if (vec)
+        compress_f64_kernel<true, false, 2, true><<<grid, kWave, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw,
+                                                                         psi);
+    else if (psi)
+        compress_f64_kernel<false, true, 2, true><<<grid, kWave, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw,
+                                                                         psi);
+    else
+        compress_f64_kernel<false, false, 2, true><<<grid, kWave, 0, st>>>(A, lda, nbc, nblk, m.f, m.s, m.phi, cw,
+                                                                          psi);
     return hipGetLastError();
 }
 

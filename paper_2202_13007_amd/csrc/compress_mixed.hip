@@ -89,8 +89,9 @@ __global__ __launch_bounds__(kWave, 2) void compress_mixed_kernel(const double* 
 
     double x[64];
     load_blocks<kVec>(A, lda, nbc, nblk, wave_base, lane, reinterpret_cast<double*>(smem), x);
-    const SlopeOut so_ = normalize_and_slope(x);
-    if constexpr (kPsi) predict_store(x, so_.s, psi, wave_base + lane, wave_base + lane < nblk);
+    SlopeOut so_ = slope_of(x);
+    if constexpr (kPsi) predict_block<true, false>(x, so_, psi, wave_base + lane, wave_base + lane < nblk);
+    divide_by_slope(x, so_.s);
 
     f32x4 acc[4][4];
 #pragma unroll

@@ -113,19 +113,15 @@ def test_compress_special_blocks():
 
 
 def test_compress_prediction_side_output():
-    """Eq. eqpredict: Psi equals the oracle's brute-force argmin except at
-    half-way ties."""
+    """Eq. eqpredict: Psi equals the oracle's brute-force argmin over the 256
+    grid points exactly (half-way ties and huge or tiny slopes included), and
+    requesting it leaves the record unchanged."""
     A = np.vstack([smooth_field(64, 4, 2.0, 1e-3, 5), special_blocks()[:, :64]])
     g, psi = gpu_compress(A, psi=True)
     o, (opsi, _, _) = oracle.compress(A, with_debug=True)
-    diff = psi.astype(int) - opsi.astype(int)
-    for b, e in zip(*np.nonzero(diff)):
-        I, J = divmod(b, A.shape[1] // 8)
-        tr = oracle.compress_block(A[8 * I:8 * I + 8, 8 * J:8 * J + 8])
-        dp = tr.arr("dprime").ravel()[e]
-        smax = np.max(np.abs(tr.arr("dprime")))
-        q = (dp - (tr.s - smax)) / (2 * smax / 256)
-        assert abs(diff[b, e]) == 1 and abs(q - np.floor(q) - 0.5) < 1e-9, f"psi block {b} elt {e}"
+    np.testing.assert_array_equal(psi, opsi)
+    plain, _ = gpu_compress(A)
+    assert_same_compressed(host(g), host(plain), "record with and without psi")
 
 
 def test_compress_full_size_8192_sampled():

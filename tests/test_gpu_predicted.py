@@ -1,0 +1,94 @@
+"""GPU parity of blaz_compress_predicted, the reading of the transform's
+input under which the DCT takes the predicted slopes of Eq. eqpredict,
+against the oracle's reading B: f, s and Psi bit-exact, phi and the codes
+bit-exact except classified rounding-boundary ties (the non-DC coefficients
+are summed in another order), the DC term in the same pairwise order."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2202_13007_amd as blaz
+from parity import TIE_RATE_MAX, assert_same_compressed, compare_compressed
+from synth import smooth_field, workload_inputs
+from test_gpu_parity import special_blocks
+from test_oracle import example1
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run(A, psi=True):
+    t = A if isinstance(A, torch.Tensor) else dev(A)
+    nb = (t.shape[0] // 8) * (t.shape[1] // 8)
+    p = torch.empty((max(nb, 1), 64), dtype=torch.uint8, device="cuda") if psi else None
+    g = blaz.compress_predicted(t, psi=p)
+    torch.cuda.synchronize()
+    return g.to_host(), (p.cpu().numpy() if psi else None)
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (264, 520), (1032, 528)])
+def test_compress_predicted_matches_oracle(shape):
+    r, c = shape
+    A = smooth_field(r, 6, 3.0, 1e-3, 600 + r, cols=c)
+    got, psi = run(A)
+    want, (opsi, cx, px) = oracle.compress(A, with_debug=True, predicted=True)
+    np.testing.assert_array_equal(psi, opsi)
+    ties = compare_compressed(got, (want.f, want.s, want.phi, want.codes), cx, px, f"predicted {shape}")
+    assert ties <= TIE_RATE_MAX * cx.size + 2
+
+
+def test_compress_predicted_example1_and_special_blocks():
+    """Example 1 gives phi 20 and the codes of reading B (-52 where Example 5
+    prints -51); the designed blocks (constant, sparse, 1e300 and 1e-300
+    magnitudes, ...) match the oracle."""
+    A = np.vstack([np.hstack([example1()] * 12), special_blocks()])
+    got, psi = run(A)
+    want, (opsi, cx, px) = oracle.compress(A, with_debug=True, predicted=True)
+    np.testing.assert_array_equal(psi, opsi)
+    ties = compare_compressed(got, (want.f, want.s, want.phi, want.codes), cx, px, "predicted special")
+    assert ties <= 8
+    f, s, phi, codes = got
+    assert phi[0] == 20 and codes[0][1] == -52 and codes[0][8] == -52
+
+
+def test_record_does_not_depend_on_psi_and_unaligned_input():
+    A = smooth_field(64, 4, 2.0, 1e-3, 610)
+    with_psi, _ = run(A)
+    without, _ = run(A, psi=False)
+    assert_same_compressed(with_psi, without, "predicted with and without psi")
+    big = np.zeros((64, 66))
+    big[:, 1:65] = A
+    unaligned, _ = run(dev(big)[:, 1:65], psi=False)  # 8-byte aligned only: the per-lane load path
+    assert_same_compressed(unaligned, without, "predicted, unaligned input")
+
+
+def test_compress_predicted_rejects_other_rates_and_decompresses():
+    A = smooth_field(64, 4, 2.0, 1e-3, 611)
+    with pytest.raises(blaz.BlazError) as e:
+        blaz.compress_predicted(dev(A), out=blaz.BlazMatrix.empty(64, 64, lines=3))
+    assert e.value.status == -6
+    g = blaz.compress_predicted(dev(A))
+    o, (_, cx, px) = oracle.compress(A, with_debug=True, predicted=True)
+    compare_compressed(g.to_host(), (o.f, o.s, o.phi, o.codes), cx, px, "predicted 64")
+    # the records are decompressed like any other
+    rec = blaz.BlazMatrix.from_host(o.rows, o.cols, o.f, o.s, o.phi, o.codes)
+    got = blaz.decompress(rec).cpu().numpy()
+    want = oracle.decompress(o)
+    assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.abs(want).max())
+
+
+def test_compress_predicted_full_size_8192_sampled():
+    """The 8192^2 field: every block on the GPU, 1500 sampled blocks on the
+    oracle."""
+    A, _ = workload_inputs("plain-8192")
+    (gf, gs, gphi, gcodes), _ = run(A, psi=False)
+    rng = np.random.default_rng(7)
+    sample = np.unique(np.concatenate([[0, 1023, 1024, len(gf) - 1], rng.integers(0, len(gf), 1500)]))
+    of, os_, ophi, ocodes, code_x, phi_x = oracle.compress_blocks(A, sample, predicted=True)
+    ties = compare_compressed((gf[sample], gs[sample], gphi[sample], gcodes[sample]),
+                              (of, os_, ophi, ocodes), code_x, phi_x, "predicted 8192 sampled")
+    assert ties <= 2
