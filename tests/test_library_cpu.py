@@ -140,6 +140,21 @@ def test_compress_validation(L):
     assert L.blaz_compress(None, 16, B(empty), 0, None, None) == 0    # empty: no-op
 
 
+def test_compress_predicted_validation(L):
+    out = mat(16, 16, 0x100000)
+    A = 0x200000
+    f = L.blaz_compress_predicted
+    assert f(None, 16, B(out), None, None) == -1
+    assert f(A, 8, B(out), None, None) == -2                  # lda < cols
+    assert f(A + 4, 16, B(out), None, None) == -4             # misaligned A
+    assert f(A, 16, B(out), 0x300008, None) == -4             # psi not 16-aligned
+    assert f(0x100000, 16, B(out), None, None) == -5          # A overlaps the output
+    three = mat(16, 16, 0x100000)
+    three.lines = 3
+    assert f(A, 16, B(three), None, None) == -6               # two kept lines only
+    assert f(None, 16, B(mat(0, 16, 0)), None, None) == 0     # empty: no-op
+
+
 def test_decompress_validation(L):
     x = mat(16, 16, 0x100000)
     assert L.blaz_decompress(B(x), None, 16, None) == -1
