@@ -338,7 +338,9 @@ __global__ __launch_bounds__(256) void convert_f32_kernel(const double* __restri
 
 // Dense binary64 (k x n, ldb) to its transpose split into BF16 hi + lo
 // (n x k, ld k), through a 64 x 64 LDS tile so that both the reads (along
-// n) and the writes (along k) are contiguous.
+// n) and the writes (along k) are contiguous.  Each thread writes two
+// consecutive k of one row of the transpose as one 4-byte pair (k is a
+// multiple of 8, so a pair never crosses the end of a row).
 __global__ __launch_bounds__(256) void convert_bf16_split_t_kernel(const double* __restrict__ B, int64_t ldb,
                                                                    __bf16* __restrict__ hi, __bf16* __restrict__ lo,
                                                                    int64_t k, int64_t n)
@@ -353,15 +355,18 @@ __global__ __launch_bounds__(256) void convert_bf16_split_t_kernel(const double*
         t[kk][tx] = ok ? B[(k0 + kk) * ldb + n0 + tx] : 0.0;
     }
     __syncthreads();
+    const int kp = threadIdx.x & 31, nr = threadIdx.x >> 5;  // 32 k pairs x 8 rows
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int nn = ty + 4 * r;
-        if (n0 + nn < n && k0 + tx < k) {
-            const double x = t[tx][nn];
-            const __bf16 h = (__bf16)(float)x;
-            const __bf16 l = (__bf16)(float)(x - (double)(float)h);
-            hi[(n0 + nn) * k + k0 + tx] = h;
-            lo[(n0 + nn) * k + k0 + tx] = l;
+    for (int r = 0; r < 8; ++r) {
+        const int nn = nr + 8 * r;
+        if (n0 + nn < n && k0 + 2 * kp < k) {
+            const double x0 = t[2 * kp][nn], x1 = t[2 * kp + 1][nn];
+            // hi = bf16(x), lo = bf16(x - hi), as the rebuild of A splits
+            const __bf16 h0 = (__bf16)(float)x0, h1 = (__bf16)(float)x1;
+            const __bf16 l0 = (__bf16)(float)(x0 - (double)(float)h0), l1 = (__bf16)(float)(x1 - (double)(float)h1);
+            const int64_t off = (n0 + nn) * k + k0 + 2 * kp;
+            *reinterpret_cast<bf16x2*>(hi + off) = bf16x2{h0, h1};
+            *reinterpret_cast<bf16x2*>(lo + off) = bf16x2{l0, l1};
         }
     }
 }
