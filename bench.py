@@ -154,19 +154,28 @@ def matmul_leg(blaz, torch, workload_inputs):
     runs = [(p, (lambda p=p: blaz.matmul(g, dB, out=outs[p], prec=p, workspace=ws))) for p in ("fp64", "fp32", "bf16x3")]
     runs.append(("plain", lambda: torch.matmul(Ad, dB, out=outs["plain"])))
     peaks = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3, "plain": 78.6}
+    # three interleaved rounds of 5 back-to-back launches per variant, median
+    # round: the clock drifts with the power draw of FP64 matrix work, so a
+    # fixed order would favour whichever variant runs in the better state
+    per = {name: [] for name, _ in runs}
     for name, fn in runs:
         fn()
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(5):
-            fn()
-        b.record()
-        torch.cuda.synchronize()
-        ms = a.elapsed_time(b) / 5
+    torch.cuda.synchronize()
+    for _ in range(3):
+        for name, fn in runs:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(5):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            per[name].append(a.elapsed_time(b) / 5)
+    for name, _ in runs:
+        ms = median(per[name])
         tf = 2 * n ** 3 / ms / 1e9
-        legs[name] = {"ms": round(ms, 4), "TFLOPs": round(tf, 2), "mfma_frac": round(tf / peaks[name], 4)}
+        legs[name] = {"ms": round(ms, 4), "TFLOPs": round(tf, 2), "mfma_frac": round(tf / peaks[name], 4),
+                      "rounds_ms": [round(t, 4) for t in per[name]]}
     # the product recompressed (results kept in the 45-byte form)
     gB = blaz.compress(dB)
     wsc = torch.empty(max(blaz.matmul_compressed_workspace_bytes(n, n, n, True, p) for p in ("fp64", "bf16x3")),
