@@ -396,6 +396,36 @@ def test_dot_dense_full_size_4096_sampled():
     assert_dots_close(got[smp], want, mag, what="dot_dense 4096")
 
 
+def band_col(og: oracle.Compressed, j: int) -> np.ndarray:
+    """Column j of a compressed matrix, decompressed by the oracle (its block column only)."""
+    nbr, nbc = og.rows // 8, og.cols // 8
+    idx = np.arange(nbr) * nbc + j // 8
+    band = oracle.Compressed(og.rows, 8, og.f[idx], og.s[idx], og.phi[idx], og.codes[idx])
+    return oracle.decompress(band)[:, j % 8]
+
+
+def test_dot_compressed_and_shared_vector_full_size_4096_sampled():
+    """The two other 4096 dot workloads as timed: row i of A with column i
+    of a compressed B (aligned groups of 8 lines and 8 columns), and every
+    row of A with one shared vector."""
+    A, B, V = workload_inputs("linalg-4096")
+    g, _ = gpu_compress(A)
+    gb, _ = gpu_compress(B)
+    rows = np.arange(4096)
+    og = oracle.Compressed(4096, 4096, *host(g))
+    ob = oracle.Compressed(4096, 4096, *host(gb))
+    smp = np.array([0, 7, 8, 2047, 4095] + list(np.random.default_rng(5).integers(0, 4096, 15)))
+    got = blaz.dot(g, dev(rows), gb, dev(rows)).cpu().numpy()
+    want = oracle.dot(og, rows[smp], ob, rows[smp])
+    mag = np.array([np.abs(band_rows(og, int(i))) @ np.abs(band_col(ob, int(i))) for i in smp])
+    assert_dots_close(got[smp], want, mag, what="dot compressed pairs 4096")
+    v0 = np.ascontiguousarray(V[0])
+    got = blaz.dot_dense(g, dev(rows), dev(v0)).cpu().numpy()
+    want = oracle.dot_dense(og, rows[smp], v0, 0)
+    mag = np.array([np.abs(band_rows(og, int(i))) @ np.abs(v0) for i in smp])
+    assert_dots_close(got[smp], want, mag, what="dot shared vector 4096")
+
+
 def test_dot_equals_matmul_element():
     """Section "Accuracy Measurements": dot(i, j) is element (i, j) of the product."""
     X = smooth_field(64, 4, 2.0, 1e-3, 420)
