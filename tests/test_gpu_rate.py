@@ -129,3 +129,23 @@ def test_compress_lines_full_size_8192_sampled(lines):
     ties = compare_compressed((gf[sample], gs[sample], gphi[sample], gcodes[sample]),
                               (want.f, want.s, want.phi, want.codes), cx, px, f"8192 L={lines} sampled")
     assert ties <= 2
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_shapes_and_rates_sweep(seed):
+    """Seeded sweep: random ragged shapes (multiples of 8 up to 520), random
+    kept lines, random field parameters; compress against the oracle, the
+    oracle's records decompressed within the tolerance, add bit-exact."""
+    rng = np.random.default_rng(900 + seed)
+    r, c = 8 * int(rng.integers(1, 66)), 8 * int(rng.integers(1, 66))
+    lines = int(rng.integers(1, 9))
+    A = smooth_field(r, int(rng.integers(1, 8)), float(rng.uniform(0.5, 6.0)), float(10 ** rng.uniform(-6, -1)),
+                     1000 + seed, cols=c) * float(10 ** rng.uniform(-3, 3))
+    got = blaz.compress(dev(A), lines=lines)
+    want, (cx, px) = oracle.compress_lines(A, lines, with_debug=True)
+    compare_compressed(host(got), (want.f, want.s, want.phi, want.codes), cx, px, f"sweep {r}x{c} L={lines}")
+    back = blaz.decompress(upload(want)).cpu().numpy()
+    assert_blocks_close(back, oracle.decompress(want), what=f"sweep decompress {r}x{c} L={lines}")
+    B = oracle.compress_lines(smooth_field(r, 3, 2.0, 1e-3, 2000 + seed, cols=c), lines)
+    assert_same_compressed(host(blaz.add(upload(want), upload(B))),
+                           (lambda z: (z.f, z.s, z.phi, z.codes))(oracle.add(want, B)), f"sweep add L={lines}")
