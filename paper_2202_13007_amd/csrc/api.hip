@@ -145,7 +145,7 @@ static MatmulWorkspace matmul_workspace(int64_t m, int64_t n, int64_t k, bool b_
             break;
         case BLAZ_PREC_BF16X3:
             w.a_bytes = 2 * round_up(mk * 2, 256);  // hi, lo
-            w.b_bytes = 2 * round_up(kn * 2, 256);
+            w.b_bytes = 2 * round_up((size_t)blaz::detail::bf16_blocked_elems(k, n) * 2, 256);  // blocked B^T
             w.tmp_bytes = b_compressed ? round_up(kn * 8, 256) : 0;
             break;
     }
@@ -271,8 +271,8 @@ static blaz_status matmul_impl(const blaz_matrix* a, const blaz_matrix* b, const
     __bf16* Bhi = reinterpret_cast<__bf16*>(wb);
     __bf16* Blo = reinterpret_cast<__bf16*>(wb + wl.b_bytes / 2);
     if (hipError_t e = launch_decompress_bf16_split(*a, Ahi, Alo, k, stream)) return hip_status(e);
-    if (hipError_t e = launch_convert_bf16_split_t(bsrc, ldbsrc, Bhi, Blo, k, n, stream)) return hip_status(e);
-    return hip_status(launch_gemm_bf16x3(Ahi, Alo, k, Bhi, Blo, k, c, ldc, m, n, k, tile, stream));
+    if (hipError_t e = launch_convert_bf16_split_blocked(bsrc, ldbsrc, Bhi, Blo, k, n, stream)) return hip_status(e);
+    return hip_status(launch_gemm_bf16x3(Ahi, Alo, k, Bhi, Blo, c, ldc, m, n, k, tile, stream));
 }
 
 BLAZ_API blaz_status blaz_matmul(const blaz_matrix* a, const blaz_matrix* b, const double* bdense, int64_t n,

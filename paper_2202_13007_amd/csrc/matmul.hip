@@ -193,8 +193,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
         }
 }
 
-// BF16x3: A hi/lo (M x K, lda) and B^T hi/lo (N x K, ldbt), all with k
-// contiguous, so that one 16-byte load gives an MFMA lane its 8 k-values.
+// BF16x3: A hi/lo (M x K, lda) with k contiguous, and B^T hi/lo (N x K) in
+// blocked form: tiles of 64 rows (n) x 32 k, each 4 KB contiguous, tile
+// (n / 64, k / 32) at ((n / 64) * nkc + k / 32) * 2048 elements, nkc =
+// ceil(K / 32), row-major inside (k contiguous).  One 16-byte load gives an
+// MFMA lane its 8 k-values, and a workgroup's B tile for one K step is two
+// contiguous 4 KB blocks.
 // K advances in steps of 32.  An LDS tile row is the row's 32 bf16 (64 B, no
 // padding) as four 16-byte chunks; chunk c of row r sits in slot
 // c ^ ((r >> 1) & 3).  Both the tile stores (4 lanes per row) and the
@@ -212,7 +216,7 @@ __device__ __forceinline__ int bf16_tile_slot(int row, int chunk)
 template <int kBM>
 __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restrict__ Ahi, const __bf16* __restrict__ Alo,
                                                           int64_t lda, const __bf16* __restrict__ Bhi,
-                                                          const __bf16* __restrict__ Blo, int64_t ldbt,
+                                                          const __bf16* __restrict__ Blo, int64_t nkc,
                                                           double* __restrict__ C, int64_t ldc, int64_t M, int64_t N,
                                                           int64_t K)
 {
@@ -246,8 +250,9 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
             const bool oka = ga < M && gk < K, okb = gb < N && gk < K;
             rah[r] = oka ? *reinterpret_cast<const uint4*>(Ahi + ga * lda + gk) : uint4{0, 0, 0, 0};
             ral[r] = oka ? *reinterpret_cast<const uint4*>(Alo + ga * lda + gk) : uint4{0, 0, 0, 0};
-            rbh[r] = okb ? *reinterpret_cast<const uint4*>(Bhi + gb * ldbt + gk) : uint4{0, 0, 0, 0};
-            rbl[r] = okb ? *reinterpret_cast<const uint4*>(Blo + gb * ldbt + gk) : uint4{0, 0, 0, 0};
+            const int64_t ob = (((gb >> 6) * nkc + (gk >> 5)) * 64 + (gb & 63)) * 32 + (gk & 31);
+            rbh[r] = okb ? *reinterpret_cast<const uint4*>(Bhi + ob) : uint4{0, 0, 0, 0};
+            rbl[r] = okb ? *reinterpret_cast<const uint4*>(Blo + ob) : uint4{0, 0, 0, 0};
         }
     };
     auto store_stage = [&](int buf) {
@@ -336,17 +341,18 @@ __global__ __launch_bounds__(256) void convert_f32_kernel(const double* __restri
     }
 }
 
-// Dense binary64 (k x n, ldb) to its transpose split into BF16 hi + lo
-// (n x k, ld k), through a 64 x 64 LDS tile so that both the reads (along
-// n) and the writes (along k) are contiguous.  Each thread writes two
-// consecutive k of one row of the transpose as one 4-byte pair (k is a
-// multiple of 8, so a pair never crosses the end of a row).
-__global__ __launch_bounds__(256) void convert_bf16_split_t_kernel(const double* __restrict__ B, int64_t ldb,
-                                                                   __bf16* __restrict__ hi, __bf16* __restrict__ lo,
-                                                                   int64_t k, int64_t n)
+// Dense binary64 (k x n, ldb) to its transpose split into BF16 hi + lo in
+// the blocked form the BF16x3 contraction reads (64 x 32 tiles, see above),
+// through a 64 (k) x 64 (n) LDS tile: the reads run along n, and each of the
+// tile's two 32-k chunks is written as one contiguous 4 KB block per array
+// (zeros beyond n and k, inside the padded workspace).
+__global__ __launch_bounds__(256) void convert_bf16_split_blocked_kernel(const double* __restrict__ B, int64_t ldb,
+                                                                         __bf16* __restrict__ hi,
+                                                                         __bf16* __restrict__ lo, int64_t k,
+                                                                         int64_t n, int64_t nkc)
 {
     __shared__ double t[64][65];
-    const int64_t k0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+    const int64_t k0 = (int64_t)blockIdx.y * 64, nb = blockIdx.x, n0 = nb * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -355,19 +361,23 @@ __global__ __launch_bounds__(256) void convert_bf16_split_t_kernel(const double*
         t[kk][tx] = ok ? B[(k0 + kk) * ldb + n0 + tx] : 0.0;
     }
     __syncthreads();
-    const int kp = threadIdx.x & 31, nr = threadIdx.x >> 5;  // 32 k pairs x 8 rows
+    const int nl = threadIdx.x >> 2, kq = (threadIdx.x & 3) * 8;  // 64 rows x 4 pieces of 8 k
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int nn = nr + 8 * r;
-        if (n0 + nn < n && k0 + 2 * kp < k) {
-            const double x0 = t[2 * kp][nn], x1 = t[2 * kp + 1][nn];
+    for (int c = 0; c < 2; ++c) {
+        const int64_t chunk = k0 / 32 + c;
+        if (chunk >= nkc) break;
+        bf16x8 h, l;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const double x = t[32 * c + kq + e][nl];
             // hi = bf16(x), lo = bf16(x - hi), as the rebuild of A splits
-            const __bf16 h0 = (__bf16)(float)x0, h1 = (__bf16)(float)x1;
-            const __bf16 l0 = (__bf16)(float)(x0 - (double)(float)h0), l1 = (__bf16)(float)(x1 - (double)(float)h1);
-            const int64_t off = (n0 + nn) * k + k0 + 2 * kp;
-            *reinterpret_cast<bf16x2*>(hi + off) = bf16x2{h0, h1};
-            *reinterpret_cast<bf16x2*>(lo + off) = bf16x2{l0, l1};
+            const __bf16 hb = (__bf16)(float)x;
+            h[e] = hb;
+            l[e] = (__bf16)(float)(x - (double)(float)hb);
         }
+        const int64_t off = ((nb * nkc + chunk) * 64 + nl) * 32 + kq;
+        *reinterpret_cast<bf16x8*>(hi + off) = h;
+        *reinterpret_cast<bf16x8*>(lo + off) = l;
     }
 }
 
@@ -399,13 +409,14 @@ hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* B, int64_t 
 }
 
 hipError_t launch_gemm_bf16x3(const __bf16* Ahi, const __bf16* Alo, int64_t lda, const __bf16* Bthi,
-                              const __bf16* Btlo, int64_t ldbt, double* C, int64_t ldc, int64_t m, int64_t n,
-                              int64_t k, int tile, hipStream_t st)
+                              const __bf16* Btlo, double* C, int64_t ldc, int64_t m, int64_t n, int64_t k, int tile,
+                              hipStream_t st)
 {
+    const int64_t nkc = bf16_k_chunks(k);
     if (tile == 64)
-        gemm_bf16x3_kernel<64><<<gemm_grid(m, n, 64), 256, 0, st>>>(Ahi, Alo, lda, Bthi, Btlo, ldbt, C, ldc, m, n, k);
+        gemm_bf16x3_kernel<64><<<gemm_grid(m, n, 64), 256, 0, st>>>(Ahi, Alo, lda, Bthi, Btlo, nkc, C, ldc, m, n, k);
     else
-        gemm_bf16x3_kernel<128><<<gemm_grid(m, n, 128), 256, 0, st>>>(Ahi, Alo, lda, Bthi, Btlo, ldbt, C, ldc, m, n, k);
+        gemm_bf16x3_kernel<128><<<gemm_grid(m, n, 128), 256, 0, st>>>(Ahi, Alo, lda, Bthi, Btlo, nkc, C, ldc, m, n, k);
     return hipGetLastError();
 }
 
@@ -417,12 +428,12 @@ hipError_t launch_convert_f32(const double* B, int64_t ldb, float* out, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_convert_bf16_split_t(const double* B, int64_t ldb, __bf16* hi, __bf16* lo, int64_t k, int64_t n,
-                                       hipStream_t st)
+hipError_t launch_convert_bf16_split_blocked(const double* B, int64_t ldb, __bf16* hi, __bf16* lo, int64_t k,
+                                             int64_t n, hipStream_t st)
 {
     if (k == 0 || n == 0) return hipSuccess;
     const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((k + 63) / 64));
-    convert_bf16_split_t_kernel<<<grid, 256, 0, st>>>(B, ldb, hi, lo, k, n);
+    convert_bf16_split_blocked_kernel<<<grid, 256, 0, st>>>(B, ldb, hi, lo, k, n, bf16_k_chunks(k));
     return hipGetLastError();
 }
 
