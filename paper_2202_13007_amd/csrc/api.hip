@@ -140,7 +140,7 @@ static MatmulWorkspace matmul_workspace(int64_t m, int64_t n, int64_t k, bool b_
             break;
         case BLAZ_PREC_FP32:
             w.a_bytes = round_up(mk * 4, 256);
-            w.b_bytes = round_up(kn * 4, 256);
+            w.b_bytes = round_up((size_t)blaz::detail::f32_blocked_elems(k, n) * 4, 256);  // blocked B^T
             w.tmp_bytes = b_compressed ? round_up(kn * 8, 256) : 0;
             break;
         case BLAZ_PREC_BF16X3:
@@ -263,8 +263,8 @@ static blaz_status matmul_impl(const blaz_matrix* a, const blaz_matrix* b, const
         float* A32 = reinterpret_cast<float*>(wa);
         float* B32 = reinterpret_cast<float*>(wb);
         if (hipError_t e = launch_decompress_f32(*a, A32, k, stream)) return hip_status(e);
-        if (hipError_t e = launch_convert_f32(bsrc, ldbsrc, B32, k, n, stream)) return hip_status(e);
-        return hip_status(launch_gemm_f32(A32, k, B32, n, c, ldc, m, n, k, tile, stream));
+        if (hipError_t e = launch_convert_f32_blocked(bsrc, ldbsrc, B32, k, n, stream)) return hip_status(e);
+        return hip_status(launch_gemm_f32(A32, k, B32, c, ldc, m, n, k, tile, stream));
     }
     __bf16* Ahi = reinterpret_cast<__bf16*>(wa);
     __bf16* Alo = reinterpret_cast<__bf16*>(wa + wl.a_bytes / 2);

@@ -57,21 +57,27 @@ hipError_t launch_dot_dense(const blaz_matrix& x, const int64_t* xrow, const dou
 // tile: 64 or 128 (the output tile of one workgroup).
 hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                            int64_t m, int64_t n, int64_t k, int tile, hipStream_t st);
-// The same product with FP32 operands on FP32 MFMA (FP32 accumulation).
-hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* B, int64_t ldb, double* C, int64_t ldc,
-                           int64_t m, int64_t n, int64_t k, int tile, hipStream_t st);
+// The same product with FP32 operands on FP32 MFMA (FP32 accumulation):
+// A (m x k, lda) k-contiguous, B^T (n x k) in the blocked form of
+// launch_convert_f32_blocked.  k a multiple of 4, lda too.
+hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* Bt, double* C, int64_t ldc, int64_t m, int64_t n,
+                           int64_t k, int tile, hipStream_t st);
 // The same product with A = Ahi + Alo (m x k) and B^T = Bthi + Btlo (n x k)
 // in BF16: C = Ahi B_hi + Ahi B_lo + Alo B_hi on BF16 MFMA, FP32 accumulation.
 // B^T is in the blocked form of launch_convert_bf16_split_blocked.
 hipError_t launch_gemm_bf16x3(const __bf16* Ahi, const __bf16* Alo, int64_t lda, const __bf16* Bthi,
                               const __bf16* Btlo, double* C, int64_t ldc, int64_t m, int64_t n, int64_t k, int tile,
                               hipStream_t st);
-// 32-k chunks of the blocked B^T form, and its elements per array: tiles of
-// 64 rows (n) x 32 k, 4 KB each, the padding zero.
+// 32-k chunks of the blocked B^T forms, and their elements per array: tiles
+// of 64 rows (n) x 32 k (4 KB in BF16, 8 KB in FP32), the padding zero.
 inline int64_t bf16_k_chunks(int64_t k) { return (k + 31) / 32; }
 inline int64_t bf16_blocked_elems(int64_t k, int64_t n) { return ((n + 63) / 64) * 64 * bf16_k_chunks(k) * 32; }
-// Dense binary64 B (k x n, ldb) to FP32 row-major (k x n, ld n).
-hipError_t launch_convert_f32(const double* B, int64_t ldb, float* out, int64_t k, int64_t n, hipStream_t st);
+inline int64_t f32_k_chunks(int64_t k) { return (k + 31) / 32; }
+inline int64_t f32_blocked_elems(int64_t k, int64_t n) { return ((n + 63) / 64) * 64 * f32_k_chunks(k) * 32; }
+// Dense binary64 B (k x n, ldb) to B^T in FP32 in blocked form: tile
+// (n / 64, k / 32) of 64 rows x 32 k (k contiguous) at
+// ((n / 64) * f32_k_chunks(k) + k / 32) * 2048 elements.
+hipError_t launch_convert_f32_blocked(const double* B, int64_t ldb, float* out, int64_t k, int64_t n, hipStream_t st);
 // Dense binary64 B (k x n, ldb) to B^T split into BF16 hi + lo in blocked
 // form: tile (n / 64, k / 32) of 64 rows x 32 k (k contiguous) at
 // ((n / 64) * bf16_k_chunks(k) + k / 32) * 2048 elements.

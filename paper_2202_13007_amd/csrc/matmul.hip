@@ -30,23 +30,19 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// Elements of padding per LDS row of the FP64/FP32 operand tiles.  gfx950's
-// LDS serves 128 B per clock from 32 four-byte banks, 64-bit accesses in
-// groups of 16 lanes and 32-bit ones in groups of 32 (this model reproduces
-// the measured conflict counts of every layout tried).  FP64: a 16-lane group
-// of the transposed A store writes column m, m+1 of rows k, k+2, ..., k+14;
-// with a 131-double row (3 doubles of padding) those rows start 12 banks
-// apart and all 16 stores hit distinct banks (counted: 0 conflicts; a
-// 130-double row gives 2-way conflicts on them, 0.8 % slower at 4096^3).
-// B rows take even padding so that their 16-byte stores stay aligned; the
+// Elements of padding per LDS row of the FP64 operand tiles.  gfx950's LDS
+// serves 128 B per clock from 32 four-byte banks, 64-bit accesses in groups
+// of 16 lanes and 32-bit ones in groups of 32 (this model reproduces the
+// measured conflict counts of the FP64 and FP32 layouts tried).  A 16-lane
+// group of the transposed A store writes column m, m+1 of rows k, k+2, ...,
+// k+14; with a 131-double row (3 doubles of padding) those rows start 12
+// banks apart and all 16 stores hit distinct banks (counted: 0 conflicts; a
+// 130-double row gives 2-way conflicts on them, 0.8 % slower at 4096^3).  B
+// rows take even padding so that their 16-byte stores stay aligned; the
 // fragment reads (16 consecutive doubles of one row per group) never
-// conflict.  FP32: 4 floats (measured against 0, 8, 12, 16, 20: 4 is
-// fastest, +6 % over 16 on the 128 tile, +10 % on the 64 tile; a
-// conflict-free XOR layout was no faster, the kernel is not LDS-bound).
-template <typename T>
-constexpr int kPadAOf = sizeof(T) == 8 ? 3 : 4;
-template <typename T>
-constexpr int kPadBOf = sizeof(T) == 8 ? 2 : 4;
+// conflict.
+constexpr int kPadA64 = 3;
+constexpr int kPadB64 = 2;
 
 // Tile (tm, tn) for workgroup `wg` of `nwg`: contiguous ranges per XCD, then
 // groups of 8 tile rows walked column by column for L2 reuse.
@@ -76,17 +72,9 @@ struct Mfma16x16x4<double> {
     __device__ static acc_t op(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
     __device__ static int row(int g, int r) { return 4 * r + g; }
 };
-template <>
-struct Mfma16x16x4<float> {
-    using acc_t = f32x4;
-    using vec_t = f32x4;
-    static constexpr int kBK = 32;
-    __device__ static acc_t op(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-    __device__ static int row(int g, int r) { return 4 * g + r; }
-};
 
-// C = A B with A (M x K, lda) and B (K x N, ldb) row-major in T; C binary64.
-// LDS rows hold kBM + kPadAOf<T> (A) and kBN + kPadBOf<T> (B) elements.
+// C = A B with A (M x K, lda) and B (K x N, ldb) row-major binary64; C
+// binary64.  LDS rows hold kBM + kPadA64 (A) and kBN + kPadB64 (B) elements.
 template <typename T, int kBM>
 __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
                                                    int64_t ldb, double* __restrict__ C, int64_t ldc, int64_t M,
@@ -104,9 +92,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
     constexpr int RV = kBM * AV / 256;    // vectors of A (and of B) per thread
     static_assert(kBM * AV == BK * BV && RV * 256 == kBM * AV, "whole vectors per thread");
 
-    __shared__ __align__(16) T As[2][BK][kBM + kPadAOf<T>];  // A tiles stored k-major (transposed), double-buffered
-    __shared__ __align__(16) T Bs[2][BK][kBN + kPadBOf<T>];  // 16-byte row stores
-    static_assert((kBN + kPadBOf<T>) * sizeof(T) % 16 == 0, "B rows keep 16-byte alignment");
+    __shared__ __align__(16) T As[2][BK][kBM + kPadA64];  // A tiles stored k-major (transposed), double-buffered
+    __shared__ __align__(16) T Bs[2][BK][kBN + kPadB64];  // 16-byte row stores
+    static_assert((kBN + kPadB64) * sizeof(T) % 16 == 0, "B rows keep 16-byte alignment");
 
     const int ntm = (int)((M + kBM - 1) / kBM);
     const int ntn = (int)((N + kBN - 1) / kBN);
@@ -188,6 +176,121 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gr = row0 + wm * (kBM / 2) + i * 16 + MF::row(lane >> 4, r);
+                if (gr < M && gc < N) C[gr * ldc + gc] = (double)acc[i][j][r];
+            }
+        }
+}
+
+// FP32: A (M x K, lda) with k contiguous and B^T (N x K) in blocked form:
+// tiles of 64 rows (n) x 32 k, 8 KB each, tile (n / 64, k / 32) at
+// ((n / 64) * nkc + k / 32) * 2048 elements, nkc = ceil(K / 32), row-major
+// inside.  K advances in steps of 32; an LDS tile row is its 32 floats
+// (128 B) as eight 16-byte chunks, chunk c of row r in slot c ^ ((r >> 1) & 7).
+// A lane's chunk c holds k = 4c .. 4c+3 of its row, and MFMA step s of chunk
+// c uses k = 4c + s in every lane group alike, so one 16-byte LDS read feeds
+// four v_mfma_f32_16x16x4f32 (measured 5 % faster than the k-major tiles
+// with transposed stores: 130 against 124 TFLOP/s at 8192^3).
+constexpr int kBKf = 32;
+
+__device__ __forceinline__ int f32_tile_slot(int row, int chunk)
+{
+    return row * kBKf + ((chunk ^ ((row >> 1) & 7)) << 2);
+}
+
+template <int kBM>
+__global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__ A, int64_t lda,
+                                                       const float* __restrict__ Bt, int64_t nkc,
+                                                       double* __restrict__ C, int64_t ldc, int64_t M, int64_t N,
+                                                       int64_t K)
+{
+    constexpr int kBN = kBM;
+    constexpr int TW = kBM / 32;
+    constexpr int CPR = kBKf / 4;      // 16-byte chunks per tile row
+    constexpr int RC = kBM * CPR / 256;  // chunks of each operand tile per thread
+    __shared__ __align__(16) float As[2][kBM * kBKf];
+    __shared__ __align__(16) float Bs[2][kBN * kBKf];
+
+    const int ntm = (int)((M + kBM - 1) / kBM);
+    const int ntn = (int)((N + kBN - 1) / kBN);
+    int tm, tn;
+    tile_of(blockIdx.x, gridDim.x, ntm, ntn, tm, tn);
+    const int64_t row0 = (int64_t)tm * kBM, col0 = (int64_t)tn * kBN;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    f32x4 ra[RC], rb[RC];
+    auto load_stage = [&](int64_t k0) {
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+            const int q = tid + 256 * r;
+            const int row = q / CPR, ck = q % CPR;
+            const int64_t gk = k0 + 4 * ck, ga = row0 + row, gb = col0 + row;
+            ra[r] = (ga < M && gk < K) ? *reinterpret_cast<const f32x4*>(A + ga * lda + gk) : f32x4{0.f, 0.f, 0.f, 0.f};
+            const int64_t ob = (((gb >> 6) * nkc + (gk >> 5)) * 64 + (gb & 63)) * kBKf + (gk & 31);
+            rb[r] = (gb < N && gk < K) ? *reinterpret_cast<const f32x4*>(Bt + ob) : f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    auto store_stage = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+            const int q = tid + 256 * r;
+            const int off = f32_tile_slot(q / CPR, q % CPR);
+            *reinterpret_cast<f32x4*>(&As[buf][off]) = ra[r];
+            *reinterpret_cast<f32x4*>(&Bs[buf][off]) = rb[r];
+        }
+    };
+
+    f32x4 acc[TW][TW];
+#pragma unroll
+    for (int i = 0; i < TW; ++i)
+#pragma unroll
+        for (int j = 0; j < TW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // The pipeline of gemm_kernel: compute on one LDS buffer while the next
+    // stage is stored to the other and the one after is fetched.
+    const int nk = (int)((K + kBKf - 1) / kBKf);
+    load_stage(0);
+    store_stage(0);
+    if (nk > 1) load_stage(kBKf);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+#pragma unroll
+        for (int cc = 0; cc < CPR; cc += 4) {
+            const int c = cc + (lane >> 4);
+            f32x4 a4[TW], b4[TW];
+#pragma unroll
+            for (int i = 0; i < TW; ++i)
+                a4[i] = *reinterpret_cast<const f32x4*>(&As[cur][f32_tile_slot(wm * (kBM / 2) + i * 16 + (lane & 15), c)]);
+#pragma unroll
+            for (int j = 0; j < TW; ++j)
+                b4[j] = *reinterpret_cast<const f32x4*>(&Bs[cur][f32_tile_slot(wn * (kBN / 2) + j * 16 + (lane & 15), c)]);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int i = 0; i < TW; ++i)
+#pragma unroll
+                    for (int j = 0; j < TW; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[i][s], b4[j][s], acc[i][j], 0, 0, 0);
+        }
+        if (kt + 1 < nk) {
+            store_stage(cur ^ 1);
+            if (kt + 2 < nk) load_stage((int64_t)(kt + 2) * kBKf);
+        }
+        __syncthreads();
+    }
+
+    // Value r of lane l holds row 4*(l/16) + r, column l%16 (FP32 16x16 form).
+#pragma unroll
+    for (int i = 0; i < TW; ++i)
+#pragma unroll
+        for (int j = 0; j < TW; ++j) {
+            const int64_t gc = col0 + wn * (kBN / 2) + j * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gr = row0 + wm * (kBM / 2) + i * 16 + 4 * (lane >> 4) + r;
                 if (gr < M && gc < N) C[gr * ldc + gc] = (double)acc[i][j][r];
             }
         }
@@ -328,16 +431,37 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
         }
 }
 
-// Dense binary64 (k x n, ldb) to FP32 (k x n, ld n): rows strided over
-// the y dimension of the grid, two elements per thread.
-__global__ __launch_bounds__(256) void convert_f32_kernel(const double* __restrict__ B, int64_t ldb,
-                                                          float* __restrict__ out, int64_t k, int64_t n)
+// Dense binary64 (k x n, ldb) to its transpose in FP32 in the blocked form
+// the FP32 contraction reads (64 x 32 tiles, see above), through a 64 (k) x
+// 64 (n) LDS tile: the reads run along n, and each of the tile's two 32-k
+// chunks is written as one contiguous 8 KB block (zeros beyond n and k,
+// inside the padded workspace).
+__global__ __launch_bounds__(256) void convert_f32_blocked_kernel(const double* __restrict__ B, int64_t ldb,
+                                                                  float* __restrict__ out, int64_t k, int64_t n,
+                                                                  int64_t nkc)
 {
-    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2;
-    if (c >= n) return;
-    for (int64_t row = blockIdx.y; row < k; row += gridDim.y) {
-        const f64x2 v = *reinterpret_cast<const f64x2*>(B + row * ldb + c);
-        *reinterpret_cast<float2*>(out + row * n + c) = make_float2((float)v[0], (float)v[1]);
+    __shared__ double t[64][65];
+    const int64_t k0 = (int64_t)blockIdx.y * 64, nb = blockIdx.x, n0 = nb * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int kk = ty + 4 * r;
+        const bool ok = k0 + kk < k && n0 + tx < n;
+        t[kk][tx] = ok ? B[(k0 + kk) * ldb + n0 + tx] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int64_t chunk = k0 / 32 + c;
+        if (chunk >= nkc) break;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {  // 64 rows x 8 pieces of 4 k, two passes
+            const int p = threadIdx.x + 256 * h, nl = p >> 3, kq = (p & 7) * 4;
+            f32x4 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = (float)t[32 * c + kq + e][nl];
+            *reinterpret_cast<f32x4*>(out + ((nb * nkc + chunk) * 64 + nl) * 32 + kq) = v;
+        }
     }
 }
 
@@ -398,13 +522,14 @@ hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* B, int64_
     return hipGetLastError();
 }
 
-hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* B, int64_t ldb, double* C, int64_t ldc,
-                           int64_t m, int64_t n, int64_t k, int tile, hipStream_t st)
+hipError_t launch_gemm_f32(const float* A, int64_t lda, const float* Bt, double* C, int64_t ldc, int64_t m, int64_t n,
+                           int64_t k, int tile, hipStream_t st)
 {
+    const int64_t nkc = f32_k_chunks(k);
     if (tile == 64)
-        gemm_kernel<float, 64><<<gemm_grid(m, n, 64), 256, 0, st>>>(A, lda, B, ldb, C, ldc, m, n, k);
+        gemm_f32_kernel<64><<<gemm_grid(m, n, 64), 256, 0, st>>>(A, lda, Bt, nkc, C, ldc, m, n, k);
     else
-        gemm_kernel<float, 128><<<gemm_grid(m, n, 128), 256, 0, st>>>(A, lda, B, ldb, C, ldc, m, n, k);
+        gemm_f32_kernel<128><<<gemm_grid(m, n, 128), 256, 0, st>>>(A, lda, Bt, nkc, C, ldc, m, n, k);
     return hipGetLastError();
 }
 
@@ -420,11 +545,11 @@ hipError_t launch_gemm_bf16x3(const __bf16* Ahi, const __bf16* Alo, int64_t lda,
     return hipGetLastError();
 }
 
-hipError_t launch_convert_f32(const double* B, int64_t ldb, float* out, int64_t k, int64_t n, hipStream_t st)
+hipError_t launch_convert_f32_blocked(const double* B, int64_t ldb, float* out, int64_t k, int64_t n, hipStream_t st)
 {
     if (k == 0 || n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((n / 2 + 255) / 256), (unsigned)(k < 4096 ? k : 4096));
-    convert_f32_kernel<<<grid, 256, 0, st>>>(B, ldb, out, k, n);
+    const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((k + 63) / 64));
+    convert_f32_blocked_kernel<<<grid, 256, 0, st>>>(B, ldb, out, k, n, f32_k_chunks(k));
     return hipGetLastError();
 }
 
