@@ -30,6 +30,12 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+// s_waitcnt immediate (gfx9 encoding) that waits for every outstanding
+// vector memory operation and leaves the export and LDS counters free:
+// vmcnt = 0 (bits 3:0 and 15:14), expcnt = 7 (bits 6:4), lgkmcnt = 15
+// (bits 11:8).
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 // Elements of padding per LDS row of the FP64 operand tiles.  gfx950's LDS
 // serves 128 B per clock from 32 four-byte banks, 64-bit accesses in groups
 // of 16 lanes and 32-bit ones in groups of 32 (this model reproduces the
@@ -304,10 +310,19 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
 // contiguous 4 KB blocks.
 // K advances in steps of 32.  An LDS tile row is the row's 32 bf16 (64 B, no
 // padding) as four 16-byte chunks; chunk c of row r sits in slot
-// c ^ ((r >> 1) & 3).  Both the tile stores (4 lanes per row) and the
+// c ^ ((r >> 1) & 3).  Both the tile fills (4 lanes per row) and the
 // fragment reads (one chunk of 16 consecutive rows per 16 lanes) are then
 // free of bank conflicts on gfx950 (counted: 0, against 2 conflict cycles
 // per access cycle with 80-byte padded rows).
+// The tiles are filled by global_load_lds_dwordx4: one instruction of a
+// wave writes 1 KB of LDS, 16 bytes per lane in lane order, here 16 tile
+// rows, so lane l fetches the chunk that belongs in slot l & 3 of row
+// l >> 2.  No registers or LDS store instructions are spent on staging
+// (measured against staging through registers: 12 % faster at 4096^3, 5 %
+// at 8192^3, 29 % for the 64 tile at 8192^3).  A
+// lane whose chunk lies outside the matrix (row >= M or N, k >= K) fetches
+// 16 zero bytes instead, so that the fills stay free of branches (with
+// branches the compiler waits for every fill before the fragment reads).
 constexpr int kBKb = 32;
 constexpr int kRowB = kBKb;
 
@@ -315,6 +330,11 @@ __device__ __forceinline__ int bf16_tile_slot(int row, int chunk)
 {
     return row * kRowB + ((chunk ^ ((row >> 1) & 3)) << 3);
 }
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// Source of the fills for chunks outside the matrix: 16 zero bytes.
+__device__ __align__(16) const __bf16 kZeroChunk[8] = {};
 
 template <int kBM>
 __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restrict__ Ahi, const __bf16* __restrict__ Alo,
@@ -325,11 +345,12 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
 {
     constexpr int kBN = kBM;
     constexpr int TW = kBM / 32;
-    constexpr int RC = kBM / 64;  // 16-byte chunks of each operand tile per thread
-    __shared__ __align__(16) __bf16 Ash[2][kBM * kRowB];  // double-buffered operand tiles
-    __shared__ __align__(16) __bf16 Asl[2][kBM * kRowB];
-    __shared__ __align__(16) __bf16 Bsh[2][kBN * kRowB];
-    __shared__ __align__(16) __bf16 Bsl[2][kBN * kRowB];
+    constexpr int RC = kBM / 64;  // 1 KB fills of each operand tile per wave
+    static_assert(kBN == kBM, "square tiles");
+    // double-buffered operand tiles: [buffer][A hi, A lo, B hi, B lo], one
+    // array (with four, the compiler waits for the other buffer's fills
+    // before every fragment read)
+    __shared__ __align__(16) __bf16 T[2][4][kBM * kRowB];
 
     const int ntm = (int)((M + kBM - 1) / kBM);
     const int ntn = (int)((N + kBN - 1) / kBN);
@@ -341,32 +362,28 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
-    // Each of the four BM x 32 tiles is 4 BM 16-byte chunks: BM/64 per thread.
-    uint4 rah[RC], ral[RC], rbh[RC], rbl[RC];
-    auto load_stage = [&](int64_t k0) {
+    // Fill of stage k0 into buffer buf: fill r of wave w covers tile rows
+    // (w * RC + r) * 16 .. +15 of each of the four tiles.
+    auto fill_stage = [&](int buf, int64_t k0) {
 #pragma unroll
         for (int r = 0; r < RC; ++r) {
-            const int q = tid + 256 * r;
-            const int row = q >> 2, kc = (q & 3) * 8;
-            const int64_t gk = k0 + kc;
-            const int64_t ga = row0 + row, gb = col0 + row;
+            const int rb = (wave * RC + r) * 16;
+            const int row = rb + (lane >> 2);
+            const int chunk = (lane & 3) ^ ((row >> 1) & 3);
+            const int64_t gk = k0 + chunk * 8, ga = row0 + row, gb = col0 + row;
             const bool oka = ga < M && gk < K, okb = gb < N && gk < K;
-            rah[r] = oka ? *reinterpret_cast<const uint4*>(Ahi + ga * lda + gk) : uint4{0, 0, 0, 0};
-            ral[r] = oka ? *reinterpret_cast<const uint4*>(Alo + ga * lda + gk) : uint4{0, 0, 0, 0};
+            const int64_t oa = ga * lda + gk;
             const int64_t ob = (((gb >> 6) * nkc + (gk >> 5)) * 64 + (gb & 63)) * 32 + (gk & 31);
-            rbh[r] = okb ? *reinterpret_cast<const uint4*>(Bhi + ob) : uint4{0, 0, 0, 0};
-            rbl[r] = okb ? *reinterpret_cast<const uint4*>(Blo + ob) : uint4{0, 0, 0, 0};
-        }
-    };
-    auto store_stage = [&](int buf) {
-#pragma unroll
-        for (int r = 0; r < RC; ++r) {
-            const int q = tid + 256 * r;
-            const int off = bf16_tile_slot(q >> 2, q & 3);
-            *reinterpret_cast<uint4*>(&Ash[buf][off]) = rah[r];
-            *reinterpret_cast<uint4*>(&Asl[buf][off]) = ral[r];
-            *reinterpret_cast<uint4*>(&Bsh[buf][off]) = rbh[r];
-            *reinterpret_cast<uint4*>(&Bsl[buf][off]) = rbl[r];
+            // byte addresses, selected as integers (a pointer select becomes a branch)
+            const uintptr_t z = reinterpret_cast<uintptr_t>(kZeroChunk);
+            const uintptr_t pah = oka ? reinterpret_cast<uintptr_t>(Ahi + oa) : z;
+            const uintptr_t pal = oka ? reinterpret_cast<uintptr_t>(Alo + oa) : z;
+            const uintptr_t pbh = okb ? reinterpret_cast<uintptr_t>(Bhi + ob) : z;
+            const uintptr_t pbl = okb ? reinterpret_cast<uintptr_t>(Blo + ob) : z;
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(pah), (lds_ptr_t)&T[buf][0][rb * kRowB], 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(pal), (lds_ptr_t)&T[buf][1][rb * kRowB], 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(pbh), (lds_ptr_t)&T[buf][2][rb * kRowB], 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(pbl), (lds_ptr_t)&T[buf][3][rb * kRowB], 16, 0, 0);
         }
     };
 
@@ -376,15 +393,17 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
 #pragma unroll
         for (int j = 0; j < TW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // Same pipeline as gemm_kernel: compute on one LDS buffer while the next
-    // stage is stored to the other and the one after is fetched.
+    // Compute on one LDS buffer while the next stage fills the other.  The
+    // fill of buffer b for stage kt+1 starts after the barrier that ends
+    // stage kt-1, the last reader of b; every wave waits for its own fills
+    // (vmcnt) before the barrier that publishes them.
     const int nk = (int)((K + kBKb - 1) / kBKb);
-    load_stage(0);
-    store_stage(0);
-    if (nk > 1) load_stage(kBKb);
+    fill_stage(0, 0);
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
+        if (kt + 1 < nk) fill_stage(cur ^ 1, (int64_t)(kt + 1) * kBKb);
         // Operands of a 16x16x32 MFMA: lane l holds the 8 k-values
         // 8*(l/16) .. 8*(l/16)+7 of row (A) or column (B) l%16; any fixed
         // assignment of k to (lane group, element) works as long as A and B
@@ -393,14 +412,14 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
 #pragma unroll
         for (int i = 0; i < TW; ++i) {
             const int off = bf16_tile_slot(wm * (kBM / 2) + i * 16 + (lane & 15), lane >> 4);
-            ah[i] = *reinterpret_cast<const bf16x8*>(&Ash[cur][off]);
-            al[i] = *reinterpret_cast<const bf16x8*>(&Asl[cur][off]);
+            ah[i] = *reinterpret_cast<const bf16x8*>(&T[cur][0][off]);
+            al[i] = *reinterpret_cast<const bf16x8*>(&T[cur][1][off]);
         }
 #pragma unroll
         for (int j = 0; j < TW; ++j) {
             const int off = bf16_tile_slot(wn * (kBN / 2) + j * 16 + (lane & 15), lane >> 4);
-            bh[j] = *reinterpret_cast<const bf16x8*>(&Bsh[cur][off]);
-            bl[j] = *reinterpret_cast<const bf16x8*>(&Bsl[cur][off]);
+            bh[j] = *reinterpret_cast<const bf16x8*>(&T[cur][2][off]);
+            bl[j] = *reinterpret_cast<const bf16x8*>(&T[cur][3][off]);
         }
 #pragma unroll
         for (int i = 0; i < TW; ++i)
@@ -410,10 +429,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const __bf16* __restri
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
             }
-        if (kt + 1 < nk) {
-            store_stage(cur ^ 1);
-            if (kt + 2 < nk) load_stage((int64_t)(kt + 2) * kBKb);
-        }
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         __syncthreads();
     }
 
