@@ -122,8 +122,9 @@ BLAZ_API blaz_status blaz_dot_dense(const blaz_matrix* x, const int64_t* xrow, c
 }
 
 // Workspace regions of blaz_matmul, each 256-byte aligned: the rebuilt A
-// and the prepared B in the contraction's operand form, plus a binary64
-// staging area for a compressed B when the contraction is not binary64.
+// and the prepared B in the contraction's operand form, plus, for a
+// compressed B and a contraction that is not binary64, a staging area where
+// B is rebuilt row-major in the operand precision (FP32, or BF16 hi and lo).
 struct MatmulWorkspace {
     size_t a_bytes, b_bytes, tmp_bytes;
     size_t total() const { return a_bytes + b_bytes + tmp_bytes; }
@@ -141,12 +142,12 @@ static MatmulWorkspace matmul_workspace(int64_t m, int64_t n, int64_t k, bool b_
         case BLAZ_PREC_FP32:
             w.a_bytes = round_up(mk * 4, 256);
             w.b_bytes = round_up((size_t)blaz::detail::f32_blocked_elems(k, n) * 4, 256);  // blocked B^T
-            w.tmp_bytes = b_compressed ? round_up(kn * 8, 256) : 0;
+            w.tmp_bytes = b_compressed ? round_up(kn * 4, 256) : 0;  // B rebuilt in FP32
             break;
         case BLAZ_PREC_BF16X3:
             w.a_bytes = 2 * round_up(mk * 2, 256);  // hi, lo
             w.b_bytes = 2 * round_up((size_t)blaz::detail::bf16_blocked_elems(k, n) * 2, 256);  // blocked B^T
-            w.tmp_bytes = b_compressed ? round_up(kn * 8, 256) : 0;
+            w.tmp_bytes = b_compressed ? round_up(kn * 4, 256) : 0;  // B rebuilt in BF16 hi, lo
             break;
     }
     return w;
@@ -233,7 +234,7 @@ static blaz_status matmul_impl(const blaz_matrix* a, const blaz_matrix* b, const
     char* ws = static_cast<char*>(workspace);
     char* wa = ws;
     char* wb = ws + wl.a_bytes;
-    double* wtmp = reinterpret_cast<double*>(ws + wl.a_bytes + wl.b_bytes);
+    char* wtmp = ws + wl.a_bytes + wl.b_bytes;
     using namespace blaz::detail;
 
     if (prec == BLAZ_PREC_FP64) {
@@ -250,20 +251,21 @@ static blaz_status matmul_impl(const blaz_matrix* a, const blaz_matrix* b, const
         return hip_status(launch_gemm_f64(A64, k, bop, ldbop, c, ldc, m, n, k, tile, stream));
     }
 
-    // Low-precision contractions: B (dense, or a compressed B rebuilt in
-    // binary64 first) is converted to the operand form.
-    const double* bsrc = bdense;
-    int64_t ldbsrc = ldb;
-    if (b) {
-        if (hipError_t e = launch_decompress(*b, wtmp, n, stream)) return hip_status(e);
-        bsrc = wtmp;
-        ldbsrc = n;
-    }
+    // Low-precision contractions: a dense B is converted to the operand
+    // form; a compressed B is rebuilt row-major in the operand precision
+    // (the same values and the same split as converting its binary64
+    // rebuild) and then transposed into the operand form.
     if (prec == BLAZ_PREC_FP32) {
         float* A32 = reinterpret_cast<float*>(wa);
         float* B32 = reinterpret_cast<float*>(wb);
         if (hipError_t e = launch_decompress_f32(*a, A32, k, stream)) return hip_status(e);
-        if (hipError_t e = launch_convert_f32_blocked(bsrc, ldbsrc, B32, k, n, stream)) return hip_status(e);
+        if (b) {
+            float* T32 = reinterpret_cast<float*>(wtmp);
+            if (hipError_t e = launch_decompress_f32(*b, T32, n, stream)) return hip_status(e);
+            if (hipError_t e = launch_transpose_f32_blocked(T32, n, B32, k, n, stream)) return hip_status(e);
+        } else if (hipError_t e = launch_convert_f32_blocked(bdense, ldb, B32, k, n, stream)) {
+            return hip_status(e);
+        }
         return hip_status(launch_gemm_f32(A32, k, B32, c, ldc, m, n, k, tile, stream));
     }
     __bf16* Ahi = reinterpret_cast<__bf16*>(wa);
@@ -271,7 +273,15 @@ static blaz_status matmul_impl(const blaz_matrix* a, const blaz_matrix* b, const
     __bf16* Bhi = reinterpret_cast<__bf16*>(wb);
     __bf16* Blo = reinterpret_cast<__bf16*>(wb + wl.b_bytes / 2);
     if (hipError_t e = launch_decompress_bf16_split(*a, Ahi, Alo, k, stream)) return hip_status(e);
-    if (hipError_t e = launch_convert_bf16_split_blocked(bsrc, ldbsrc, Bhi, Blo, k, n, stream)) return hip_status(e);
+    if (b) {
+        __bf16* Thi = reinterpret_cast<__bf16*>(wtmp);
+        __bf16* Tlo = Thi + k * n;
+        if (hipError_t e = launch_decompress_bf16_split(*b, Thi, Tlo, n, stream)) return hip_status(e);
+        if (hipError_t e = launch_transpose_bf16_pair_blocked(Thi, Tlo, n, Bhi, Blo, k, n, stream))
+            return hip_status(e);
+    } else if (hipError_t e = launch_convert_bf16_split_blocked(bdense, ldb, Bhi, Blo, k, n, stream)) {
+        return hip_status(e);
+    }
     return hip_status(launch_gemm_bf16x3(Ahi, Alo, k, Bhi, Blo, c, ldc, m, n, k, tile, stream));
 }
 

@@ -83,6 +83,11 @@ hipError_t launch_convert_f32_blocked(const double* B, int64_t ldb, float* out, 
 // ((n / 64) * bf16_k_chunks(k) + k / 32) * 2048 elements.
 hipError_t launch_convert_bf16_split_blocked(const double* B, int64_t ldb, __bf16* hi, __bf16* lo, int64_t k,
                                              int64_t n, hipStream_t st);
+// The same blocked forms from row-major k x n operands already in FP32, or
+// split into BF16 hi + lo (ld a multiple of 8, 16-byte aligned rows).
+hipError_t launch_transpose_f32_blocked(const float* in, int64_t ld, float* out, int64_t k, int64_t n, hipStream_t st);
+hipError_t launch_transpose_bf16_pair_blocked(const __bf16* hi_in, const __bf16* lo_in, int64_t ld, __bf16* hi,
+                                              __bf16* lo, int64_t k, int64_t n, hipStream_t st);
 
 }  // namespace detail
 }  // namespace blaz

@@ -547,6 +547,82 @@ static unsigned gemm_grid(int64_t m, int64_t n, int tile)
     return (unsigned)(((m + tile - 1) / tile) * ((n + tile - 1) / tile));
 }
 
+// Row-major k x n operands already in the contraction's precision (a
+// compressed B rebuilt straight into FP32, or into BF16 hi + lo) to the
+// blocked B^T form of the converters above, through a 64 (k) x 64 (n) LDS
+// tile.  Half the bytes of going through binary64: the rebuild writes 4
+// bytes per element instead of 8, and this pass reads them.  The LDS rows
+// hold 66 bf16 or 65 floats, so that the column reads of the four (BF16) or
+// eight (FP32) k-pieces fall in different banks.
+__global__ __launch_bounds__(256) void transpose_bf16_pair_blocked_kernel(const __bf16* __restrict__ hi_in,
+                                                                          const __bf16* __restrict__ lo_in,
+                                                                          int64_t ld, __bf16* __restrict__ hi,
+                                                                          __bf16* __restrict__ lo, int64_t k,
+                                                                          int64_t n, int64_t nkc)
+{
+    __shared__ uint32_t th[64][33], tl[64][33];  // 64 k-rows of 64 bf16 (+ 2 of padding)
+    const int64_t k0 = (int64_t)blockIdx.y * 64, nb = blockIdx.x, n0 = nb * 64;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {  // 64 rows x 8 pieces of 8 bf16
+        const int q = threadIdx.x + 256 * r, row = q >> 3, pc = q & 7;
+        const bool ok = k0 + row < k && n0 + 8 * pc < n;
+        const int64_t o = (k0 + row) * ld + n0 + 8 * pc;
+        const uint4 vh = ok ? *reinterpret_cast<const uint4*>(hi_in + o) : uint4{0, 0, 0, 0};
+        const uint4 vl = ok ? *reinterpret_cast<const uint4*>(lo_in + o) : uint4{0, 0, 0, 0};
+        th[row][4 * pc] = vh.x, th[row][4 * pc + 1] = vh.y, th[row][4 * pc + 2] = vh.z, th[row][4 * pc + 3] = vh.w;
+        tl[row][4 * pc] = vl.x, tl[row][4 * pc + 1] = vl.y, tl[row][4 * pc + 2] = vl.z, tl[row][4 * pc + 3] = vl.w;
+    }
+    __syncthreads();
+    const auto* bh = reinterpret_cast<const uint16_t*>(&th[0][0]);
+    const auto* bl = reinterpret_cast<const uint16_t*>(&tl[0][0]);
+    const int nl = threadIdx.x >> 2, kq = (threadIdx.x & 3) * 8;  // 64 rows x 4 pieces of 8 k
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int64_t chunk = k0 / 32 + c;
+        if (chunk >= nkc) break;
+        uint32_t h[4], l[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r0 = 32 * c + kq + 2 * e;  // two k-values per dword
+            h[e] = bh[r0 * 66 + nl] | ((uint32_t)bh[(r0 + 1) * 66 + nl] << 16);
+            l[e] = bl[r0 * 66 + nl] | ((uint32_t)bl[(r0 + 1) * 66 + nl] << 16);
+        }
+        const int64_t off = ((nb * nkc + chunk) * 64 + nl) * 32 + kq;
+        *reinterpret_cast<uint4*>(hi + off) = uint4{h[0], h[1], h[2], h[3]};
+        *reinterpret_cast<uint4*>(lo + off) = uint4{l[0], l[1], l[2], l[3]};
+    }
+}
+
+__global__ __launch_bounds__(256) void transpose_f32_blocked_kernel(const float* __restrict__ in, int64_t ld,
+                                                                    float* __restrict__ out, int64_t k, int64_t n,
+                                                                    int64_t nkc)
+{
+    __shared__ float t[64][65];
+    const int64_t k0 = (int64_t)blockIdx.y * 64, nb = blockIdx.x, n0 = nb * 64;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {  // 64 rows x 16 pieces of 4 floats
+        const int q = threadIdx.x + 256 * r, row = q >> 4, pc = q & 15;
+        const bool ok = k0 + row < k && n0 + 4 * pc < n;
+        const f32x4 v = ok ? *reinterpret_cast<const f32x4*>(in + (k0 + row) * ld + n0 + 4 * pc) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[row][4 * pc + e] = v[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int64_t chunk = k0 / 32 + c;
+        if (chunk >= nkc) break;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {  // 64 rows x 8 pieces of 4 k, two passes
+            const int p = threadIdx.x + 256 * h, nl = p >> 3, kq = (p & 7) * 4;
+            f32x4 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = t[32 * c + kq + e][nl];
+            *reinterpret_cast<f32x4*>(out + ((nb * nkc + chunk) * 64 + nl) * 32 + kq) = v;
+        }
+    }
+}
+
 hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                            int64_t m, int64_t n, int64_t k, int tile, hipStream_t st)
 {
@@ -594,6 +670,23 @@ hipError_t launch_convert_bf16_split_blocked(const double* B, int64_t ldb, __bf1
     if (k == 0 || n == 0) return hipSuccess;
     const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((k + 63) / 64));
     convert_bf16_split_blocked_kernel<<<grid, 256, 0, st>>>(B, ldb, hi, lo, k, n, bf16_k_chunks(k));
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_bf16_pair_blocked(const __bf16* hi_in, const __bf16* lo_in, int64_t ld, __bf16* hi,
+                                              __bf16* lo, int64_t k, int64_t n, hipStream_t st)
+{
+    if (k == 0 || n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((k + 63) / 64));
+    transpose_bf16_pair_blocked_kernel<<<grid, 256, 0, st>>>(hi_in, lo_in, ld, hi, lo, k, n, bf16_k_chunks(k));
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_f32_blocked(const float* in, int64_t ld, float* out, int64_t k, int64_t n, hipStream_t st)
+{
+    if (k == 0 || n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((k + 63) / 64));
+    transpose_f32_blocked_kernel<<<grid, 256, 0, st>>>(in, ld, out, k, n, f32_k_chunks(k));
     return hipGetLastError();
 }
 

@@ -802,6 +802,22 @@ def test_matmul_low_precision_compressed_b(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("tile", [64, 128])
+@pytest.mark.parametrize("m,k,n", [(136, 200, 72), (392, 136, 264)])
+def test_matmul_low_precision_compressed_b_is_dense_of_its_rebuild(prec, tile, m, k, n):
+    """A compressed B is rebuilt straight into the operand precision and
+    transposed; a dense B is converted from binary64.  Both must give the
+    same operands, hence the same product bit for bit, when the dense B is
+    the binary64 rebuild of the compressed one."""
+    A = smooth_field(m, 4, 2.0, 1e-3, 480 + m, cols=k)
+    B = smooth_field(k, 4, 2.0, 1e-3, 481 + k, cols=n)
+    gx, gy = blaz.compress(dev(A)), blaz.compress(dev(B))
+    got = blaz.matmul(gx, gy, prec=prec, tile=tile)
+    want = blaz.matmul(gx, blaz.decompress(gy), prec=prec, tile=tile)
+    assert torch.equal(got, want), (prec, tile, m, k, n, (got - want).abs().max().item())
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_matmul_low_precision_full_size_4096_sampled(prec):
     """Compressed 4096^2 field times dense U[-1, 1] in FP32 / BF16x3: sampled
     entries against the oracle, and the whole product against the FP64 path."""
