@@ -596,7 +596,15 @@ def main():
         "hardware": "Intel Core i7-1165G7, 4 cores (the paper's machine; no GPU numbers are published)",
         "blaz_add_n2000_ms": 0.15, "blaz_add_n2000_GBps_fp64_equiv": 640.0,
         "blaz_scale_n2000_ms": 0.14, "blaz_scale_n2000_GBps_fp64_equiv": 457.0,
-        "dense_add_n2000_GBps": 10.3, "note": "context only, not a target"}
+        "dense_add_n2000_GBps": 10.3,
+        # ratios against the uncompressed operation on the same CPU, read from
+        # the performance figure (Experimental Evaluation, Performance, Figure
+        # figtime); zfp runs at a rate equivalent to blaz's
+        "vs_uncompressed": {"blaz_add_speedup": {"n80": 3, "n2000": 62},
+                            "zfp_add_slowdown": {"n80": 121, "n2000": 115},
+                            "dot_slowdown_n2000": {"blaz": 31, "zfp": 62},
+                            "matmul": "blaz close to the uncompressed product, zfp about 10x slower than blaz"},
+        "note": "context only, not a target"}
     del D
     if not args.no_extra:
         print("# cold/warm single-op leg", file=sys.stderr, flush=True)
