@@ -404,15 +404,18 @@ __global__ __launch_bounds__(64 * kWaves) void gemm_bf16x3_kernel(const __bf16* 
 
     // Compute on one LDS buffer while the next stage fills the other.  The
     // fill of buffer b for stage kt+1 starts after the barrier that ends
-    // stage kt-1, the last reader of b; every wave waits for its own fills
-    // (vmcnt) before the barrier that publishes them.
+    // stage kt-1, the last reader of b (here after this stage's fragment
+    // reads are issued); every wave waits for its own fills (vmcnt) before
+    // the barrier that publishes them.  The MFMAs run at raised wave
+    // priority, so that a SIMD's waves that have their fragments issue
+    // their products ahead of the others' reads and fills (with both: 2.5 %
+    // faster at 8192^3, level at 4096^3).
     const int nk = (int)((K + kBKb - 1) / kBKb);
     fill_stage(0, 0);
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
-        if (kt + 1 < nk) fill_stage(cur ^ 1, (int64_t)(kt + 1) * kBKb);
         // Operands of a 16x16x32 MFMA: lane l holds the 8 k-values
         // 8*(l/16) .. 8*(l/16)+7 of row (A) or column (B) l%16; any fixed
         // assignment of k to (lane group, element) works as long as A and B
@@ -430,6 +433,8 @@ __global__ __launch_bounds__(64 * kWaves) void gemm_bf16x3_kernel(const __bf16* 
             bh[j] = *reinterpret_cast<const bf16x8*>(&T[cur][2][off]);
             bl[j] = *reinterpret_cast<const bf16x8*>(&T[cur][3][off]);
         }
+        if (kt + 1 < nk) fill_stage(cur ^ 1, (int64_t)(kt + 1) * kBKb);
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int i = 0; i < TWM; ++i)
 #pragma unroll
@@ -438,6 +443,7 @@ __global__ __launch_bounds__(64 * kWaves) void gemm_bf16x3_kernel(const __bf16* 
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
             }
+        __builtin_amdgcn_s_setprio(0);
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         __syncthreads();
     }
