@@ -153,6 +153,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             // A operand: lane holds A[m = lane%16][k = lane/16]; B operand:
@@ -167,6 +168,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
 #pragma unroll
                 for (int j = 0; j < TW; ++j) acc[i][j] = MF::op(a[i], b[j], acc[i][j]);
         }
+        __builtin_amdgcn_s_setprio(0);
         if (kt + 1 < nk) {
             store_stage(cur ^ 1);
             if (kt + 2 < nk) load_stage((int64_t)(kt + 2) * BK);
@@ -263,6 +265,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int cc = 0; cc < CPR; cc += 4) {
             const int c = cc + (lane >> 4);
@@ -281,6 +284,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
                     for (int j = 0; j < TW; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[i][s], b4[j][s], acc[i][j], 0, 0, 0);
         }
+        __builtin_amdgcn_s_setprio(0);
         if (kt + 1 < nk) {
             store_stage(cur ^ 1);
             if (kt + 2 < nk) load_stage((int64_t)(kt + 2) * kBKf);
