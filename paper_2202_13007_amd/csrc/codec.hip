@@ -118,14 +118,16 @@ hipError_t launch_decompress(const blaz_matrix& m, double* A, int64_t lda, hipSt
 
 hipError_t launch_decompress_f32(const blaz_matrix& m, float* A, int64_t lda, hipStream_t st)
 {
-    const bool vec = (reinterpret_cast<uintptr_t>(A) % 8 == 0) && (lda % 2 == 0);
+    // each block row is two 16-byte stores: 16-byte aligned rows
+    const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % 4 == 0);
     return launch_decompress_to(m, OutF32{A}, vec, lda, st);
 }
 
 hipError_t launch_decompress_bf16_split(const blaz_matrix& m, __bf16* hi, __bf16* lo, int64_t lda, hipStream_t st)
 {
-    const bool vec = (reinterpret_cast<uintptr_t>(hi) % 4 == 0) && (reinterpret_cast<uintptr_t>(lo) % 4 == 0) &&
-                     (lda % 2 == 0);
+    // each block row is one 16-byte store per array: 16-byte aligned rows
+    const bool vec = (reinterpret_cast<uintptr_t>(hi) % 16 == 0) && (reinterpret_cast<uintptr_t>(lo) % 16 == 0) &&
+                     (lda % 8 == 0);
     return launch_decompress_to(m, OutBF16Split{hi, lo}, vec, lda, st);
 }
 
