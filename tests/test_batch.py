@@ -3,9 +3,11 @@
 CPU tests cover the host-only planner (validation, chunk counts, dropped
 empty items).  GPU tests check that every batched result equals the
 standalone entry point's result bit for bit, for several grid sizes and
-when the run is captured in a HIP graph and replayed.
+when the run is captured in a HIP graph and replayed; a captured sequence of
+the single-operation entry points replays bit for bit too.
 """
 import ctypes
+import types
 
 import numpy as np
 import pytest
@@ -231,3 +233,62 @@ def test_batch_rejects_invalid_item_without_launching():
     with pytest.raises(blaz.BlazError) as e:
         B.plan()
     assert "item 1" in str(e.value)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_request_sequence_graph_capture_replays(prec):
+    """The seven-launch sequence of the small workload (compress x2, add,
+    scale, decompress, dot, matmul) captured in one graph: every replay,
+    after the outputs are cleared eagerly, gives the eager results bit for
+    bit (no launch in the sequence records a memset or allocates)."""
+    import torch
+    import paper_2202_13007_amd as blaz
+    A = smooth_field(136, 4, 2.0, 1e-3, 601, cols=200)
+    Bm = smooth_field(200, 4, 2.0, 1e-3, 602, cols=72)
+    dA = torch.from_numpy(A).cuda()
+    dB = torch.from_numpy(Bm).cuda()
+    dA2 = torch.from_numpy(smooth_field(136, 4, 2.0, 1e-3, 603, cols=200)).cuda()
+    x, y = blaz.BlazMatrix.empty(136, 200), blaz.BlazMatrix.empty(200, 72)
+    x2, z, w = (blaz.BlazMatrix.empty(136, 200) for _ in range(3))
+    D = torch.empty((136, 200), dtype=torch.float64, device="cuda")
+    C = torch.empty((136, 72), dtype=torch.float64, device="cuda")
+    rows = torch.arange(0, 136, 9, dtype=torch.int64, device="cuda")   # 16 lines of x
+    cols = torch.arange(0, 64, 4, dtype=torch.int64, device="cuda")    # 16 columns of y
+    dots = torch.empty(rows.numel(), dtype=torch.float64, device="cuda")
+    ws = torch.empty(blaz.matmul_workspace_bytes(136, 72, 200, True, prec), dtype=torch.uint8, device="cuda")
+
+    def sequence():
+        blaz.compress(dA, out=x)
+        blaz.compress(dB, out=y)
+        blaz.compress(dA2, out=x2)
+        blaz.add(x, x2, out=z)
+        blaz.scale(z, 1.7, out=w)
+        blaz.decompress(w, out=D)
+        blaz.dot(x, rows, y, cols, out=dots)
+        blaz.matmul(w, y, out=C, prec=prec, workspace=ws)
+
+    outs = (x, y, x2, z, w, D, dots, C)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        sequence()  # eager run: the reference, and the warm-up
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    def snap(o):
+        if isinstance(o, torch.Tensor):
+            return o.clone()
+        return types.SimpleNamespace(**{k: getattr(o, k).clone() for k in ("f", "s", "phi", "codes")})
+
+    want = [snap(o) for o in outs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sequence()
+    for rep in range(3):
+        for o in outs:
+            clear(o)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, wnt in zip(outs, want):
+            assert_equal(snap(o), wnt)
