@@ -10,14 +10,19 @@
 //           C = Alo Bhi + Ahi Blo + Ahi Bhi (the Alo Blo term, ~2^-16
 //           relative, is dropped), FP32 accumulation
 //
-// Tiling: a 256-thread workgroup computes a BMxBM tile of C (BM = 128 or 64);
-// its four waves each own a quadrant as (BM/32)x(BM/32) MFMA tiles of 16x16.
-// The 64 tile gives small products four times as many workgroups.  K advances
-// through LDS in steps of BK; the next step's global loads are issued into
-// registers before the current step's MFMAs, so HBM/L2 latency overlaps the
-// matrix math.  Workgroup ids are remapped so that each XCD (the hardware
-// deals workgroups to the 8 XCDs round-robin) works on a contiguous group of
-// tiles that share rows of A and columns of B in its own L2.
+// Tiling: a workgroup computes a BMxBM tile of C (BM = 128 or 64; the 64
+// tile gives small products four times as many workgroups).  FP64 and FP32
+// run four waves, each owning a quadrant as (BM/32)x(BM/32) MFMA tiles of
+// 16x16; K advances through double-buffered LDS tiles, and the stage after
+// next is loaded into registers during the current stage's MFMAs, so HBM/L2
+// latency overlaps the matrix math.  BF16x3 fills its LDS tiles straight from
+// memory (global_load_lds) and runs eight waves on the 128 tile.  The MFMAs
+// run at raised wave priority.  Workgroup ids are remapped so that each XCD
+// (the hardware deals workgroups to the 8 XCDs round-robin) works on a
+// contiguous group of tiles that share rows of A and columns of B in its own
+// L2.  The file also holds the preparation of B for the FP32 and BF16x3
+// products: conversion of a dense binary64 B, or transposition of a
+// compressed B rebuilt in the operand precision, into blocked B^T tiles.
 #include <hip/hip_runtime.h>
 
 #include "blaz_internal.hpp"
