@@ -10,8 +10,7 @@ import oracle
 import paper_2202_13007_amd as blaz
 from synth import smooth_field, uniform_matrix, workload_inputs
 
-from parity import (TIE_RATE_MAX, assert_blocks_close, assert_dots_close, assert_same_compressed,
-                    compare_compressed, near_integer)
+from parity import assert_blocks_close, assert_dots_close, assert_same_compressed, compare_compressed
 
 pytestmark = pytest.mark.gpu
 
