@@ -12,8 +12,6 @@
 namespace blaz {
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 
@@ -343,9 +341,10 @@ __device__ __forceinline__ void quantize_store_lines(const double D[64], const S
 // Output forms of the decompression: binary64 (the plain method), and the
 // operand forms of the low-precision contractions in blaz_matmul: FP32, or
 // BF16 hi + lo with hi = bf16(x), lo = bf16(x - hi).
-// kRow8: the form can store one block row (8 consecutive values) of a lane
-// with 16-byte stores of its own (the narrow forms: a row is 32 or 2 x 16
-// bytes, and the rows of adjacent lanes' blocks are adjacent).
+// kRow8: the form stores one block row (8 consecutive values) of a lane with
+// 16-byte stores of its own (store8; the narrow forms: a row is 32 or
+// 2 x 16 bytes, and the rows of adjacent lanes' blocks are adjacent);
+// otherwise the rows go through LDS to full-width stores (store2).
 struct OutF64 {
     static constexpr bool kRow8 = false;
     double* p;
@@ -363,10 +362,6 @@ struct OutF32 {
         *reinterpret_cast<f32x4v*>(p + off) = f32x4v{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
         *reinterpret_cast<f32x4v*>(p + off + 4) = f32x4v{(float)v[4], (float)v[5], (float)v[6], (float)v[7]};
     }
-    __device__ void store2(int64_t off, double a, double b) const
-    {
-        *reinterpret_cast<f32x2*>(p + off) = f32x2{(float)a, (float)b};
-    }
     __device__ void store(int64_t off, double a) const { p[off] = (float)a; }
 };
 struct OutBF16Split {
@@ -375,12 +370,6 @@ struct OutBF16Split {
     __bf16* lo;
     __device__ static __bf16 high(double x) { return (__bf16)(float)x; }
     __device__ static __bf16 low(double x, __bf16 h) { return (__bf16)(float)(x - (double)(float)h); }
-    __device__ void store2(int64_t off, double a, double b) const
-    {
-        const __bf16 ha = high(a), hb = high(b);
-        *reinterpret_cast<bf16x2*>(hi + off) = bf16x2{ha, hb};
-        *reinterpret_cast<bf16x2*>(lo + off) = bf16x2{low(a, ha), low(b, hb)};
-    }
     __device__ void store(int64_t off, double a) const
     {
         const __bf16 h = high(a);
