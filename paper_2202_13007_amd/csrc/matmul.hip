@@ -504,7 +504,10 @@ __global__ __launch_bounds__(256) void convert_f32_blocked_kernel(const double* 
                                                                   int64_t nkc)
 {
     __shared__ double t[64][65];
-    const int64_t k0 = (int64_t)blockIdx.y * 64, nb = blockIdx.x, n0 = nb * 64;
+    // one-dimensional grid over the 64 x 64 tiles, n fastest (a grid's y
+    // extent is limited to 65536, which would bound k)
+    const int64_t ntn = (n + 63) / 64;
+    const int64_t nb = (int64_t)blockIdx.x % ntn, k0 = ((int64_t)blockIdx.x / ntn) * 64, n0 = nb * 64;
     load_b_tile(B, ldb, k, n, k0, n0, t);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -532,7 +535,10 @@ __global__ __launch_bounds__(256) void convert_bf16_split_blocked_kernel(const d
                                                                          int64_t n, int64_t nkc)
 {
     __shared__ double t[64][65];
-    const int64_t k0 = (int64_t)blockIdx.y * 64, nb = blockIdx.x, n0 = nb * 64;
+    // one-dimensional grid over the 64 x 64 tiles, n fastest (a grid's y
+    // extent is limited to 65536, which would bound k)
+    const int64_t ntn = (n + 63) / 64;
+    const int64_t nb = (int64_t)blockIdx.x % ntn, k0 = ((int64_t)blockIdx.x / ntn) * 64, n0 = nb * 64;
     load_b_tile(B, ldb, k, n, k0, n0, t);
     const int nl = threadIdx.x >> 2, kq = (threadIdx.x & 3) * 8;  // 64 rows x 4 pieces of 8 k
 #pragma unroll
@@ -575,7 +581,10 @@ __global__ __launch_bounds__(256) void transpose_bf16_pair_blocked_kernel(const 
                                                                           int64_t n, int64_t nkc)
 {
     __shared__ uint32_t th[64][33], tl[64][33];  // 64 k-rows of 64 bf16 (+ 2 of padding)
-    const int64_t k0 = (int64_t)blockIdx.y * 64, nb = blockIdx.x, n0 = nb * 64;
+    // one-dimensional grid over the 64 x 64 tiles, n fastest (a grid's y
+    // extent is limited to 65536, which would bound k)
+    const int64_t ntn = (n + 63) / 64;
+    const int64_t nb = (int64_t)blockIdx.x % ntn, k0 = ((int64_t)blockIdx.x / ntn) * 64, n0 = nb * 64;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {  // 64 rows x 8 pieces of 8 bf16
         const int q = threadIdx.x + 256 * r, row = q >> 3, pc = q & 7;
@@ -612,7 +621,10 @@ __global__ __launch_bounds__(256) void transpose_f32_blocked_kernel(const float*
                                                                     int64_t nkc)
 {
     __shared__ float t[64][65];
-    const int64_t k0 = (int64_t)blockIdx.y * 64, nb = blockIdx.x, n0 = nb * 64;
+    // one-dimensional grid over the 64 x 64 tiles, n fastest (a grid's y
+    // extent is limited to 65536, which would bound k)
+    const int64_t ntn = (n + 63) / 64;
+    const int64_t nb = (int64_t)blockIdx.x % ntn, k0 = ((int64_t)blockIdx.x / ntn) * 64, n0 = nb * 64;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {  // 64 rows x 16 pieces of 4 floats
         const int q = threadIdx.x + 256 * r, row = q >> 4, pc = q & 15;
@@ -673,7 +685,7 @@ hipError_t launch_gemm_bf16x3(const __bf16* Ahi, const __bf16* Alo, int64_t lda,
 hipError_t launch_convert_f32_blocked(const double* B, int64_t ldb, float* out, int64_t k, int64_t n, hipStream_t st)
 {
     if (k == 0 || n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((k + 63) / 64));
+    const unsigned grid = (unsigned)(((n + 63) / 64) * ((k + 63) / 64));
     convert_f32_blocked_kernel<<<grid, 256, 0, st>>>(B, ldb, out, k, n, f32_k_chunks(k));
     return hipGetLastError();
 }
@@ -682,7 +694,7 @@ hipError_t launch_convert_bf16_split_blocked(const double* B, int64_t ldb, __bf1
                                              int64_t n, hipStream_t st)
 {
     if (k == 0 || n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((k + 63) / 64));
+    const unsigned grid = (unsigned)(((n + 63) / 64) * ((k + 63) / 64));
     convert_bf16_split_blocked_kernel<<<grid, 256, 0, st>>>(B, ldb, hi, lo, k, n, bf16_k_chunks(k));
     return hipGetLastError();
 }
@@ -691,7 +703,7 @@ hipError_t launch_transpose_bf16_pair_blocked(const __bf16* hi_in, const __bf16*
                                               __bf16* lo, int64_t k, int64_t n, hipStream_t st)
 {
     if (k == 0 || n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((k + 63) / 64));
+    const unsigned grid = (unsigned)(((n + 63) / 64) * ((k + 63) / 64));
     transpose_bf16_pair_blocked_kernel<<<grid, 256, 0, st>>>(hi_in, lo_in, ld, hi, lo, k, n, bf16_k_chunks(k));
     return hipGetLastError();
 }
@@ -699,7 +711,7 @@ hipError_t launch_transpose_bf16_pair_blocked(const __bf16* hi_in, const __bf16*
 hipError_t launch_transpose_f32_blocked(const float* in, int64_t ld, float* out, int64_t k, int64_t n, hipStream_t st)
 {
     if (k == 0 || n == 0) return hipSuccess;
-    const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((k + 63) / 64));
+    const unsigned grid = (unsigned)(((n + 63) / 64) * ((k + 63) / 64));
     transpose_f32_blocked_kernel<<<grid, 256, 0, st>>>(in, ld, out, k, n, f32_k_chunks(k));
     return hipGetLastError();
 }

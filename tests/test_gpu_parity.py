@@ -816,6 +816,33 @@ def test_matmul_low_precision_compressed_b_is_dense_of_its_rebuild(prec, tile, m
     assert torch.equal(got, want), (prec, tile, m, k, n, (got - want).abs().max().item())
 
 
+def test_matmul_low_precision_k_beyond_a_grid_dimension():
+    """k = 4,194,368: 65,537 tiles of 64 k-values, one more than a grid's y
+    extent allows, so the B preparations must not put k on that axis.  A
+    property check (the oracle would take minutes here): the FP32 and BF16x3
+    products, with B dense and compressed, agree with the FP64 product (held
+    to the oracle by the tests above) within the low-precision bounds."""
+    m, k, n = 8, 4_194_368, 8
+    A = smooth_field(m, 2, 1.0, 1e-3, 620, cols=k)
+    B = uniform_matrix(k, n, 621)
+    gx = blaz.compress(dev(A))
+    dB = dev(B)
+    gy = blaz.compress(dB)
+    Bd = blaz.decompress(gy)
+    Xd = blaz.decompress(gx)
+    for b, bfull in ((dB, dB), (gy, Bd)):
+        want = blaz.matmul(gx, b, prec="fp64").cpu().numpy()
+        mag = (Xd.abs() @ bfull.abs()).cpu().numpy()
+        for prec in ("fp32", "bf16x3"):
+            got = blaz.matmul(gx, b, prec=prec).cpu().numpy()
+            assert_dots_close(got, want, mag, rel=low_precision_tol(prec, k), what=f"matmul {prec} k={k}")
+            # at this K the FP32 accumulation dominates both arithmetics: its
+            # expected size, plus the BF16 split's own 3 * 2^-16
+            rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+            fro = (2 + 4 * np.sqrt(k)) * U32 + (3 * 2.0 ** -16 if prec == "bf16x3" else 0.0)
+            assert rel < fro, (prec, rel, fro)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_matmul_low_precision_full_size_4096_sampled(prec):
     """Compressed 4096^2 field times dense U[-1, 1] in FP32 / BF16x3: sampled
