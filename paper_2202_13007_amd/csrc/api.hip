@@ -237,16 +237,18 @@ static blaz_status matmul_impl(const blaz_matrix* a, const blaz_matrix* b, const
     char* wtmp = ws + wl.a_bytes + wl.b_bytes;
     using namespace blaz::detail;
 
+    // With B compressed too, both rebuilds go into one launch.
     if (prec == BLAZ_PREC_FP64) {
         double* A64 = reinterpret_cast<double*>(wa);
-        if (hipError_t e = launch_decompress(*a, A64, k, stream)) return hip_status(e);
         const double* bop = bdense;
         int64_t ldbop = ldb;
         if (b) {
             double* B64 = reinterpret_cast<double*>(wb);
-            if (hipError_t e = launch_decompress(*b, B64, n, stream)) return hip_status(e);
+            if (hipError_t e = launch_decompress_pair(*a, A64, k, *b, B64, n, stream)) return hip_status(e);
             bop = B64;
             ldbop = n;
+        } else if (hipError_t e = launch_decompress(*a, A64, k, stream)) {
+            return hip_status(e);
         }
         return hip_status(launch_gemm_f64(A64, k, bop, ldbop, c, ldc, m, n, k, tile, stream));
     }
@@ -258,13 +260,13 @@ static blaz_status matmul_impl(const blaz_matrix* a, const blaz_matrix* b, const
     if (prec == BLAZ_PREC_FP32) {
         float* A32 = reinterpret_cast<float*>(wa);
         float* B32 = reinterpret_cast<float*>(wb);
-        if (hipError_t e = launch_decompress_f32(*a, A32, k, stream)) return hip_status(e);
         if (b) {
             float* T32 = reinterpret_cast<float*>(wtmp);
-            if (hipError_t e = launch_decompress_f32(*b, T32, n, stream)) return hip_status(e);
+            if (hipError_t e = launch_decompress_pair_f32(*a, A32, k, *b, T32, n, stream)) return hip_status(e);
             if (hipError_t e = launch_transpose_f32_blocked(T32, n, B32, k, n, stream)) return hip_status(e);
-        } else if (hipError_t e = launch_convert_f32_blocked(bdense, ldb, B32, k, n, stream)) {
-            return hip_status(e);
+        } else {
+            if (hipError_t e = launch_decompress_f32(*a, A32, k, stream)) return hip_status(e);
+            if (hipError_t e = launch_convert_f32_blocked(bdense, ldb, B32, k, n, stream)) return hip_status(e);
         }
         return hip_status(launch_gemm_f32(A32, k, B32, c, ldc, m, n, k, tile, stream));
     }
@@ -272,15 +274,17 @@ static blaz_status matmul_impl(const blaz_matrix* a, const blaz_matrix* b, const
     __bf16* Alo = reinterpret_cast<__bf16*>(wa + wl.a_bytes / 2);
     __bf16* Bhi = reinterpret_cast<__bf16*>(wb);
     __bf16* Blo = reinterpret_cast<__bf16*>(wb + wl.b_bytes / 2);
-    if (hipError_t e = launch_decompress_bf16_split(*a, Ahi, Alo, k, stream)) return hip_status(e);
     if (b) {
         __bf16* Thi = reinterpret_cast<__bf16*>(wtmp);
         __bf16* Tlo = Thi + k * n;
-        if (hipError_t e = launch_decompress_bf16_split(*b, Thi, Tlo, n, stream)) return hip_status(e);
+        if (hipError_t e = launch_decompress_pair_bf16_split(*a, Ahi, Alo, k, *b, Thi, Tlo, n, stream))
+            return hip_status(e);
         if (hipError_t e = launch_transpose_bf16_pair_blocked(Thi, Tlo, n, Bhi, Blo, k, n, stream))
             return hip_status(e);
-    } else if (hipError_t e = launch_convert_bf16_split_blocked(bdense, ldb, Bhi, Blo, k, n, stream)) {
-        return hip_status(e);
+    } else {
+        if (hipError_t e = launch_decompress_bf16_split(*a, Ahi, Alo, k, stream)) return hip_status(e);
+        if (hipError_t e = launch_convert_bf16_split_blocked(bdense, ldb, Bhi, Blo, k, n, stream))
+            return hip_status(e);
     }
     return hip_status(launch_gemm_bf16x3(Ahi, Alo, k, Bhi, Blo, c, ldc, m, n, k, tile, stream));
 }

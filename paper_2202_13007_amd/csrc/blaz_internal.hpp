@@ -44,6 +44,15 @@ hipError_t launch_decompress(const blaz_matrix& m, double* A, int64_t lda, hipSt
 // Decompression into the operand forms of the low-precision contractions.
 hipError_t launch_decompress_f32(const blaz_matrix& m, float* A, int64_t lda, hipStream_t st);
 hipError_t launch_decompress_bf16_split(const blaz_matrix& m, __bf16* hi, __bf16* lo, int64_t lda, hipStream_t st);
+// Both operands of a product (a, then b) rebuilt in one launch, in the same
+// output form: one launch when they have the same kept lines, else two.
+hipError_t launch_decompress_pair(const blaz_matrix& a, double* A, int64_t lda, const blaz_matrix& b, double* B,
+                                  int64_t ldb, hipStream_t st);
+hipError_t launch_decompress_pair_f32(const blaz_matrix& a, float* A, int64_t lda, const blaz_matrix& b, float* B,
+                                      int64_t ldb, hipStream_t st);
+hipError_t launch_decompress_pair_bf16_split(const blaz_matrix& a, __bf16* Ahi, __bf16* Alo, int64_t lda,
+                                             const blaz_matrix& b, __bf16* Bhi, __bf16* Blo, int64_t ldb,
+                                             hipStream_t st);
 hipError_t launch_add(const blaz_matrix& x, const blaz_matrix& y, const blaz_matrix& z, bool negate_y,
                       hipStream_t st);
 hipError_t launch_scale(const blaz_matrix& x, double c, const blaz_matrix& z, hipStream_t st);
