@@ -280,3 +280,16 @@ def test_tie_classifier():
         compare_compressed((f, s, phi, codes_g), (f, s, phi, codes_o), code_x, np.array([20.5, 20.5]))
     with pytest.raises(AssertionError):    # s must be bit-exact
         compare_compressed((f, s + 1e-16 * 4, phi, codes), (f, s, phi, codes), code_x, np.array([20.5, 20.5]))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU's shard; asked for more it says so and
+    exits with status 2 before touching a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=root)
+    assert r.returncode == 2, (r.returncode, r.stdout[-500:], r.stderr[-500:])
+    assert "one GPU only" in r.stdout + r.stderr
