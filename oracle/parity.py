@@ -1,4 +1,5 @@
-"""Comparison rules between the HIP library and the FP64 oracle.
+"""Comparison rules between the HIP library and the FP64 oracle -- test
+infrastructure, used only by the tests and the benchmark's parity report.
 
 * f, s, phi, codes of a compression: bit-exact, except at rounding-boundary
   ties.  A mismatching code (or phi) is a tie when the oracle's value before
@@ -9,6 +10,8 @@
 * add, sub, scale: bit-exact.
 * decompression: |X_gpu - X_oracle| <= 1e-12 * max|X_oracle| per 8x8 block.
 * dot and matmul: |r_gpu - r_oracle| <= 1e-12 * sum_k |x_k y_k|.
+* products whose contraction runs in FP32 or BF16 hi+lo (three products):
+  |r_gpu - r_oracle| <= low_precision_tol(prec, k) * sum_k |x_k y_k|.
 """
 from __future__ import annotations
 
@@ -18,6 +21,16 @@ TIE_REL = 2.0 ** -40
 TIE_RATE_MAX = 1e-6
 DECOMP_REL = 1e-12
 DOT_REL = 1e-12
+U32 = 2.0 ** -24
+
+
+def low_precision_tol(prec, k):
+    """Bound on |C - C64| relative to sum_k |a_k b_k| for a K-term product
+    with FP32 accumulation: operand rounding (FP32: 2 u32; BF16x3: 3 * 2^-16
+    from the split and the dropped lo*lo term) plus the accumulation (K/4 u32
+    for the FP32 16x16x4 form, K u32 for BF16x3, whose MFMA sums 32 products
+    per step)."""
+    return (2 + k / 4 + 4) * U32 if prec == "fp32" else 3 * 2.0 ** -16 + (k + 4) * U32
 
 
 def near_integer(x):

@@ -1,10 +1,12 @@
 """Batching: one persistent launch over a flat chunk queue.
 
 CPU tests cover the host-only planner (validation, chunk counts, dropped
-empty items).  GPU tests check that every batched result equals the
-standalone entry point's result bit for bit, for several grid sizes and
-when the run is captured in a HIP graph and replayed; a captured sequence of
-the single-operation entry points replays bit for bit too.
+empty items).  GPU tests check every batched result against the FP64 oracle
+under the parity rules (compress bit-exact except classified boundary ties,
+add/sub/scale bit-exact, decompression and dot products within 1e-12) and
+against the standalone entry point's result bit for bit, for several grid
+sizes and when the run is captured in a HIP graph and replayed; a captured
+sequence of the single-operation entry points replays bit for bit too.
 """
 import ctypes
 import types
@@ -107,54 +109,105 @@ def test_plan_rejects_partial_overlap():
 # --------------------------------------------------------------------------
 
 def make_workload(torch, blaz):
-    """A mix of operations on matrices of uneven sizes, with both the batch
-    and the standalone results' destinations."""
+    """A mix of operations on matrices of uneven sizes.  The operands of the
+    block-level operations are the oracle's compressions of seeded fields,
+    uploaded.  Returns the batch, the standalone results for each batched
+    destination, and for each destination the oracle's check."""
+    import oracle
+    from oracle.parity import (TIE_RATE_MAX, assert_blocks_close, assert_dots_close, assert_same_compressed,
+                               compare_compressed)
+
+    def up(c):
+        return blaz.BlazMatrix.from_host(c.rows, c.cols, c.f, c.s, c.phi, c.codes)
+
+    def same_as(o, what):
+        def check(got):
+            assert_same_compressed(got.to_host(), (o.f, o.s, o.phi, o.codes), what)
+        return check
+
+    def compressed_as(A, what):
+        o, (_, code_x, phi_x) = oracle.compress(A, with_debug=True)
+
+        def check(got):
+            ties = compare_compressed(got.to_host(), (o.f, o.s, o.phi, o.codes), code_x, phi_x, what)
+            assert ties <= TIE_RATE_MAX * (o.codes.size + len(o.phi)), (what, ties)
+        return check
+
+    def dense_as(want, what):
+        def check(got):
+            assert_blocks_close(got.cpu().numpy(), want, what=what)
+        return check
+
+    def dots_as(want, mag, what):
+        def check(got):
+            assert_dots_close(got.cpu().numpy(), want, mag, what=what)
+        return check
+
     rng = np.random.default_rng(0)
     shapes = [(8, 8), (64, 64), (24, 1032), (264, 520), (1032, 528)]
-    dense = [torch.from_numpy(smooth_field(r, 6, 3.0, 1e-3, 900 + i, cols=c)).cuda() for i, (r, c) in enumerate(shapes)]
-    dense2 = [torch.from_numpy(smooth_field(r, 6, 3.0, 1e-3, 950 + i, cols=c)).cuda() for i, (r, c) in enumerate(shapes)]
-    # operands for the ops, compressed by the standalone path
-    X = [blaz.compress(d) for d in dense]
-    Y = [blaz.compress(d) for d in dense2]
+    hostA = [smooth_field(r, 6, 3.0, 1e-3, 900 + i, cols=c) for i, (r, c) in enumerate(shapes)]
+    hostB = [smooth_field(r, 6, 3.0, 1e-3, 950 + i, cols=c) for i, (r, c) in enumerate(shapes)]
+    dense = [torch.from_numpy(a).cuda() for a in hostA]
+    OX = [oracle.compress(a) for a in hostA]
+    OY = [oracle.compress(b) for b in hostB]
+    X = [up(o) for o in OX]
+    Y = [up(o) for o in OY]
     B = blaz.Batch()
-    expect = []  # (batched destination, standalone result)
+    expect = []  # (batched destination, standalone result, oracle check)
     for i, (r, c) in enumerate(shapes):
         out = blaz.BlazMatrix.empty(r, c)
         B.compress(dense[i], out)
-        expect.append((out, X[i]))
+        expect.append((out, blaz.compress(dense[i]), compressed_as(hostA[i], f"compress {r}x{c}")))
         z = blaz.BlazMatrix.empty(r, c)
         B.add(X[i], Y[i], z)
-        expect.append((z, blaz.add(X[i], Y[i])))
+        expect.append((z, blaz.add(X[i], Y[i]), same_as(oracle.add(OX[i], OY[i]), f"add {r}x{c}")))
         w = blaz.BlazMatrix.empty(r, c)
         B.sub(X[i], Y[i], w)
-        expect.append((w, blaz.sub(X[i], Y[i])))
+        expect.append((w, blaz.sub(X[i], Y[i]),
+                       same_as(oracle.add(OX[i], oracle.scale(OY[i], -1.0)), f"sub {r}x{c}")))
         v = blaz.BlazMatrix.empty(r, c)
         B.scale(Y[i], -1.7, v)
-        expect.append((v, blaz.scale(Y[i], -1.7)))
+        expect.append((v, blaz.scale(Y[i], -1.7), same_as(oracle.scale(OY[i], -1.7), f"scale {r}x{c}")))
         D = torch.empty((r, c), dtype=torch.float64, device="cuda")
         B.decompress(X[i], D)
-        expect.append((D, blaz.decompress(X[i])))
-    # dot products: 264x520 times (520x?) -> use x = X[3] (264x520) with y = compressed 520x64
-    ymat = blaz.compress(torch.from_numpy(smooth_field(520, 4, 2.0, 1e-3, 990, cols=64)).cuda())
-    xrow = torch.from_numpy(rng.integers(0, 264, 100)).cuda()
-    ycol = torch.from_numpy(rng.integers(0, 64, 100)).cuda()
+        expect.append((D, blaz.decompress(X[i]), dense_as(oracle.decompress(OX[i]), f"decompress {r}x{c}")))
+    # dot products: lines of the 264x520 matrix with columns of a compressed 520x64
+    oy = oracle.compress(smooth_field(520, 4, 2.0, 1e-3, 990, cols=64))
+    ymat = up(oy)
+    Xd3, Yd = oracle.decompress(OX[3]), oracle.decompress(oy)
+    xr = rng.integers(0, 264, 100)
+    yc = rng.integers(0, 64, 100)
+    xrow, ycol = torch.from_numpy(xr).cuda(), torch.from_numpy(yc).cuda()
     out = torch.empty(100, dtype=torch.float64, device="cuda")
     B.dot(X[3], xrow, ymat, ycol, out)
-    expect.append((out, blaz.dot(X[3], xrow, ymat, ycol)))
+    expect.append((out, blaz.dot(X[3], xrow, ymat, ycol),
+                   dots_as(oracle.dot(OX[3], xr, oy, yc),
+                           np.array([np.abs(Xd3[i]) @ np.abs(Yd[:, j]) for i, j in zip(xr, yc)]), "dot")))
     # aligned groups (the 8 lines of a block row in order) take the grouped path
-    lines = torch.arange(64, dtype=torch.int64).cuda()
+    li = np.arange(64)
+    lines = torch.from_numpy(li).cuda()
     out3 = torch.empty(64, dtype=torch.float64, device="cuda")
     B.dot(X[3], lines, ymat, lines, out3)
-    expect.append((out3, blaz.dot(X[3], lines, ymat, lines)))
-    V48 = torch.from_numpy(uniform_matrix(48, 528, 992)).cuda()
+    expect.append((out3, blaz.dot(X[3], lines, ymat, lines),
+                   dots_as(oracle.dot(OX[3], li, oy, li),
+                           np.array([np.abs(Xd3[i]) @ np.abs(Yd[:, i]) for i in li]), "dot aligned")))
+    Xd4 = oracle.decompress(OX[4])
+    V48h = uniform_matrix(48, 528, 992)
+    V48 = torch.from_numpy(V48h).cuda()
     out4 = torch.empty(48, dtype=torch.float64, device="cuda")
     B.dot_dense(X[4], lines[:48], V48, out4)
-    expect.append((out4, blaz.dot_dense(X[4], lines[:48], V48)))
-    V = torch.from_numpy(uniform_matrix(50, 528, 991)).cuda()
-    rows = torch.from_numpy(rng.integers(0, 1032, 50)).cuda()
+    expect.append((out4, blaz.dot_dense(X[4], lines[:48], V48),
+                   dots_as(oracle.dot_dense(OX[4], li[:48], V48h, 528),
+                           np.array([np.abs(Xd4[i]) @ np.abs(V48h[i]) for i in range(48)]), "dot_dense aligned")))
+    Vh = uniform_matrix(50, 528, 991)
+    V = torch.from_numpy(Vh).cuda()
+    rr = rng.integers(0, 1032, 50)
+    rows = torch.from_numpy(rr).cuda()
     out2 = torch.empty(50, dtype=torch.float64, device="cuda")
     B.dot_dense(X[4], rows, V, out2)
-    expect.append((out2, blaz.dot_dense(X[4], rows, V)))
+    expect.append((out2, blaz.dot_dense(X[4], rows, V),
+                   dots_as(oracle.dot_dense(OX[4], rr, Vh, 528),
+                           np.array([np.abs(Xd4[i]) @ np.abs(Vh[q]) for q, i in enumerate(rr)]), "dot_dense")))
     return B, expect
 
 
@@ -188,7 +241,8 @@ def test_batch_matches_standalone(workgroups):
     P = B.plan()
     P.run(workgroups)
     torch.cuda.synchronize()
-    for got, want in expect:
+    for got, want, check in expect:
+        check(got)
         assert_equal(got, want)
 
 
@@ -212,12 +266,13 @@ def test_batch_graph_capture_replays():
     with torch.cuda.graph(g):
         P.run()
     for rep in range(3):
-        for got, _ in expect:
+        for got, _, _ in expect:
             clear(got)
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        for got, want in expect:
+        for got, want, check in expect:
+            check(got)
             assert_equal(got, want)
 
 

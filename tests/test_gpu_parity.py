@@ -10,7 +10,8 @@ import oracle
 import paper_2202_13007_amd as blaz
 from synth import smooth_field, uniform_matrix, workload_inputs
 
-from parity import assert_blocks_close, assert_dots_close, assert_same_compressed, compare_compressed
+from oracle.parity import (TIE_RATE_MAX, U32, assert_blocks_close, assert_dots_close, assert_same_compressed,
+                           compare_compressed, low_precision_tol)
 
 pytestmark = pytest.mark.gpu
 
@@ -106,9 +107,22 @@ def special_blocks():
 
 
 def test_compress_special_blocks():
+    """Designed blocks.  Some are built to put a coefficient exactly on a
+    truncation boundary (the sign-consistent block's DC term is 63/8 with
+    phi = 16; the sparse diagonal block has rational coefficients); a code
+    there may land on either side, so ties are allowed only up to the number
+    of non-zero oracle values before truncation that sit within the tie
+    distance of an integer (the DC term among them is pinned and must agree)."""
+    from oracle.parity import near_integer
     A = special_blocks()
-    ties = check_compress(A, "special blocks", max_ties=8)
-    print(f"special blocks: {ties} boundary ties")
+    g, _ = gpu_compress(A)
+    o, (_, code_x, phi_x) = oracle.compress(A, with_debug=True)
+    ties = compare_compressed(host(g), oracle_tuple(o), code_x, phi_x, "special blocks")
+    with np.errstate(invalid="ignore"):
+        boundary = int((near_integer(code_x) & (code_x != 0)).sum() + near_integer(phi_x).sum())
+    print(f"special blocks: {ties} boundary ties of {boundary} values on a boundary")
+    assert ties <= boundary
+    np.testing.assert_array_equal(host(g)[3][:, 0], o.codes[:, 0])  # DC codes: pinned order
 
 
 def test_compress_prediction_side_output():
@@ -131,12 +145,15 @@ def test_compress_full_size_8192_sampled():
     gf, gs, gphi, gcodes = host(g)
     nbc = A.shape[1] // 8
     rng = np.random.default_rng(0)
+    # 38k blocks, over a million codes, so that the tie count bounds a rate of 1e-6
     sample = np.unique(np.concatenate([[0, 1, nbc - 1, nbc, len(gf) - 1],
-                                       rng.integers(0, len(gf), 3000)]))
+                                       rng.integers(0, len(gf), 38000)]))
     of, os_, ophi, ocodes, code_x, phi_x = oracle.compress_blocks(A, sample)
     ties = compare_compressed((gf[sample], gs[sample], gphi[sample], gcodes[sample]),
                               (of, os_, ophi, ocodes), code_x, phi_x, "8192 sampled")
-    assert ties <= 1
+    ncodes = ocodes.size + len(sample)
+    print(f"8192 sampled: {ties} boundary ties in {ncodes} codes and phi")
+    assert ncodes >= 1_000_000 and ties <= TIE_RATE_MAX * ncodes
     # properties on every block
     np.testing.assert_array_equal(gf, A[::8, ::8].ravel())
     assert np.all(gs > 0) and np.all(gphi >= 1)
@@ -732,13 +749,41 @@ def test_compress_mixed_precision_special_blocks_and_psi(prec):
     assert torch.equal(p, p64)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_compress_mixed_precision_full_size_16384_sampled(prec):
-    """16384x16384 field (32 sinusoids, <= 32 cycles/side, N(0, 1e-4)): all
-    blocks on the GPU, a sample on the oracle; decompressed error next to the
-    method's own error."""
+@pytest.fixture(scope="module")
+def field_16384():
+    """The 16384x16384 field (32 sinusoids, <= 32 cycles/side, N(0, 1e-4)) on
+    the host and on the device, shared by the tests at that size."""
     (A,) = workload_inputs("mixed-16384")
     t = dev(A)
+    yield A, t
+    del t
+    torch.cuda.empty_cache()
+
+
+def test_compress_full_size_16384_sampled(field_16384):
+    """The binary64 path at 4.19 M blocks: every block on the GPU, 38k blocks
+    (over a million codes) on the oracle, properties on all blocks."""
+    A, t = field_16384
+    gf, gs, gphi, gcodes = host(blaz.compress(t))
+    rng = np.random.default_rng(8)
+    nb = len(gf)
+    smp = np.unique(np.concatenate([[0, nb - 1], rng.integers(0, nb, 38000)]))
+    of, os_, ophi, ocodes, code_x, phi_x = oracle.compress_blocks(A, smp)
+    ties = compare_compressed((gf[smp], gs[smp], gphi[smp], gcodes[smp]), (of, os_, ophi, ocodes),
+                              code_x, phi_x, "16384 sampled")
+    ncodes = ocodes.size + len(smp)
+    print(f"16384 sampled: {ties} boundary ties in {ncodes} codes and phi")
+    assert ncodes >= 1_000_000 and ties <= TIE_RATE_MAX * ncodes
+    np.testing.assert_array_equal(gf, A[::8, ::8].ravel())
+    assert np.all(gs > 0) and np.all(gphi >= 1)
+    assert np.all(np.abs(gcodes.astype(int)) <= 127)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_compress_mixed_precision_full_size_16384_sampled(prec, field_16384):
+    """The 16384x16384 field in FP32 / BF16x3: all blocks on the GPU, a sample
+    on the oracle; decompressed error next to the method's own error."""
+    A, t = field_16384
     g = blaz.compress(t, prec=prec)
     gh = host(g)
     rng = np.random.default_rng(7)
@@ -756,16 +801,8 @@ def test_compress_mixed_precision_full_size_16384_sampled(prec):
     assert mixed <= own * 1.01 + 1e-9
 
 
-# Low-precision contractions (FP32, BF16 hi+lo with three products).  Bound
-# on |C - C64| relative to sum_k |a_k b_k|: operand rounding (FP32: 2 u32;
-# BF16x3: 3 * 2^-16 from the split and the dropped lo*lo term) plus FP32
-# accumulation over K terms (K * u32 for BF16x3, whose MFMA sums 32 products
-# per step; K/4 * u32 for the FP32 16x16x4 form).
-U32 = 2.0 ** -24
-
-
-def low_precision_tol(prec, k):
-    return (2 + k / 4 + 4) * U32 if prec == "fp32" else 3 * 2.0 ** -16 + (k + 4) * U32
+# Low-precision contractions (FP32, BF16 hi+lo with three products): the
+# per-entry bound is low_precision_tol (oracle.parity).
 
 
 def low_precision_fro(prec, k):

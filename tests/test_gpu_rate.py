@@ -9,7 +9,7 @@ import torch
 
 import oracle
 import paper_2202_13007_amd as blaz
-from parity import TIE_RATE_MAX, assert_blocks_close, assert_dots_close, assert_same_compressed, compare_compressed
+from oracle.parity import TIE_RATE_MAX, assert_blocks_close, assert_dots_close, assert_same_compressed, compare_compressed
 from synth import smooth_field, workload_inputs
 
 pytestmark = pytest.mark.gpu

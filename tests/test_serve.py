@@ -1,7 +1,9 @@
 """Serving loop: continuous batching with HBM-budget admission.
 
-GPU tests check that every request's result is the same alone and in the
-mix (bit for bit: the batched paths run the same device code), that a tiny
+GPU tests check every request's result against the FP64 oracle under the
+parity rules (the resident operands are the oracle's records, uploaded), and
+that it is the same alone and in the mix (bit for bit: the batched paths run
+the same device code); that a tiny
 budget forces queueing without exceeding it, and that a request larger than
 the budget is refused before anything runs.  The CPU test checks the
 request generator."""
@@ -58,21 +60,84 @@ def _same(a, b):
                for k in ("f", "s", "phi", "codes"))
 
 
+class OracleOperands:
+    """The oracle's side of the serving pool: for every side n, the oracle's
+    compressions of the n x n corners of the two fields.  The server's
+    resident operands are replaced by uploads of these records, so that both
+    sides start from the same inputs and no oracle input comes from the GPU."""
+
+    def __init__(self, pool, sides):
+        import oracle
+        import paper_2202_13007_amd as blaz
+        self.A = pool.A.cpu().numpy()
+        self.B = pool.B.cpu().numpy()
+        self.x, self.y, self.cache = {}, {}, {}
+        for n in sorted(set(sides)):
+            self.x[n] = oracle.compress(self.A[:n, :n])
+            self.y[n] = oracle.compress(self.B[:n, :n])
+            for o, side in ((self.x[n], pool.x), (self.y[n], pool.y)):
+                side[n] = blaz.BlazMatrix.from_host(n, n, o.f, o.s, o.phi, o.codes)
+
+    def check(self, r, got, prec):
+        """The request's result against the oracle, under the parity rules
+        (a low-precision product under its FP32-accumulation bound)."""
+        import oracle
+        from oracle.parity import (DOT_REL, TIE_RATE_MAX, assert_dots_close, assert_same_compressed,
+                                   compare_compressed, low_precision_tol)
+        from paper_2202_13007_amd.serve import SCALE_C
+        n = r.n
+        what = f"request {r.rid} {r.op} n={n}"
+        key = (r.op, n)
+        if r.op == "compress":
+            if key not in self.cache:
+                self.cache[key] = oracle.compress(self.A[:n, :n], with_debug=True)
+            o, (_, code_x, phi_x) = self.cache[key]
+            ties = compare_compressed(got.to_host(), (o.f, o.s, o.phi, o.codes), code_x, phi_x, what)
+            assert ties <= TIE_RATE_MAX * (o.codes.size + len(o.phi)), (what, ties)
+        elif r.op in ("add", "scale"):
+            if key not in self.cache:
+                self.cache[key] = (oracle.add(self.x[n], self.y[n]) if r.op == "add"
+                                   else oracle.scale(self.x[n], SCALE_C))
+            o = self.cache[key]
+            assert_same_compressed(got.to_host(), (o.f, o.s, o.phi, o.codes), what)
+        else:
+            if ("dense", n) not in self.cache:
+                self.cache[("dense", n)] = (oracle.decompress(self.x[n]), oracle.decompress(self.y[n]))
+            Xd, Yd = self.cache[("dense", n)]
+            if r.op == "dot":
+                idx = np.arange(n)
+                want = oracle.dot(self.x[n], idx, self.y[n], idx)
+                mag = np.einsum("ij,ji->i", np.abs(Xd), np.abs(Yd))
+                assert_dots_close(got.cpu().numpy(), want, mag, what=what)
+            else:
+                if key not in self.cache:
+                    self.cache[key] = (oracle.gemm(Xd, Yd), np.abs(Xd) @ np.abs(Yd))
+                want, mag = self.cache[key]
+                rel = DOT_REL if prec == "fp64" else low_precision_tol(prec, n)
+                assert_dots_close(got.cpu().numpy(), want, mag, rel=rel, what=f"{what} {prec}")
+
+
 @pytest.mark.gpu
 @pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
 def test_results_same_alone_and_in_the_mix(prec):
+    """Every request of a 300-request mix (sides 8..512, arriving faster than
+    they are served, so ticks batch many of them and the batch and the
+    contractions overlap) matches the oracle under the parity rules, and
+    equals the same request run alone bit for bit."""
     import torch
     from paper_2202_13007_amd.serve import OperandPool, Server
     from paper_2202_13007_amd.tune import Autotuner
     A, B = _setup()
     reqs = make_requests(300, rate=20000.0, seed=11, n_min=8, n_max=512)
     pool = OperandPool(A, B, [r.n for r in reqs])
+    orc = OracleOperands(pool, [r.n for r in reqs])
     srv = Server(pool, hbm_budget=1 << 30, matmul_prec=prec, tuner=Autotuner(path=None), keep_results=True)
     srv.prepare(reqs)
     rep = srv.run(reqs, "batched")
     assert rep["requests"] == 300 and rep["ticks"] < 300  # requests were batched together
     for r in reqs:
         assert np.isfinite(r.done) and r.done >= r.arrival
+        orc.check(r, r.result, prec)
         assert _same(r.result, _alone(pool, r, prec)), (r.rid, r.op, r.n)
     torch.cuda.synchronize()
 
@@ -84,6 +149,7 @@ def test_tiny_budget_forces_queueing():
     reqs = make_requests(120, rate=50000.0, seed=12, n_min=8, n_max=256)
     biggest = max(output_bytes(r.op, r.n, "fp64") for r in reqs)
     pool = OperandPool(A, B, [r.n for r in reqs])
+    orc = OracleOperands(pool, [r.n for r in reqs])
     srv = Server(pool, hbm_budget=biggest, keep_results=True)
     rep = srv.run(reqs, "batched")
     assert srv.peak_used <= biggest
@@ -93,6 +159,7 @@ def test_tiny_budget_forces_queueing():
     assert need > 1
     assert rep["ticks"] >= need
     for r in reqs:
+        orc.check(r, r.result, "fp64")
         assert _same(r.result, _alone(pool, r, "fp64")), (r.rid, r.op, r.n)
 
 
@@ -102,9 +169,11 @@ def test_plain_form_matches_too_and_oversized_request_is_refused():
     A, B = _setup(256)
     reqs = make_requests(40, rate=50000.0, seed=13, n_min=8, n_max=256)
     pool = OperandPool(A, B, [r.n for r in reqs])
+    orc = OracleOperands(pool, [r.n for r in reqs])
     srv = Server(pool, keep_results=True)
     srv.run(reqs, "plain")
     for r in reqs:
+        orc.check(r, r.result, "fp64")
         assert _same(r.result, _alone(pool, r, "fp64")), (r.rid, r.op, r.n)
     small = Server(pool, hbm_budget=min(output_bytes(r.op, r.n, "fp64") for r in reqs) - 1)
     with pytest.raises(ValueError):
