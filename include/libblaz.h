@@ -45,11 +45,14 @@ typedef enum {
     BLAZ_OK = 0,
     BLAZ_ERR_NULL = -1,        /* a required pointer is NULL                          */
     BLAZ_ERR_SHAPE = -2,       /* rows/cols negative or not a multiple of 8, more than
-                                  2^38 blocks, ld < cols, or a dense operand whose last
-                                  element lies 2^60 or more elements past its first   */
+                                  2^32 - 256 blocks, ld < cols, a dense operand whose
+                                  last element lies 2^60 or more elements past its
+                                  first, or a product whose launches would exceed one
+                                  dispatch's 2^32 - 1 work-items                     */
     BLAZ_ERR_MISMATCH = -3,    /* operand shapes do not agree                         */
     BLAZ_ERR_ALIGN = -4,       /* a pointer is not aligned to its element type         */
-    BLAZ_ERR_ARG = -5,         /* another invalid argument (count < 0, bad enum, overlap) */
+    BLAZ_ERR_ARG = -5,         /* another invalid argument (count < 0 or a dot count
+                                  above 2^27 - 8, bad enum, overlap)                   */
     BLAZ_ERR_UNSUPPORTED = -6, /* a valid request this build does not implement        */
     BLAZ_ERR_WORKSPACE = -7,   /* workspace missing or smaller than required           */
     BLAZ_ERR_HIP = -8          /* the HIP runtime reported an error                    */
@@ -182,14 +185,17 @@ blaz_status blaz_scale(const blaz_matrix *x, double c, const blaz_matrix *z, hip
  * count int64; an index outside its matrix yields out[q] = NaN.  Queries are
  * taken 8 at a time: 8 consecutive queries on the lines 8I..8I+7 in order
  * (and the columns 8J..8J+7 of Y in order) rebuild each block once for the 8;
- * every query gets the same bits either way. */
+ * every query gets the same bits either way.  A call takes at most
+ * 2^27 - 8 queries (32 lanes each in one dispatch of at most 2^32 - 1
+ * work-items); more is BLAZ_ERR_ARG. */
 blaz_status blaz_dot(const blaz_matrix *x, const int64_t *xrow, const blaz_matrix *y, const int64_t *ycol,
                      int64_t count, double *out, hipStream_t stream);
 
 /* Dot products of lines of a compressed matrix with dense vectors:
  * out[q] = sum_k X[xrow[q], k] * v[q*ldv + k].  ldv = 0 uses one vector for
  * every q; otherwise ldv >= x->cols.  v is 16-byte aligned and, when
- * ldv != 0, ldv is even.  An index outside X yields NaN. */
+ * ldv != 0, ldv is even.  An index outside X yields NaN.  At most 2^27 - 8
+ * queries, as for blaz_dot. */
 blaz_status blaz_dot_dense(const blaz_matrix *x, const int64_t *xrow, const double *v, int64_t ldv,
                            int64_t count, double *out, hipStream_t stream);
 

@@ -185,6 +185,22 @@ int device_cu_count()
 }  // namespace detail
 }  // namespace blaz
 
+// Every launch of a product fits one dispatch: the contraction's grid of
+// output tiles (512 lanes per workgroup for the BF16x3 128 tile, 256
+// otherwise), the rebuild of A (and of a compressed B) in 64-block waves,
+// and the low-precision preparation of B in 64 x 64 tiles of 256 lanes.
+static bool matmul_fits_dispatch(int64_t m, int64_t n, int64_t k, bool b_compressed, blaz_precision prec, int tile)
+{
+    const int64_t tiles = ((m + tile - 1) / tile) * ((n + tile - 1) / tile);
+    const int lanes = (prec == BLAZ_PREC_BF16X3 && tile == 128) ? 512 : 256;
+    if (!fits_dispatch(tiles, lanes)) return false;
+    if (k == 0) return true;
+    const int64_t waves = ((m / 8) * (k / 8) + 63) / 64 + (b_compressed ? ((k / 8) * (n / 8) + 63) / 64 : 0);
+    if (!fits_dispatch(waves, 64)) return false;
+    if (prec != BLAZ_PREC_FP64 && !fits_dispatch(((n + 63) / 64) * ((k + 63) / 64), 256)) return false;
+    return true;
+}
+
 // The library's tile choice: the 128 tile once it gives every compute unit a
 // workgroup, the 64 tile (four times as many workgroups) below that.
 static int default_gemm_tile(int64_t m, int64_t n)
@@ -229,6 +245,7 @@ static blaz_status matmul_impl(const blaz_matrix* a, const blaz_matrix* b, const
     // k == 0: the product is the zero matrix; the contraction kernel with an
     // empty K loop writes exactly that and reads nothing.
     if (tile == 0) tile = default_gemm_tile(m, n);
+    if (!matmul_fits_dispatch(m, n, k, b != nullptr, prec, tile)) return BLAZ_ERR_SHAPE;
     if (k == 0) return hip_status(blaz::detail::launch_gemm_f64(nullptr, 0, nullptr, 0, c, ldc, m, n, 0, tile, stream));
 
     char* ws = static_cast<char*>(workspace);

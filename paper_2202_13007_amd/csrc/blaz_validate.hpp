@@ -11,16 +11,28 @@ namespace blaz {
 namespace validate {
 
 constexpr int64_t kRecordBytes = 45;  // f (8) + s (8) + phi (1) + 28 codes (two kept lines)
-constexpr int64_t kMaxDots = int64_t(1) << 32;  // eight dot products per workgroup: grid < 2^32
+
+// A dispatch's grid size is a 32-bit count of work-items (lanes), so every
+// launch must stay at or below 2^32 - 1 lanes.
+constexpr int64_t kMaxLanes = (int64_t(1) << 32) - 1;
+inline bool fits_dispatch(int64_t workgroups, int64_t lanes_per_workgroup)
+{
+    return workgroups >= 0 && workgroups <= kMaxLanes / lanes_per_workgroup;
+}
+// Blocks per compressed matrix: the one-lane-per-block kernels (add, sub,
+// scale, diagnose) round the block count up to whole 256-lane workgroups,
+// the codec kernels to whole 64-lane waves, so 2^32 - 256 blocks (about
+// 193 GB compressed) is the largest count every kernel launches as one grid.
+constexpr int64_t kMaxBlocks = (int64_t(1) << 32) - 256;
+// Dot products per call: eight per 256-lane workgroup, 32 lanes each.
+constexpr int64_t kMaxDots = kMaxBlocks / 32;
 
 inline bool aligned(const void* p, uintptr_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
 
 inline blaz_status check_shape(int64_t rows, int64_t cols)
 {
     if (rows < 0 || cols < 0 || rows % 8 != 0 || cols % 8 != 0) return BLAZ_ERR_SHAPE;
-    // keep the one-lane-per-block grids (256 lanes per workgroup) well
-    // within 2^31 workgroups: at most 2^38 blocks
-    if (rows > 0 && cols > 0 && (rows / 8) > (int64_t(1) << 38) / (cols / 8)) return BLAZ_ERR_SHAPE;
+    if (rows > 0 && cols > 0 && (rows / 8) > kMaxBlocks / (cols / 8)) return BLAZ_ERR_SHAPE;
     return BLAZ_OK;
 }
 

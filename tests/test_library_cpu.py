@@ -54,14 +54,59 @@ def test_block_count_and_bytes(L):
     assert L.blaz_compressed_bytes(7, 8) == 0
 
 
+MAX_BLOCKS = (1 << 32) - 256  # blocks per matrix: every kernel's grid within 2^32 - 1 work-items
+MAX_DOTS = MAX_BLOCKS // 32   # dot products per call: 32 work-items each
+
+
 def test_shape_limits(L):
-    """Shapes must be non-negative multiples of 8 with at most 2^38 blocks
-    (the one-lane-per-block grids stay well inside 2^31 workgroups)."""
-    assert L.blaz_block_count(8 << 19, 8 << 19) == 1 << 38          # exactly the limit
-    assert L.blaz_block_count((8 << 19) + 8, 8 << 19) == -2          # one block row more
+    """Shapes must be non-negative multiples of 8 with at most 2^32 - 256
+    blocks: the one-lane-per-block kernels round the count up to 256-lane
+    workgroups, and a dispatch holds at most 2^32 - 1 work-items."""
+    rows, cols = 8 * 256, 8 * ((1 << 24) - 1)
+    assert L.blaz_block_count(rows, cols) == MAX_BLOCKS              # exactly the limit
+    assert L.blaz_block_count(rows + 8, cols) == -2                  # one block row more
+    assert L.blaz_block_count(8 << 16, 8 << 16) == -2                # 2^32 blocks
     assert L.blaz_block_count(-8, 8) == -2 and L.blaz_block_count(12, 8) == -2
-    assert L.blaz_compressed_bytes((8 << 19) + 8, 8 << 19) == 0
+    assert L.blaz_compressed_bytes(rows, cols) == 45 * MAX_BLOCKS
+    assert L.blaz_compressed_bytes(rows + 8, cols) == 0
     assert L.blaz_matmul_workspace_bytes(8, 8, 12, 0, 0) == 0
+    x = mat(rows + 8, cols, 1 << 40)
+    assert L.blaz_scale(B(x), 2.0, B(x), None) == -2                 # in place: refused, not launched
+
+
+def test_dot_count_limit(L):
+    """At most 2^27 - 8 dot products per call (eight per 256-lane workgroup).
+    At the limit the count passes and the misaligned output is the first
+    error; one more is refused as an invalid count."""
+    x, y = mat(16, 16, 0x100000), mat(16, 16, 0x200000)
+    assert MAX_DOTS == (1 << 27) - 8
+    assert L.blaz_dot(B(x), 0x300000, B(y), 0x400000, MAX_DOTS, 0x500004, None) == -4
+    assert L.blaz_dot(B(x), 0x300000, B(y), 0x400000, MAX_DOTS + 1, 0x500000, None) == -5
+    assert L.blaz_dot_dense(B(x), 0x300000, 0x600000, 0, MAX_DOTS, 0x500004, None) == -4
+    assert L.blaz_dot_dense(B(x), 0x300000, 0x600000, 0, MAX_DOTS + 1, 0x500000, None) == -5
+
+
+def test_matmul_launch_limits(L):
+    """A product whose launches would not fit one dispatch is refused as a
+    shape error before anything is enqueued: the contraction's grid of
+    output tiles, and the rebuild of both compressed operands in one grid."""
+    # 2^19 x 2^19 output: 2^26 tiles of 64 x 64, 256 lanes each
+    m = n = 1 << 19
+    a, b = mat(m, 8, 1 << 40), mat(8, n, 1 << 42)
+    need = L.blaz_matmul_workspace_bytes(m, n, 8, 1, 0)
+    assert need > 0
+    assert L.blaz_matmul_tiled(B(a), B(b), None, n, n, 1 << 44, n, 0, 1 << 46, need, 64, None) == -2
+    # 128 tiles with 512 lanes (BF16x3): 2^12 x (2^12 - 1) tiles exceed 2^32 - 1 lanes
+    m2, n2 = 128 << 12, 128 * ((1 << 12) - 1)
+    a2, b2 = mat(m2, 8, 1 << 40), mat(8, n2, 1 << 42)
+    need2 = L.blaz_matmul_workspace_bytes(m2, n2, 8, 1, 2)
+    assert L.blaz_matmul_tiled(B(a2), B(b2), None, n2, n2, 1 << 44, n2, 2, 1 << 46, need2, 128, None) == -2
+    # rebuilds: A with the largest block count plus B's blocks in one grid of 64-block waves
+    k = 8 * ((1 << 24) - 1)
+    a3, b3 = mat(8 * 256, k, 1 << 40), mat(k, 8 * 64, 1 << 44)
+    need3 = L.blaz_matmul_workspace_bytes(8 * 256, 8 * 64, k, 1, 0)
+    assert L.blaz_matmul_tiled(B(a3), B(b3), None, 8 * 64, 8 * 64, 1 << 46, 8 * 64, 0, 1 << 47, need3, 64,
+                               None) == -2
 
 
 def test_leading_dimension_limit(L):
@@ -263,7 +308,7 @@ def test_kept_lines_validation(L):
 # --------------------------------------------------------------------------
 
 def test_tie_classifier():
-    from parity import compare_compressed
+    from oracle.parity import compare_compressed
     f, s = np.zeros(2), np.ones(2)
     phi = np.array([20, 20], np.uint8)
     codes = np.zeros((2, 28), np.int8)
