@@ -29,6 +29,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -113,27 +115,126 @@ def traffic_for(kernel: str, sources):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(A, B, rows):
-    import oracle
+def host_identity():
+    """Threads the oracle may use (the process's CPU affinity, capped by
+    OMP_NUM_THREADS when that is set) and the CPU model string."""
+    import subprocess
+    cores = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(cores, int(env)) if env.isdigit() and int(env) > 0 else cores
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        model = next((ln.split(":", 1)[1].strip() for ln in out.splitlines() if ln.startswith("Model name")), "")
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if not model and os.path.exists("/proc/cpuinfo"):
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    return cores, threads, model
 
-    a = A[:rows].copy()
-    b = B[:rows].copy()
-    t0 = time.perf_counter()
+
+def oracle_step(oracle, a, b):
+    """The step on the oracle: compress both, add, scale by 1.7, decompress."""
     x = oracle.compress(a)
     y = oracle.compress(b)
-    z = oracle.add(x, y)
-    w = oracle.scale(z, 1.7)
+    w = oracle.scale(oracle.add(x, y), 1.7)
     oracle.decompress(w)
-    dt = time.perf_counter() - t0
+    return x, y
+
+
+def cpu_baseline(A, B, rows, workload_inputs, band=64, queries=128):
+    """The oracle (plain C, FP64, one block at a time) timed on this host on
+    bounded samples of the workloads, single-threaded and with its block loops
+    on every allowed core: the step on the first `rows` rows of both 8192^2
+    fields (FP64-equivalent GB/s, as `value`), a band of rows of the 4096^3
+    product (decompress the band of A, then the i-k-j product; `band` rows
+    single-threaded, 8x as many on all cores) and a set of the 4096 row dot
+    products with their own vectors (`queries`, 8x as many on all cores).
+    Returns the report and the oracle's records of the step sample (for
+    parity)."""
+    import oracle
+
+    cores, threads, model = host_identity()
+    a = np.ascontiguousarray(A[:rows])
+    b = np.ascontiguousarray(B[:rows])
     n2 = a.shape[0] * a.shape[1]
+    Am, Bm, Vm = workload_inputs("linalg-4096")
+    n = Am.shape[0]
+    res = {}
+    recs = None
+    for name, t, scale in (("single_thread", 1, 1), ("all_cores", threads, 8)):
+        nb_rows, nq = band * scale, queries * scale
+        xa = oracle.compress(np.ascontiguousarray(Am[:nb_rows]))
+        xr = oracle.compress(np.ascontiguousarray(Am[: 8 * ((nq + 7) // 8)]))
+        qrows = np.arange(nq)
+        V = np.ascontiguousarray(Vm[:nq])
+        oracle.set_threads(t)
+        t0 = time.perf_counter()
+        out = oracle_step(oracle, a, b)
+        dt = time.perf_counter() - t0
+        recs = recs or out
+        t1 = time.perf_counter()
+        oracle.gemm(oracle.decompress(xa), Bm)
+        dm = time.perf_counter() - t1
+        t2 = time.perf_counter()
+        oracle.dot_dense(xr, qrows, V, n)
+        dd = time.perf_counter() - t2
+        res[name] = {"threads": t, "step_GBps_fp64_equiv": round(64.0 * n2 / dt / 1e9, 4), "step_s": round(dt, 2),
+                     "matmul_band_rows": nb_rows, "matmul_GFLOPs": round(2.0 * nb_rows * n * n / dm / 1e9, 3),
+                     "matmul_s": round(dm, 2), "dots": nq,
+                     "dots_GBps": round((45 * (n // 8) + 8 * n + 16) * nq / dd / 1e9, 4), "dots_s": round(dd, 2)}
+    oracle.set_threads(threads)
     return {
-        "value": round(64.0 * n2 / dt / 1e9, 4),
+        "value": res["all_cores"]["step_GBps_fp64_equiv"],
         "unit": "GB/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"first {rows} rows of both fields ({a.shape[0]}x{a.shape[1]}, {n2 // 64} blocks each): "
-                  f"same step (compress x2, add, scale, decompress), single-threaded C, {dt:.1f} s",
-    }
+        "sample": f"step (compress x2, add, scale 1.7, decompress) on the first {rows} rows of both fields "
+                  f"({a.shape[0]}x{a.shape[1]}, {n2 // 64} blocks each); 4096^3 product on a band of rows "
+                  f"(decompress + i-k-j); a set of the 4096 row dots with own vectors; value = the step on all "
+                  f"cores",
+        "host_cores": cores,
+        "model": model,
+        **res,
+    }, recs
+
+
+def parity_report(A, B, gx, gy, ox, oy):
+    """The GPU's records of the step against the oracle's on the oracle's
+    sample (a prefix of block rows): f and s bit-exact, phi and codes
+    bit-exact except classified rounding-boundary ties, whose count and rate
+    per code are reported (the rate must stay under 1e-6)."""
+    import oracle
+    from oracle.parity import TIE_RATE_MAX, compare_compressed
+
+    rep = {"blocks": 0, "codes": 0, "ties": 0, "f_s_exact": True, "ok": True}
+    try:
+        for M, g, o in ((A, gx, ox), (B, gy, oy)):
+            nb = o.nblk
+            gf = g.f[:nb].cpu().numpy()
+            gs = g.s[:nb].cpu().numpy()
+            gphi = g.phi[:nb].cpu().numpy()
+            gc = g.codes[:nb].cpu().numpy()
+            exact = (np.array_equal(gf.view(np.uint64), o.f.view(np.uint64))
+                     and np.array_equal(gs.view(np.uint64), o.s.view(np.uint64)))
+            rep["f_s_exact"] = rep["f_s_exact"] and exact
+            diff = np.flatnonzero((gphi != o.phi) | np.any(gc != o.codes, axis=1))
+            if diff.size:
+                _, _, _, _, code_x, phi_x = oracle.compress_blocks(M, diff)
+                rep["ties"] += compare_compressed((gf[diff], gs[diff], gphi[diff], gc[diff]),
+                                                  (o.f[diff], o.s[diff], o.phi[diff], o.codes[diff]),
+                                                  code_x, phi_x, "bench sample")
+            rep["blocks"] += nb
+            rep["codes"] += 29 * nb
+    except AssertionError as e:
+        rep["ok"] = False
+        rep["error"] = str(e)[:300]
+    rep["tie_rate"] = float(f"{rep['ties'] / max(rep['codes'], 1):.3e}")
+    rep["ok"] = rep["ok"] and rep["f_s_exact"] and rep["tie_rate"] < TIE_RATE_MAX
+    rep["rule"] = ("f, s bit-exact; phi and 28 codes per block bit-exact except rounding-boundary ties "
+                   "(oracle value within 2^-40 of an integer, results 1 apart); codes = 29 per block")
+    return rep
 
 
 def matmul_leg(blaz, torch, workload_inputs):
@@ -463,7 +564,6 @@ def main():
               "(the per-GPU shard is the measured unit; see the sharding notes).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2202_13007_amd as blaz
@@ -630,7 +730,9 @@ def main():
         torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(A, B, min(args.cpu_rows, n))
+        print("# CPU oracle leg", file=sys.stderr, flush=True)
+        result["cpu_baseline"], (ox, oy) = cpu_baseline(A, B, min(args.cpu_rows, n), workload_inputs)
+        result["parity"] = parity_report(A, B, x, y, ox, oy)
     print(json.dumps(result), flush=True)
 
 

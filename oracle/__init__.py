@@ -40,7 +40,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no fast-math, no FP contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+        subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
                         "-Wall", "-o", tmp, _SRC, "-lm"], check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -59,6 +59,8 @@ def lib():
         D = ctypes.c_double
         sig = {
             "oracle_trace_size": ([], ctypes.c_size_t),
+            "oracle_set_threads": ([ctypes.c_int], None),
+            "oracle_max_threads": ([], ctypes.c_int),
             "oracle_compress_block": ([P, P], None),
             "oracle_compress_block_predicted": ([P, P], None),
             "oracle_predicted_slopes": ([P, D, P, P], None),
@@ -88,6 +90,16 @@ def lib():
             fn.restype = res
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the whole-matrix loops (blocks, product rows, queries are
+    split between them; results do not depend on the count)."""
+    lib().oracle_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())
 
 
 def _p(a):

@@ -22,15 +22,24 @@
  * block at a caller-given stride).
  * Block (I, J) of a rows x cols matrix has flat index I*(cols/8) + J.
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math).
+ * Threads: the whole-matrix loops below hand whole blocks (or whole output
+ * rows, or whole queries) to OpenMP threads; every block's arithmetic is the
+ * same sequential code whatever the thread count, so the results do not
+ * depend on it.  oracle_set_threads() fixes the count (1 = serial).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (no fast-math).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define NB 8            /* block side */
 #define NKEPT 28        /* coefficients kept by the quantization */
+
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oracle_max_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* Helpers                                                                   */
@@ -400,10 +409,11 @@ static void compress_with(block_fn block, const double *A, int64_t rows, int64_t
                           uint8_t *psi, double *code_x, double *phi_x)
 {
     int64_t nbc = cols / NB, nbr = rows / NB;
-    double M[64];
-    oracle_block_trace tr;
+#pragma omp parallel for schedule(static)
     for (int64_t I = 0; I < nbr; ++I)
         for (int64_t J = 0; J < nbc; ++J) {
+            double M[64];
+            oracle_block_trace tr;
             int64_t b = I * nbc + J;
             load_block(A, lda, I, J, M);
             block(M, &tr);
@@ -444,10 +454,11 @@ void oracle_compress_blocks(const double *A, int64_t cols, int64_t lda,
                             double *code_x, double *phi_x, int predicted)
 {
     int64_t nbc = cols / NB;
-    double M[64];
-    oracle_block_trace tr;
     block_fn block = predicted ? oracle_compress_block_predicted : oracle_compress_block;
+#pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < count; ++q) {
+        double M[64];
+        oracle_block_trace tr;
         int64_t b = blocks[q];
         load_block(A, lda, b / nbc, b % nbc, M);
         block(M, &tr);
@@ -466,9 +477,10 @@ void oracle_decompress(const double *f, const double *s, const uint8_t *phi, con
                        int64_t rows, int64_t cols, double *A, int64_t lda)
 {
     int64_t nbc = cols / NB, nbr = rows / NB;
-    double B[64];
+#pragma omp parallel for schedule(static)
     for (int64_t I = 0; I < nbr; ++I)
         for (int64_t J = 0; J < nbc; ++J) {
+            double B[64];
             int64_t b = I * nbc + J;
             oracle_decompress_block(f[b], s[b], phi[b], codes + b * NKEPT, B);
             for (int i = 0; i < NB; ++i)
@@ -553,6 +565,7 @@ void oracle_add_codes(int64_t nblk, int ncodes, int64_t cstride,
                       const double *f2, const double *s2, const uint8_t *phi2, const int8_t *c2,
                       double *f, double *s, uint8_t *phi, int8_t *codes)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t b = 0; b < nblk; ++b) {
         double fb = f1[b] + f2[b];
         double sb = s1[b] + s2[b];
@@ -591,6 +604,7 @@ void oracle_scale_codes(int64_t nblk, int ncodes, int64_t cstride, const double 
                         const uint8_t *phi1, const int8_t *c1, double c, double *f, double *s, uint8_t *phi,
                         int8_t *codes)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t b = 0; b < nblk; ++b) {
         f[b] = f1[b] * c;
         s[b] = s1[b] * c;
@@ -641,18 +655,22 @@ void oracle_dot(const double *xf, const double *xs, const uint8_t *xphi, const i
                 const double *yf, const double *ys, const uint8_t *yphi, const int8_t *yc, int64_t cols_y,
                 const int64_t *xrow, const int64_t *ycol, int64_t count, double *out)
 {
-    double *r = (double *)malloc(sizeof(double) * (size_t)n);
-    double *c = (double *)malloc(sizeof(double) * (size_t)n);
-    for (int64_t q = 0; q < count; ++q) {
-        decompress_row(xf, xs, xphi, xc, n, xrow[q], r);
-        decompress_col(yf, ys, yphi, yc, n, cols_y, ycol[q], c);
-        double acc = 0.0;
-        for (int64_t k = 0; k < n; ++k)
-            acc += r[k] * c[k];
-        out[q] = acc;
+#pragma omp parallel
+    {
+        double *r = (double *)malloc(sizeof(double) * (size_t)n);
+        double *c = (double *)malloc(sizeof(double) * (size_t)n);
+#pragma omp for schedule(static)
+        for (int64_t q = 0; q < count; ++q) {
+            decompress_row(xf, xs, xphi, xc, n, xrow[q], r);
+            decompress_col(yf, ys, yphi, yc, n, cols_y, ycol[q], c);
+            double acc = 0.0;
+            for (int64_t k = 0; k < n; ++k)
+                acc += r[k] * c[k];
+            out[q] = acc;
+        }
+        free(r);
+        free(c);
     }
-    free(r);
-    free(c);
 }
 
 /* Dot product of line xrow[q] of compressed X (n columns) with a dense
@@ -660,16 +678,20 @@ void oracle_dot(const double *xf, const double *xs, const uint8_t *xphi, const i
 void oracle_dot_dense(const double *xf, const double *xs, const uint8_t *xphi, const int8_t *xc, int64_t n,
                       const int64_t *xrow, const double *v, int64_t ldv, int64_t count, double *out)
 {
-    double *r = (double *)malloc(sizeof(double) * (size_t)n);
-    for (int64_t q = 0; q < count; ++q) {
-        decompress_row(xf, xs, xphi, xc, n, xrow[q], r);
-        const double *vq = v + q * ldv;
-        double acc = 0.0;
-        for (int64_t k = 0; k < n; ++k)
-            acc += r[k] * vq[k];
-        out[q] = acc;
+#pragma omp parallel
+    {
+        double *r = (double *)malloc(sizeof(double) * (size_t)n);
+#pragma omp for schedule(static)
+        for (int64_t q = 0; q < count; ++q) {
+            decompress_row(xf, xs, xphi, xc, n, xrow[q], r);
+            const double *vq = v + q * ldv;
+            double acc = 0.0;
+            for (int64_t k = 0; k < n; ++k)
+                acc += r[k] * vq[k];
+            out[q] = acc;
+        }
+        free(r);
     }
-    free(r);
 }
 
 /* Plain i-k-j product C = A B of dense row-major matrices, m x k times
@@ -679,6 +701,7 @@ void oracle_dot_dense(const double *xf, const double *xs, const uint8_t *xphi, c
 void oracle_gemm(const double *A, int64_t lda, const double *B, int64_t ldb,
                  double *C, int64_t ldc, int64_t m, int64_t n, int64_t k)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < m; ++i) {
         for (int64_t j = 0; j < n; ++j)
             C[i * ldc + j] = 0.0;

@@ -504,3 +504,33 @@ def test_gemm_catches_transpose():
     A = np.arange(6.0).reshape(2, 3)
     B = np.arange(12.0).reshape(3, 4)
     np.testing.assert_array_equal(oracle.gemm(A, B), A @ B)
+
+
+def test_thread_count_does_not_change_results():
+    """The whole-matrix loops split blocks, product rows and queries between
+    threads; each is computed by the same sequential code, so one thread and
+    several give the same bits."""
+    A = smooth_field(64, 6, 3.0, 1e-3, 31, cols=136)
+    B = smooth_field(136, 6, 3.0, 1e-3, 32, cols=72)
+    rows = np.arange(0, 64, 3)
+    V = np.random.default_rng(33).uniform(-1, 1, (len(rows), 136))
+    outs = []
+    try:
+        for threads in (1, 4):
+            oracle.set_threads(threads)
+            x, (psi, cx, px) = oracle.compress(A, with_debug=True)
+            y = oracle.compress(B)
+            z = oracle.scale(oracle.add(x, x), -1.5)
+            Xd, Yd = oracle.decompress(x), oracle.decompress(y)
+            outs.append([x.f, x.s, x.phi, x.codes, psi, cx, px, z.f, z.s, z.phi, z.codes, Xd,
+                         oracle.gemm(Xd, Yd), oracle.dot(x, rows, y, rows % 72),
+                         oracle.dot_dense(x, rows, V, 136)])
+    finally:
+        oracle.set_threads(oracle_default_threads())
+    for a, b in zip(*outs):
+        assert np.array_equal(np.asarray(a).view(np.uint8), np.asarray(b).view(np.uint8))
+
+
+def oracle_default_threads():
+    import os
+    return len(os.sched_getaffinity(0))
