@@ -53,7 +53,22 @@ def parse():
     ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="HBM budget of the serving loop")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 64x64 latency, cold-cache, tunable-rate and 16384x16384 mixed-precision legs")
-    return ap.parse_args()
+    ap.add_argument("--only", default="",
+                    help="comma-separated legs to run after the step (cold, rates, transform, serving, latency, "
+                         "matmul, mixed, cpu); default: every leg the other flags leave on")
+    args = ap.parse_args()
+    args.legs = {"cold", "rates", "transform", "serving", "latency", "matmul", "mixed", "cpu"}
+    if args.only:
+        args.legs &= set(args.only.split(","))
+    if args.no_extra:
+        args.legs -= {"cold", "rates", "transform", "latency", "mixed"}
+    if args.no_matmul:
+        args.legs.discard("matmul")
+    if args.no_cpu_baseline:
+        args.legs.discard("cpu")
+    if args.serve_requests <= 0:
+        args.legs.discard("serving")
+    return args
 
 
 def elapsed_ms(pairs):
@@ -706,30 +721,32 @@ def main():
                             "matmul": "blaz close to the uncompressed product, zfp about 10x slower than blaz"},
         "note": "context only, not a target"}
     del D
-    if not args.no_extra:
+    legs = args.legs
+    if "cold" in legs:
         print("# cold/warm single-op leg", file=sys.stderr, flush=True)
         result["ops_single_launch"] = cold_ops_leg(blaz, torch, dA, dB)
-    if not args.no_extra:
+    if "rates" in legs:
         print("# tunable-rate leg", file=sys.stderr, flush=True)
         result["rates_8192"] = rates_leg(blaz, torch, dA)
+    if "transform" in legs:
         print("# transform-input leg", file=sys.stderr, flush=True)
         result["transform_input_8192"] = transform_input_leg(blaz, torch, dA)
-    if args.serve_requests > 0:
+    if "serving" in legs:
         result["serving"] = serving_leg(torch, dA, dB, args.serve_requests, args.serve_budget_gib)
     del dA, dB
 
-    if not args.no_extra:
+    if "latency" in legs:
         print("# 64x64 latency leg", file=sys.stderr, flush=True)
         result["latency_64"] = latency_leg(blaz, torch, workload_inputs)
-    if not args.no_matmul:
+    if "matmul" in legs:
         print("# 4096 linear-algebra leg", file=sys.stderr, flush=True)
         result["matmul_4096"] = matmul_leg(blaz, torch, workload_inputs)
-    if not args.no_extra:
+    if "mixed" in legs:
         print("# 16384 mixed-precision leg", file=sys.stderr, flush=True)
         result["mixed_16384"] = mixed_leg(blaz, torch, workload_inputs)
         torch.cuda.empty_cache()
 
-    if not args.no_cpu_baseline:
+    if "cpu" in legs:
         print("# CPU oracle leg", file=sys.stderr, flush=True)
         result["cpu_baseline"], (ox, oy) = cpu_baseline(A, B, min(args.cpu_rows, n), workload_inputs)
         result["parity"] = parity_report(A, B, x, y, ox, oy)
