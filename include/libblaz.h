@@ -55,7 +55,9 @@ typedef enum {
                                   above 2^27 - 8, bad enum, overlap)                   */
     BLAZ_ERR_UNSUPPORTED = -6, /* a valid request this build does not implement        */
     BLAZ_ERR_WORKSPACE = -7,   /* workspace missing or smaller than required           */
-    BLAZ_ERR_HIP = -8          /* the HIP runtime reported an error                    */
+    BLAZ_ERR_HIP = -8,         /* the HIP runtime reported an error                    */
+    BLAZ_ERR_TOO_LARGE = -9    /* blaz_matmul_static: the product's workspace exceeds
+                                  BLAZ_STATIC_SCRATCH_BYTES                           */
 } blaz_status;
 
 /* Arithmetic of the DCT stage in blaz_compress and of the contraction in
@@ -229,6 +231,29 @@ blaz_status blaz_matmul(const blaz_matrix *a, const blaz_matrix *b, const double
 blaz_status blaz_matmul_tiled(const blaz_matrix *a, const blaz_matrix *b, const double *bdense, int64_t n,
                               int64_t ldb, double *c, int64_t ldc, blaz_precision prec, void *workspace,
                               size_t ws_bytes, int32_t tile, hipStream_t stream);
+
+/* Bytes of the library's static scratch array: device memory that every
+ * device the library runs on holds from the library's load until the
+ * process ends, used as the workspace of blaz_matmul_static. */
+#define BLAZ_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* blaz_matmul without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops and harnesses
+ * that forbid allocation).  Same operands, results and errors as
+ * blaz_matmul (bit for bit: the same kernels run), with the workspace taken
+ * from the library's static scratch array of BLAZ_STATIC_SCRATCH_BYTES
+ * bytes (256 MiB: every product up to 4096 x 4096 x 4096 in every operand
+ * form and precision fits).  A product whose workspace
+ * (blaz_matmul_workspace_bytes) exceeds it returns BLAZ_ERR_TOO_LARGE before
+ * anything is enqueued.  The call allocates nothing: the first call on a
+ * device looks up that device's address of the array (make it once before
+ * capturing a graph).  Every call on a device shares that device's array,
+ * which keeps the last call's contents (no call needs it cleared): calls
+ * whose work may overlap on one device -- on different streams, or from
+ * different host threads without ordering -- race on it and give undefined
+ * results; calls on one stream are ordered and safe. */
+blaz_status blaz_matmul_static(const blaz_matrix *a, const blaz_matrix *b, const double *bdense, int64_t n,
+                               int64_t ldb, double *c, int64_t ldc, blaz_precision prec, hipStream_t stream);
 
 /* Bytes of workspace blaz_matmul_compressed needs: the contraction's own
  * workspace plus an m x n binary64 staging area for the product. */

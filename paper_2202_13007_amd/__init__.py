@@ -7,6 +7,7 @@ Python binding (``api``) and the build script (``_build``).
 from .api import (DIAGNOSE_FIELDS, Batch, BatchPlan, BlazMatrix, add, code_stride, compress,  # noqa: F401
                   compress_predicted, decompress,
                   diagnose, dot, dot_dense,
-                  matmul, matmul_compressed, matmul_compressed_workspace_bytes, matmul_workspace_bytes, scale,
+                  matmul, matmul_compressed, matmul_compressed_workspace_bytes, matmul_static,
+                  matmul_workspace_bytes, scale,
                   sub)
 from ._lib import BlazError, EXPORTS, LIB_PATH  # noqa: F401

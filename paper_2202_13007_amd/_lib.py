@@ -15,7 +15,7 @@ BLAZ_OK = 0
 STATUS_NAMES = {
     0: "BLAZ_OK", -1: "BLAZ_ERR_NULL", -2: "BLAZ_ERR_SHAPE", -3: "BLAZ_ERR_MISMATCH",
     -4: "BLAZ_ERR_ALIGN", -5: "BLAZ_ERR_ARG", -6: "BLAZ_ERR_UNSUPPORTED",
-    -7: "BLAZ_ERR_WORKSPACE", -8: "BLAZ_ERR_HIP",
+    -7: "BLAZ_ERR_WORKSPACE", -8: "BLAZ_ERR_HIP", -9: "BLAZ_ERR_TOO_LARGE",
 }
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
@@ -24,7 +24,7 @@ EXPORTS = (
     "blaz_block_count", "blaz_compressed_bytes", "blaz_code_stride", "blaz_compressed_bytes_lines", "blaz_compress", "blaz_compress_predicted",
     "blaz_decompress", "blaz_add",
     "blaz_sub", "blaz_scale", "blaz_dot", "blaz_dot_dense", "blaz_matmul_workspace_bytes",
-    "blaz_matmul", "blaz_matmul_tiled", "blaz_matmul_compressed_workspace_bytes", "blaz_matmul_compressed",
+    "blaz_matmul", "blaz_matmul_tiled", "blaz_matmul_static", "blaz_matmul_compressed_workspace_bytes", "blaz_matmul_compressed",
     "blaz_diagnose", "blaz_status_string", "blaz_batch_plan_bytes", "blaz_batch_plan", "blaz_batch_run",
 )
 
@@ -107,6 +107,7 @@ def lib():
         "blaz_matmul_workspace_bytes": ([I64, I64, I64, I, I], ctypes.c_size_t),
         "blaz_matmul": ([M, M, P, I64, I64, P, I64, I, P, ctypes.c_size_t, P], I),
         "blaz_matmul_tiled": ([M, M, P, I64, I64, P, I64, I, P, ctypes.c_size_t, ctypes.c_int32, P], I),
+        "blaz_matmul_static": ([M, M, P, I64, I64, P, I64, I, P], I),
         "blaz_matmul_compressed_workspace_bytes": ([I64, I64, I64, I, I], ctypes.c_size_t),
         "blaz_matmul_compressed": ([M, M, P, I64, I64, M, I, P, ctypes.c_size_t, ctypes.c_int32, P], I),
         "blaz_status_string": ([I], ctypes.c_char_p),

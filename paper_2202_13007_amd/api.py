@@ -320,6 +320,27 @@ def matmul(a: BlazMatrix, b: BlazMatrix | torch.Tensor, out: torch.Tensor | None
     return out
 
 
+STATIC_SCRATCH_BYTES = 256 << 20  # BLAZ_STATIC_SCRATCH_BYTES
+
+
+def matmul_static(a: BlazMatrix, b: BlazMatrix | torch.Tensor, out: torch.Tensor,
+                  prec: str = "fp64") -> torch.Tensor:
+    """C = A B as ``matmul``, with the workspace taken from the library's
+    static scratch array (no device allocation by the library or here: the
+    caller passes the output).  Calls that overlap on one device race on the
+    array; calls on one stream are ordered."""
+    stream, dev = _stream_dev()
+    compressed_b = isinstance(b, BlazMatrix)
+    n = _operand_b(a, b, "matmul_static B", dev)
+    _check_dense(out, "matmul_static out", dev, (a.rows, n))
+    ma = a.c(dev)
+    mb = b.c(dev) if compressed_b else None
+    check(_lib.lib().blaz_matmul_static(ctypes.byref(ma), ctypes.byref(mb) if compressed_b else None,
+                                        None if compressed_b else _ptr(b), n, 0 if compressed_b else b.stride(0),
+                                        _ptr(out), out.stride(0), _lib.PREC[prec], stream), "blaz_matmul_static")
+    return out
+
+
 def matmul_compressed_workspace_bytes(m: int, n: int, k: int, b_compressed: bool, prec: str = "fp64") -> int:
     return int(_lib.lib().blaz_matmul_compressed_workspace_bytes(m, n, k, int(b_compressed), _lib.PREC[prec]))
 

@@ -4,6 +4,7 @@
 
 #include <atomic>
 #include <cstdint>
+#include <mutex>
 
 #include "blaz_internal.hpp"
 #include "blaz_validate.hpp"
@@ -320,6 +321,49 @@ BLAZ_API blaz_status blaz_matmul_tiled(const blaz_matrix* a, const blaz_matrix* 
     return matmul_impl(a, b, bdense, n, ldb, c, ldc, prec, workspace, ws_bytes, tile, stream);
 }
 
+// ---------------------------------------------------------------------------
+// The product without a caller workspace.  Its workspace is `scratch`, a
+// file-scope device array that every device the library runs on holds until
+// the process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[BLAZ_STATIC_SCRATCH_BYTES];
+
+// This device's address of `scratch`, looked up on the first call on the
+// device (with that device current) and kept per device.
+static blaz_status static_scratch(void** out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::atomic<void*> addr[kMaxDevices];
+    static std::mutex lookup;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return BLAZ_ERR_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return BLAZ_ERR_UNSUPPORTED;
+    void* p = addr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> hold(lookup);
+        p = addr[dev].load(std::memory_order_acquire);
+        if (!p) {
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return BLAZ_ERR_HIP;
+            addr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return BLAZ_OK;
+}
+
+BLAZ_API blaz_status blaz_matmul_static(const blaz_matrix* a, const blaz_matrix* b, const double* bdense, int64_t n,
+                                        int64_t ldb, double* c, int64_t ldc, blaz_precision prec, hipStream_t stream)
+{
+    // a request whose workspace would not fit is refused before the lookup
+    if (a && check_matrix(a) == BLAZ_OK && valid_precision(prec) && check_shape(a->cols, n) == BLAZ_OK &&
+        matmul_workspace(a->rows, n, a->cols, b != nullptr, prec).total() > BLAZ_STATIC_SCRATCH_BYTES)
+        return BLAZ_ERR_TOO_LARGE;
+    void* ws = nullptr;
+    if (blaz_status st = static_scratch(&ws)) return st;
+    return matmul_impl(a, b, bdense, n, ldb, c, ldc, prec, ws, BLAZ_STATIC_SCRATCH_BYTES, 0, stream);
+}
+
 // The compressed-output product: the contraction writes C into a staging
 // region after the contraction's own workspace, then C is compressed.
 static size_t matmul_compressed_workspace(int64_t m, int64_t n, int64_t k, bool b_compressed, blaz_precision prec)
@@ -387,6 +431,9 @@ BLAZ_API const char* blaz_status_string(blaz_status status)
         case BLAZ_ERR_UNSUPPORTED: return "request not supported by this build";
         case BLAZ_ERR_WORKSPACE: return "workspace missing or too small";
         case BLAZ_ERR_HIP: return "the HIP runtime reported an error";
+        case BLAZ_ERR_TOO_LARGE:
+            return "the request needs more than the library's static scratch (BLAZ_STATIC_SCRATCH_BYTES); "
+                   "pass a workspace to blaz_matmul instead";
     }
     return "unknown status";
 }

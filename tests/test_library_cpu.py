@@ -149,8 +149,21 @@ def test_binding_rejects_host_tensors(L):
 
 
 def test_status_strings(L):
-    for st in range(-8, 1):
+    for st in range(-9, 1):
         assert len(L.blaz_status_string(st)) > 5
+
+
+def test_static_product_refuses_what_the_scratch_cannot_hold(L):
+    """blaz_matmul_static refuses a product whose workspace exceeds the
+    static array before it looks the array up or enqueues anything."""
+    scratch = 256 << 20
+    assert L.blaz_matmul_workspace_bytes(4096, 4096, 4096, 1, 0) == scratch
+    a, b = mat(4096, 4096, 1 << 40), mat(4096, 4104, 1 << 42)
+    assert L.blaz_matmul_workspace_bytes(4096, 4104, 4096, 1, 0) > scratch
+    assert L.blaz_matmul_static(B(a), B(b), None, 4104, 4104, 1 << 44, 4104, 0, None) == -9
+    # FP32 with a dense B: a 8192 x 8192 A alone needs 256 MiB, the blocked B^T more
+    a2 = mat(8192, 8192, 1 << 40)
+    assert L.blaz_matmul_static(B(a2), None, 1 << 42, 64, 64, 1 << 44, 64, 1, None) == -9
 
 
 def mat(rows, cols, base):
