@@ -57,11 +57,19 @@ __device__ __forceinline__ void normalize(double x[64])
 // lanes' registers through a 5 KiB LDS tile: every global instruction moves
 // 16 B per lane over a contiguous 1 KiB run (4 lanes per block row segment,
 // 16 blocks per instruction), and each lane then reads or writes its own
-// block's 64 B in LDS.  The tile gives each lane a 80-byte slot (64 B of data
-// + 16 B of padding) so that the per-lane LDS accesses spread over all banks.
+// block's 64 B in LDS.  Each lane has a 64-byte slot; the four 16-byte
+// chunks of slot s sit in the order c ^ ((s >> 1) & 3), which makes both
+// access patterns free of bank conflicts (gfx950 serves 16-byte accesses 8
+// lanes at a time from 32 four-byte banks): the global-side 8 lanes move the
+// four chunks of two neighbouring slots, the lane-side 8 lanes one chunk of
+// 8 consecutive slots.  (80-byte slots in natural order conflicted 2-way on
+// every global-side phase: 4.2e6 conflict cycles per 8192^2 compress.)
 // ---------------------------------------------------------------------------
 constexpr int kWave = 64;
-constexpr int kSlot = 10;  // doubles per lane slot in the LDS tile
+constexpr int kSlot = 8;  // doubles per lane slot in the LDS tile
+
+// Offset (doubles) of chunk c (columns 2c, 2c+1 of a block row) of slot s.
+__device__ __forceinline__ int slot_chunk(int s, int c) { return s * kSlot + 2 * (c ^ ((s >> 1) & 3)); }
 
 // Global offsets (in doubles, row 0) of the four 16-byte chunks a lane moves:
 // chunk k covers part (lane & 3) of block wave_base + (lane >> 2) + 16 k.
@@ -124,11 +132,11 @@ __device__ __forceinline__ void load_blocks(const double* __restrict__ A, int64_
         for (int r = 0; r < 8; ++r) {
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                *reinterpret_cast<f64x2*>(&tile[((lane >> 2) + 16 * k) * kSlot + 2 * (lane & 3)]) = g[r][k];
+                *reinterpret_cast<f64x2*>(&tile[slot_chunk((lane >> 2) + 16 * k, lane & 3)]) = g[r][k];
             __syncthreads();
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-                const f64x2 v = *reinterpret_cast<const f64x2*>(&tile[lane * kSlot + 2 * p]);
+                const f64x2 v = *reinterpret_cast<const f64x2*>(&tile[slot_chunk(lane, p)]);
                 x[r * 8 + 2 * p] = v[0];
                 x[r * 8 + 2 * p + 1] = v[1];
             }
@@ -487,11 +495,11 @@ __device__ __forceinline__ void decompress_wave(const double* __restrict__ f, co
         for (int r = 0; r < 8; ++r) {
 #pragma unroll
             for (int p = 0; p < 4; ++p)
-                *reinterpret_cast<f64x2*>(&tile[lane * kSlot + 2 * p]) = f64x2{x[r * 8 + 2 * p], x[r * 8 + 2 * p + 1]};
+                *reinterpret_cast<f64x2*>(&tile[slot_chunk(lane, p)]) = f64x2{x[r * 8 + 2 * p], x[r * 8 + 2 * p + 1]};
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const f64x2 v = *reinterpret_cast<const f64x2*>(&tile[((lane >> 2) + 16 * k) * kSlot + 2 * (lane & 3)]);
+                const f64x2 v = *reinterpret_cast<const f64x2*>(&tile[slot_chunk((lane >> 2) + 16 * k, lane & 3)]);
                 if (wc.ok[k]) out.store2(wc.off[k] + r * lda, v[0], v[1]);
             }
             __syncthreads();
