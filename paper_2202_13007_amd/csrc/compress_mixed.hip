@@ -5,13 +5,23 @@
 // Delta' = Delta / s, the DC coefficient (fixed-order binary64, as in the
 // plain kernel), m, phi and the truncation of the codes (Eq. eqphi) are
 // exactly those of compress_f64_kernel.  Only the 63 other coefficients of
-// the two-dimensional DCT-II (Eq. eqdct) change arithmetic: for the wave's
-// 64 blocks they are one matrix product
-//     D[b][c] = sum_e Delta'[b][e] K[e][c],   K[e][c] = T(i, u) T(j, v)
-// with e = 8u + v the element and c = 8i + j the coefficient (the Kronecker
-// form of the separable transform), 64 x 64 x 64 per wave on MFMA with FP32
-// accumulation.  Delta' goes through LDS to reach the MFMA operand layout and
-// D comes back through LDS to one block per lane for the quantization.
+// the two-dimensional DCT-II (Eq. eqdct), D = T Delta' T^T, change
+// arithmetic: both 8-point passes run on MFMA with FP32 accumulation.
+//
+// Four blocks at a time form a 16 x 16 operand X = [P Q; R S] (blocks side by
+// side and one above the other).  The row pass is X diag(T^T, T^T), which is
+// [P T^T  Q T^T; R T^T  S T^T], and the column pass is diag(T, T) times that,
+// which is T (.) T^T of each block: two 16 x 16 x 16 products per four
+// blocks, a quarter of the multiply-adds of the 64 x 64 Kronecker form.  The
+// k index of each product is assigned to (lane group g, slot t) as
+// k = 4 g + t, for A and B alike, which the sum over k allows.  With that
+// assignment the row pass's result, which lane (g, n) holds as rows
+// 4 g .. 4 g + 3 of column n, is exactly the B operand lane (g, n) supplies
+// to the column pass, so the two passes chain in registers; the block
+// diagonal constants are the same four values per lane for both passes.
+// Delta' reaches the operand layout through LDS (rows of 4 values, 16-byte
+// or 8-byte reads) and D returns through LDS to one block per lane for the
+// quantization; both layouts are free of bank conflicts.
 #include <hip/hip_runtime.h>
 
 #include "blaz_codec.hpp"
@@ -21,57 +31,25 @@
 namespace blaz {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// bf16 bit pattern of a float, rounded to nearest even (finite inputs).
-constexpr uint16_t bf16_bits(float f)
-{
-    uint32_t u = __builtin_bit_cast(uint32_t, f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-constexpr float bf16_value(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+// FP32 staging of Delta' and of D: one block per 68 floats (4 floats of
+// padding), row u as two 16-byte halves stored in the order
+// h ^ ((u >> 2) & 1).  Writes (a lane's own block, 8 lanes per access
+// phase on 8 blocks) and operand reads (8 lanes on 8 rows of one block)
+// both touch 32 distinct banks.
+constexpr int kPitchF = 68;
+__device__ __forceinline__ int f32_slot(int blk, int u, int h) { return blk * kPitchF + 8 * u + 4 * (h ^ ((u >> 2) & 1)); }
 
-// K in FP32, [e][c]: the B operand of the FP32 16x16x4 MFMA takes one k = e
-// row element per lane.
-struct KronF32 {
-    float v[64 * 64];
-};
-// K split into BF16 hi + lo, stored transposed [c][e]: the B operand of the
-// BF16 16x16x32 MFMA takes 8 consecutive e of one column c per lane.
-struct alignas(16) KronBF16 {
-    uint16_t hi[64 * 64];
-    uint16_t lo[64 * 64];
-};
+// BF16 staging of Delta' (hi and lo arrays): one block per 72 bf16, row u as
+// two 8-byte halves stored in the order h ^ ((u >> 1) & 1): 16-byte row
+// writes and 8-byte operand reads without bank conflicts.
+constexpr int kPitchH = 72;
+__device__ __forceinline__ int bf16_slot(int blk, int u, int h) { return blk * kPitchH + 8 * u + 4 * (h ^ ((u >> 1) & 1)); }
 
-constexpr double kron(int e, int c) { return dct_t(c / 8, e / 8) * dct_t(c % 8, e % 8); }
-
-constexpr KronF32 make_kron_f32()
-{
-    KronF32 k{};
-    for (int e = 0; e < 64; ++e)
-        for (int c = 0; c < 64; ++c) k.v[e * 64 + c] = (float)kron(e, c);
-    return k;
-}
-
-constexpr KronBF16 make_kron_bf16()
-{
-    KronBF16 k{};
-    for (int c = 0; c < 64; ++c)
-        for (int e = 0; e < 64; ++e) {
-            const double t = kron(e, c);
-            const uint16_t h = bf16_bits((float)t);
-            k.hi[c * 64 + e] = h;
-            k.lo[c * 64 + e] = bf16_bits((float)(t - (double)bf16_value(h)));
-        }
-    return k;
-}
-
-__constant__ KronF32 kKronF32 = make_kron_f32();
-__constant__ KronBF16 kKronBF16 = make_kron_bf16();
-
-constexpr int kRowF = 65;  // floats per LDS row: consecutive rows start one bank apart
-constexpr int kRowH = 72;  // bf16 per LDS row (144 B): 16 rows land on 16 distinct 4-bank groups
+__device__ __forceinline__ short bf16_bits_of(__bf16 h) { return __builtin_bit_cast(short, h); }
 
 template <int kPrec, bool kVec, bool kPsi>
 __global__ __launch_bounds__(kWave, 2) void compress_mixed_kernel(const double* __restrict__ A, int64_t lda,
@@ -80,9 +58,10 @@ __global__ __launch_bounds__(kWave, 2) void compress_mixed_kernel(const double* 
                                                                uint32_t* __restrict__ codes,
                                                                uint8_t* __restrict__ psi)
 {
-    // One buffer for the row staging, the MFMA operand, the MFMA result and
-    // the packed codes, used one after the other.
-    __shared__ __align__(16) unsigned char smem[2 * 64 * kRowH * 2];
+    // One buffer for the row staging, the operand staging, D and the packed
+    // codes, used one after the other.
+    __shared__ __align__(16) unsigned char smem[2 * 64 * kPitchH * 2];
+    static_assert(sizeof(smem) >= 64 * kPitchF * 4, "D fits the buffer");
     const int lane = threadIdx.x;
     const int g = lane >> 4, l16 = lane & 15;
     const int64_t wave_base = (int64_t)blockIdx.x * kWave;
@@ -93,91 +72,114 @@ __global__ __launch_bounds__(kWave, 2) void compress_mixed_kernel(const double* 
     if constexpr (kPsi) predict_block<true, false>(x, so_, psi, wave_base + lane, wave_base + lane < nblk);
     divide_by_slope(x, so_.s);
 
-    f32x4 acc[4][4];
+    // The block-diagonal constants of lane (g, n = l16) at slot t: row
+    // 4 g + t, column n of diag(T^T, T^T) (row pass, B operand) and row n,
+    // column 4 g + t of diag(T, T) (column pass, A operand), both
+    // T(n % 8, 4 (g % 2) + t) when the diagonal blocks agree (g / 2 == n / 8).
+    double tc[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 4; ++t) tc[t] = (g >> 1) == (l16 >> 3) ? dct_t(l16 & 7, 4 * (g & 1) + t) : 0.0;
 
+    // Operand of the row pass for group G: lane (g, m = l16) supplies
+    // X[m][4 g .. 4 g + 3] = half g % 2 of row m % 8 of block
+    // 4 G + 2 (m / 8) + g / 2.  Result: lane (g, c) holds
+    // D[4 (g % 2) + r][c % 8], r = 0..3, of block 4 G + 2 (g / 2) + c / 8.
+    f32x4 dacc[16];
+    const int xu = l16 & 7, xh = g & 1, xb = 2 * (l16 >> 3) + (g >> 1);
     if constexpr (kPrec == BLAZ_PREC_FP32) {
-        // Operand A[b][e] = Delta'[b][e] in FP32, row b = lane.
-        float* af = reinterpret_cast<float*>(smem);
+        float* sf = reinterpret_cast<float*>(smem);
+        __syncthreads();  // the row staging is done with the buffer
 #pragma unroll
-        for (int e = 0; e < 64; ++e) af[lane * kRowF + e] = (float)x[e];
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                *reinterpret_cast<f32x4*>(&sf[f32_slot(lane, u, h)]) =
+                    f32x4{(float)x[8 * u + 4 * h], (float)x[8 * u + 4 * h + 1], (float)x[8 * u + 4 * h + 2],
+                          (float)x[8 * u + 4 * h + 3]};
         __syncthreads();
-        // 16x16x4: lane holds A[m = l%16][k = l/16] and B[k = l/16][n = l%16].
+        float c[4];
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) {
-            float a[4], bv[4];
+        for (int t = 0; t < 4; ++t) c[t] = (float)tc[t];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) a[mt] = af[(mt * 16 + l16) * kRowF + ks * 4 + g];
+        for (int G = 0; G < 16; ++G) {
+            const f32x4 a = *reinterpret_cast<const f32x4*>(&sf[f32_slot(4 * G + xb, xu, xh)]);
+            f32x4 r = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) bv[nt] = kKronF32.v[(ks * 4 + g) * 64 + nt * 16 + l16];
+            for (int t = 0; t < 4; ++t) r = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], c[t], r, 0, 0, 0);
+            f32x4 d = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt], bv[nt], acc[mt][nt], 0, 0, 0);
+            for (int t = 0; t < 4; ++t) d = __builtin_amdgcn_mfma_f32_16x16x4f32(c[t], r[t], d, 0, 0, 0);
+            dacc[G] = d;
         }
     } else {
-        // Operand A[b][e] = Delta'[b][e] split into BF16 hi + lo.
-        __bf16* ah = reinterpret_cast<__bf16*>(smem);
-        __bf16* al = ah + 64 * kRowH;
+        // Delta' = hi + lo, hi = bf16(Delta'), lo = bf16(Delta' - hi)
+        __bf16* sh = reinterpret_cast<__bf16*>(smem);
+        __bf16* sl = sh + 64 * kPitchH;
+        __syncthreads();  // the row staging is done with the buffer
 #pragma unroll
-        for (int e0 = 0; e0 < 64; e0 += 8) {
+        for (int u = 0; u < 8; ++u) {
             bf16x8 h, l;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const float xf = (float)x[e0 + q];
-                const __bf16 hq = (__bf16)xf;
-                h[q] = hq;
-                l[q] = (__bf16)(float)(x[e0 + q] - (double)(float)hq);
+                const double xv = x[8 * u + q];
+                const __bf16 hq = (__bf16)(float)xv;
+                // slot of value q: its half q / 4 lands in position (q / 4) ^ ((u >> 1) & 1)
+                const int pos = 4 * ((q >> 2) ^ ((u >> 1) & 1)) + (q & 3);
+                h[pos] = hq;
+                l[pos] = (__bf16)(float)(xv - (double)(float)hq);
             }
-            *reinterpret_cast<bf16x8*>(&ah[lane * kRowH + e0]) = h;
-            *reinterpret_cast<bf16x8*>(&al[lane * kRowH + e0]) = l;
+            *reinterpret_cast<bf16x8*>(&sh[lane * kPitchH + 8 * u]) = h;
+            *reinterpret_cast<bf16x8*>(&sl[lane * kPitchH + 8 * u]) = l;
         }
         __syncthreads();
-        // 16x16x32: lane holds the 8 k-values 8*(l/16).. of row (A) or
-        // column (B) l%16, for A and B alike.
+        s16x4 ch, cl;
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            bf16x8 a_hi[4], a_lo[4], b_hi[4], b_lo[4];
+        for (int t = 0; t < 4; ++t) {
+            const __bf16 hq = (__bf16)(float)tc[t];
+            ch[t] = bf16_bits_of(hq);
+            cl[t] = bf16_bits_of((__bf16)(float)(tc[t] - (double)(float)hq));
+        }
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const int off = (mt * 16 + l16) * kRowH + ks * 32 + 8 * g;
-                a_hi[mt] = *reinterpret_cast<const bf16x8*>(&ah[off]);
-                a_lo[mt] = *reinterpret_cast<const bf16x8*>(&al[off]);
+        for (int G = 0; G < 16; ++G) {
+            const int off = bf16_slot(4 * G + xb, xu, xh);
+            const s16x4 ah = __builtin_bit_cast(s16x4, *reinterpret_cast<const bf16x4*>(&sh[off]));
+            const s16x4 al = __builtin_bit_cast(s16x4, *reinterpret_cast<const bf16x4*>(&sl[off]));
+            f32x4 r = f32x4{0.f, 0.f, 0.f, 0.f};
+            r = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, ch, r, 0, 0, 0);
+            r = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, cl, r, 0, 0, 0);
+            r = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, ch, r, 0, 0, 0);
+            s16x4 rh, rl;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const __bf16 hq = (__bf16)r[t];
+                rh[t] = bf16_bits_of(hq);
+                rl[t] = bf16_bits_of((__bf16)(r[t] - (float)hq));
             }
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const int off = (nt * 16 + l16) * 64 + ks * 32 + 8 * g;
-                b_hi[nt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&kKronBF16.hi[off]));
-                b_lo[nt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&kKronBF16.lo[off]));
-            }
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt) {
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_lo[mt], b_hi[nt], acc[mt][nt], 0, 0, 0);
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi[mt], b_lo[nt], acc[mt][nt], 0, 0, 0);
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_hi[mt], b_hi[nt], acc[mt][nt], 0, 0, 0);
-                }
+            f32x4 d = f32x4{0.f, 0.f, 0.f, 0.f};
+            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ch, rl, d, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(cl, rh, d, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ch, rh, d, 0, 0, 0);
+            dacc[G] = d;
         }
     }
     __syncthreads();  // every operand read is done before D overwrites the buffer
 
-    // D[b][c]: value r of lane l in tile (mt, nt) is row b = 16 mt + 4 (l/16) + r,
-    // column c = 16 nt + l%16 (16x16 FP32-accumulator layout).
+    // D back to one block per lane, each block stored transposed (row j of
+    // the stored block is column j of D): lane (g, c) writes D[4 (g % 2) ..
+    // 4 (g % 2) + 3][c % 8] as one 16-byte half.
     float* df = reinterpret_cast<float*>(smem);
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) df[(mt * 16 + 4 * g + r) * kRowF + nt * 16 + l16] = acc[mt][nt][r];
+    for (int G = 0; G < 16; ++G)
+        *reinterpret_cast<f32x4*>(&df[f32_slot(4 * G + 2 * (g >> 1) + (l16 >> 3), l16 & 7, g & 1)]) = dacc[G];
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 64; ++c) x[c] = (double)df[lane * kRowF + c];
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const f32x4 v = *reinterpret_cast<const f32x4*>(&df[f32_slot(lane, j, h)]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[8 * (4 * h + q) + j] = (double)v[q];
+        }
     x[0] = so_.dc;
 
     quantize_store(x, so_, nblk, wave_base, lane, smem, fo, so, phio, codes);
