@@ -557,6 +557,18 @@ def serving_leg(torch, dA, dB, count, budget_gib, loads=(0.5, 0.8, 1.2)):
         cap[name] = max(srv.run(make_requests(len(calib), rate=0.0, seed=502), mode)["req_per_s"] for _ in range(2))
     out["capacity_req_per_s"] = {k: round(v, 1) for k, v in cap.items()}
     out["capacity_speedup_vs_plain"] = {k: round(v / cap["plain"], 3) for k, v in cap.items()}
+    # How much of the plain form's device time the binary64 products take:
+    # the calibration set's matmul requests alone, in the plain form.  Running
+    # every other request concurrently with them can shorten the set by at
+    # most the remaining share.
+    t_all = len(calib) / cap["plain"]
+    t_mm = min(servers["plain"].run([r for r in make_requests(len(calib), rate=0.0, seed=502)
+                                     if r.op == "matmul"], "plain")["makespan_s"] for _ in range(2))
+    mm = [r for r in calib if r.op == "matmul"]
+    out["plain_fp64_matmul_share"] = {
+        "matmul_requests": len(mm), "matmul_only_s": round(t_mm, 4), "all_requests_s": round(t_all, 4),
+        "share": round(t_mm / t_all, 4), "max_gain_from_overlap": round(t_all / t_mm, 4),
+        "note": "the calibration set's binary64 products alone in the plain form, against the whole set"}
     out["runs"] = {}
     for load in loads:
         rate = load * cap["plain"]
@@ -572,7 +584,134 @@ def serving_leg(torch, dA, dB, count, budget_gib, loads=(0.5, 0.8, 1.2)):
     return out
 
 
+# ---------------------------------------------------------------------------
+# Summaries of rocprofv3 output (CSV directories written with -d DIR -o run),
+# printed as the text tables kept under profiles/.  CPU only.
+# ---------------------------------------------------------------------------
+
+def short_kernel_name(name: str) -> str:
+    name = name[5:] if name.startswith("void ") else name
+    depth, cut = 0, len(name)
+    for i, ch in enumerate(name):  # drop the parameter list (outside template brackets)
+        depth += ch == "<"
+        depth -= ch == ">"
+        if ch == "(" and depth == 0:
+            cut = i
+            break
+    name = name[:cut]
+    if name.startswith("at::native::"):
+        name = "torch " + name[len("at::native::"):]
+    return name[:62]
+
+
+def read_csv(path):
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_trace(d):
+    """Per (kernel, grid size in work-items, workgroup size): calls and the
+    average, median, min and max duration from run_kernel_trace.csv."""
+    groups = {}
+    for r in read_csv(os.path.join(d, "run_kernel_trace.csv")):
+        key = (short_kernel_name(r["Kernel_Name"]), int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]),
+               int(r["Workgroup_Size_X"]) * int(r["Workgroup_Size_Y"]) * int(r["Workgroup_Size_Z"]))
+        groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines = [f"{'kernel':62s} {'grid':>9s} {'wg':>4s} {'calls':>6s} {'avg_us':>9s} {'median_us':>10s} {'min_us':>9s} "
+             f"{'max_us':>9s}"]
+    for (k, g, w), ts in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        ts = sorted(ts)
+        lines.append(f"{k:62s} {g:9d} {w:4d} {len(ts):6d} {sum(ts) / len(ts):9.2f} {ts[len(ts) // 2]:10.2f} "
+                     f"{ts[0]:9.2f} {ts[-1]:9.2f}")
+    return "\n".join(lines)
+
+
+def summarize_pmc(d):
+    """Per (kernel, grid size): dispatches and each counter's average value."""
+    groups = {}
+    for r in read_csv(os.path.join(d, "run_counter_collection.csv")):
+        key = (short_kernel_name(r["Kernel_Name"]), int(r["Grid_Size"]))
+        groups.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    counters = sorted({c for v in groups.values() for c in v})
+    lines = [f"{'kernel':62s} {'grid':>9s} {'n':>4s} " + " ".join(f"{c:>22s}" for c in counters)]
+    for (k, g), v in sorted(groups.items()):
+        n = max(len(x) for x in v.values())
+        lines.append(f"{k:62s} {g:9d} {n:4d} " + " ".join(
+            f"{sum(v[c]) / len(v[c]):22.4g}" if c in v else f"{'-':>22s}" for c in counters))
+    return "\n".join(lines)
+
+
+STEP_KERNELS = {  # kernel -> (sources, algorithmic bytes read, written per block) on the plain-8192 step
+    "compress_f64_kernel": (CODEC_SOURCES, BLOCK, RECORD),
+    "decompress_kernel": (CODEC_SOURCES, RECORD, BLOCK),
+    "add_kernel": (("paper_2202_13007_amd/csrc/ops.hip", "paper_2202_13007_amd/csrc/blaz_ops.hpp"), 2 * RECORD, RECORD),
+    "scale_kernel": (("paper_2202_13007_amd/csrc/ops.hip", "paper_2202_13007_amd/csrc/blaz_ops.hpp"), RECORD, RECORD),
+}
+
+
+def summarize_traffic(fetch_dir, write_dir, nblk=1 << 20, copy_bytes=1 << 29):
+    """HBM bytes per dispatch of the step's kernels from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
+    for the bench's plain copy of a 512 MiB matrix (copy_bytes each way).
+    Writes profiles/traffic.json (bench.py fills `roofline.traffic` from it
+    while the kernel's sources are unchanged) and returns the text table."""
+    def per_kernel(d, counter):
+        acc = {}
+        for r in read_csv(os.path.join(d, "run_counter_collection.csv")):
+            if r["Counter_Name"] != counter:
+                continue
+            name = short_kernel_name(r["Kernel_Name"])
+            if int(r["Grid_Size"]) == 1048576 and name.startswith("blaz::"):
+                base = name.split("::")[1].split("<")[0]
+            elif "copyBuffer" in name and int(r["Grid_Size"]) == 131072:  # the 512 MiB copy
+                base = "copy"
+            else:
+                continue
+            acc.setdefault(base, []).append(float(r["Counter_Value"]))
+        return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    ff = copy_bytes / (fetch["copy"][0] * 1024)
+    wf = copy_bytes / (write["copy"][0] * 1024)
+    lines = [f"copy: FETCH_SIZE {fetch['copy'][0]:.0f} KiB, WRITE_SIZE {write['copy'][0]:.0f} KiB per dispatch for "
+             f"{copy_bytes:,} B each way -> factors {ff:.4f}, {wf:.4f}"]
+    rec = {}
+    for k, (srcs, rd, wr) in STEP_KERNELS.items():
+        if k not in fetch or k not in write:
+            continue
+        rb, wb = fetch[k][0] * 1024 * ff, write[k][0] * 1024 * wf
+        alg = (rd + wr) * nblk
+        rec[k] = {"workload": "plain-8192 (1,048,576 blocks)", "sources": list(srcs),
+                  "sources_sha256": sources_sha256(srcs), "bytes_per_launch": int(round(rb + wb)),
+                  "read_bytes": int(round(rb)), "write_bytes": int(round(wb)), "fetch_factor": round(ff, 5),
+                  "write_factor": round(wf, 5), "dispatches": [fetch[k][1], write[k][1]]}
+        lines.append(f"{k.split('_')[0]:11s} FETCH_SIZE {fetch[k][0]:10.1f} KiB x{ff:.4f} = {rb / 1e6:8.2f} MB "
+                     f"(algorithmic {rd * nblk / 1e6:8.2f})   WRITE_SIZE {write[k][0]:10.1f} KiB x{wf:.4f} = "
+                     f"{wb / 1e6:8.2f} MB (algorithmic {wr * nblk / 1e6:8.2f})   total/algorithmic "
+                     f"{(rb + wb) / alg:.4f}")
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    return "\n".join(lines)
+
+
+def summarize_main(argv):
+    """python bench.py --summarize {trace DIR | pmc DIR | traffic FETCH_DIR WRITE_DIR}"""
+    kind = argv[0]
+    if kind == "trace":
+        print(summarize_trace(argv[1]))
+    elif kind == "pmc":
+        print(summarize_pmc(argv[1]))
+    elif kind == "traffic":
+        print(summarize_traffic(argv[1], argv[2]))
+    else:
+        raise SystemExit(summarize_main.__doc__)
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize":
+        summarize_main(sys.argv[2:])
+        return
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
