@@ -529,7 +529,8 @@ def serving_leg(torch, dA, dB, count, budget_gib, loads=(0.5, 0.8, 1.2)):
     fields (each side n uses their n x n corners).  The plain form's capacity
     is measured with every request of a calibration set arriving at once;
     the Poisson stream then arrives at 0.5x, 0.8x and 1.2x that rate and is
-    served in the plain form, batched with FP64 matmuls, and batched with
+    served in the plain form, batched with FP64 matmuls (standalone, and
+    with each tick's products of side <= 512 as one group), and batched with
     BF16x3 matmuls."""
     from paper_2202_13007_amd.serve import OperandPool, Server, make_requests
     from paper_2202_13007_amd.tune import Autotuner
@@ -544,6 +545,7 @@ def serving_leg(torch, dA, dB, count, budget_gib, loads=(0.5, 0.8, 1.2)):
            "sides": "log-uniform in [64, 8192], multiples of 8"}
     servers = {"plain": Server(pool, budget, "fp64", tuner=tuner),
                "batched_fp64": Server(pool, budget, "fp64", tuner=tuner),
+               "batched_fp64_grouped": Server(pool, budget, "fp64", tuner=tuner, group_products=True),
                "batched_bf16x3": Server(pool, budget, "bf16x3", tuner=tuner)}
     for srv in servers.values():
         srv.prepare(calib)

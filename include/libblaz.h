@@ -356,6 +356,72 @@ blaz_status blaz_batch_plan(const blaz_batch_item *items, int64_t n_items, void 
 blaz_status blaz_batch_run(const void *plan_dev, int64_t n_plan, int64_t total_chunks, uint64_t *counter,
                            int64_t workgroups, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Grouped products: many binary64 matrix multiplications (last paragraph of
+ * Section "Basic Linear Algebra Algorithms": every block rebuilt once, then
+ * the product) of any sizes in at most three launches -- one rebuild of
+ * every compressed operand of every product, then one contraction over the
+ * output tiles of every product on 128 x 128 tiles and one on 64 x 64 tiles.
+ * Each product computes exactly what blaz_matmul_tiled computes for it with
+ * BLAZ_PREC_FP64 (the same per-block rebuild and per-tile contraction run),
+ * bit for bit.
+ *
+ * Usage mirrors batching: blaz_matmul_group_plan() validates the items with
+ * blaz_matmul's rules, assigns each product's rebuilt operands a region of
+ * the caller's workspace and writes a plan image into caller-owned HOST
+ * memory; the caller copies the image to device memory; blaz_matmul_group_run()
+ * enqueues the launches (no memset, copy or allocation, so a run can be
+ * captured in a HIP graph; the plan and workspace may be reused by later
+ * runs on the same stream).  The products of a group run concurrently: no
+ * product may write another's operands or output.
+ * ------------------------------------------------------------------------- */
+typedef struct blaz_matmul_item {
+    blaz_matrix a;          /* A, m x k, compressed (two kept lines)                */
+    blaz_matrix b;          /* B, k x n, compressed (two kept lines), or an empty   */
+                            /* descriptor (rows = cols = 0) when bdense is given    */
+    const double *bdense;   /* dense binary64 B, k x n (ldb >= n, even, 16-byte     */
+                            /* aligned), or NULL when b is compressed               */
+    int64_t n;              /* columns of B and C                                   */
+    int64_t ldb;            /* leading dimension of bdense                          */
+    double *c;              /* C, m x n binary64, leading dimension ldc >= n        */
+    int64_t ldc;
+    int32_t tile;           /* output tile 64 or 128; 0 = blaz_matmul's choice     */
+    int32_t reserved;       /* must be 0                                            */
+} blaz_matmul_item;
+
+/* Counts a plan was built with (host memory, filled by the plan call, read
+ * by the run call). */
+typedef struct blaz_matmul_group_info {
+    int64_t rebuild_jobs;    /* compressed operands to rebuild                     */
+    int64_t rebuild_waves;   /* waves of the rebuild launch                        */
+    int64_t items128;        /* products on 128 x 128 tiles                        */
+    int64_t workgroups128;   /* workgroups of their contraction launch             */
+    int64_t items64;         /* products on 64 x 64 tiles                          */
+    int64_t workgroups64;
+    size_t plan_bytes;       /* bytes of the plan image                            */
+    size_t workspace_bytes;  /* bytes of workspace the products need               */
+} blaz_matmul_group_info;
+
+/* Bytes of the plan image for n_items products (an upper bound). */
+size_t blaz_matmul_group_plan_bytes(int64_t n_items);
+
+/* Validate items[0..n_items) (BLAZ_PREC_FP64 contraction) and write the plan
+ * image into plan (host, plan_bytes >= blaz_matmul_group_plan_bytes(n_items),
+ * 8-byte aligned).  workspace: device memory of ws_bytes bytes, 256-byte
+ * aligned, holding every product's rebuilt operands (8 m k bytes for A and
+ * 8 k n for a compressed B, each rounded up to 256); info->workspace_bytes
+ * returns the bytes needed, also when the call fails with BLAZ_ERR_WORKSPACE
+ * (so a first call with workspace = NULL sizes it).  Products with m = 0 or
+ * n = 0 are dropped; k = 0 writes zeros.  On an invalid product the status
+ * of the first violated rule is returned and info->rebuild_jobs holds the
+ * product's index.  Host-only: nothing is read or written on the device. */
+blaz_status blaz_matmul_group_plan(const blaz_matmul_item *items, int64_t n_items, void *workspace,
+                                   size_t ws_bytes, void *plan, size_t plan_bytes, blaz_matmul_group_info *info);
+
+/* Run a plan whose image has been copied to plan_dev (device, 8-byte
+ * aligned), with the counts the plan call returned in info. */
+blaz_status blaz_matmul_group_run(const void *plan_dev, const blaz_matmul_group_info *info, hipStream_t stream);
+
 /* A static description of a status code. */
 const char *blaz_status_string(blaz_status status);
 

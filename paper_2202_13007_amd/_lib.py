@@ -26,6 +26,7 @@ EXPORTS = (
     "blaz_sub", "blaz_scale", "blaz_dot", "blaz_dot_dense", "blaz_matmul_workspace_bytes",
     "blaz_matmul", "blaz_matmul_tiled", "blaz_matmul_static", "blaz_matmul_compressed_workspace_bytes", "blaz_matmul_compressed",
     "blaz_diagnose", "blaz_status_string", "blaz_batch_plan_bytes", "blaz_batch_plan", "blaz_batch_run",
+    "blaz_matmul_group_plan_bytes", "blaz_matmul_group_plan", "blaz_matmul_group_run",
 )
 
 
@@ -57,6 +58,35 @@ class BatchItemC(ctypes.Structure):
         ("ycol", ctypes.c_void_p),
         ("count", ctypes.c_int64),
         ("out", ctypes.c_void_p),
+    ]
+
+
+class MatmulItemC(ctypes.Structure):
+    """Mirror of ``blaz_matmul_item``."""
+    _fields_ = [
+        ("a", BlazMatrixC),
+        ("b", BlazMatrixC),
+        ("bdense", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("ldb", ctypes.c_int64),
+        ("c", ctypes.c_void_p),
+        ("ldc", ctypes.c_int64),
+        ("tile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class MatmulGroupInfoC(ctypes.Structure):
+    """Mirror of ``blaz_matmul_group_info``."""
+    _fields_ = [
+        ("rebuild_jobs", ctypes.c_int64),
+        ("rebuild_waves", ctypes.c_int64),
+        ("items128", ctypes.c_int64),
+        ("workgroups128", ctypes.c_int64),
+        ("items64", ctypes.c_int64),
+        ("workgroups64", ctypes.c_int64),
+        ("plan_bytes", ctypes.c_size_t),
+        ("workspace_bytes", ctypes.c_size_t),
     ]
 
 
@@ -114,6 +144,9 @@ def lib():
         "blaz_batch_plan_bytes": ([I64], ctypes.c_size_t),
         "blaz_batch_plan": ([P, I64, P, ctypes.c_size_t, P, P], I),
         "blaz_batch_run": ([P, I64, I64, P, I64, P], I),
+        "blaz_matmul_group_plan_bytes": ([I64], ctypes.c_size_t),
+        "blaz_matmul_group_plan": ([P, I64, P, ctypes.c_size_t, P, ctypes.c_size_t, P], I),
+        "blaz_matmul_group_run": ([P, P, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)

@@ -451,6 +451,77 @@ class Batch:
         return BatchPlan(plan_dev, host, n_plan.value, total.value, counter, list(self._keep))
 
 
+class MatmulGroup:
+    """Collects binary64 products C = A B (A compressed, B compressed or
+    dense float64); ``plan()`` validates them, allocates the workspace for
+    the rebuilt operands and uploads the plan.  Products run concurrently:
+    none may write another's operands or output."""
+
+    def __init__(self):
+        self.items = []
+        self._keep = []
+
+    def add(self, a: BlazMatrix, b: BlazMatrix | torch.Tensor, out: torch.Tensor, tile: int = 0):
+        dev = torch.cuda.current_device()
+        compressed_b = isinstance(b, BlazMatrix)
+        n = _operand_b(a, b, "group matmul B", dev)
+        _check_dense(out, "group matmul out", dev, (a.rows, n))
+        it = _lib.MatmulItemC()
+        it.a = a.c(dev)
+        it.b = b.c(dev) if compressed_b else BlazMatrixC(0, 0, None, None, None, None)
+        it.bdense = None if compressed_b else b.data_ptr()
+        it.n = n
+        it.ldb = 0 if compressed_b else b.stride(0)
+        it.c = out.data_ptr()
+        it.ldc = out.stride(0)
+        it.tile = int(tile)
+        it.reserved = 0
+        self.items.append(it)
+        self._keep.extend((a, b, out))
+        return self
+
+    def plan(self, device=None, workspace: torch.Tensor | None = None) -> "MatmulGroupPlan":
+        n = len(self.items)
+        arr = (_lib.MatmulItemC * max(n, 1))(*self.items)
+        nbytes = int(_lib.lib().blaz_matmul_group_plan_bytes(n))
+        host = torch.empty(max(nbytes, 8), dtype=torch.uint8, pin_memory=torch.cuda.is_available())
+        info = _lib.MatmulGroupInfoC()
+        dev = torch.device("cuda") if device is None else torch.device(device)
+
+        def call(ws):
+            return _lib.lib().blaz_matmul_group_plan(ctypes.cast(arr, ctypes.c_void_p), n,
+                                                     None if ws is None else _ptr(ws),
+                                                     0 if ws is None else ws.numel(),
+                                                     ctypes.c_void_p(host.data_ptr()), host.numel(),
+                                                     ctypes.byref(info))
+        st = call(workspace)
+        if st == -7 and workspace is None:  # BLAZ_ERR_WORKSPACE: size it, then plan again
+            workspace = torch.empty(max(int(info.workspace_bytes), 1), dtype=torch.uint8, device=dev)
+            st = call(workspace)
+        if st != _lib.BLAZ_OK:
+            raise _lib.BlazError(st, f"blaz_matmul_group_plan (product {info.rebuild_jobs})")
+        plan_dev = host.to(dev, non_blocking=True)
+        return MatmulGroupPlan(plan_dev, host, info, workspace, list(self._keep))
+
+
+class MatmulGroupPlan:
+    """A validated group of products resident on the device; ``run()``
+    enqueues the rebuild and contraction launches."""
+
+    def __init__(self, plan_dev, plan_host, info, workspace, keep):
+        self.plan_dev, self.plan_host, self.info = plan_dev, plan_host, info
+        self.workspace = workspace
+        self._keep = keep
+
+    def run(self):
+        stream, dev = _stream_dev()
+        if not _on_device(self.plan_dev, dev):
+            raise ValueError(f"MatmulGroupPlan.run: the plan lives on {self.plan_dev.device}, the current stream "
+                             f"on device {dev}")
+        check(_lib.lib().blaz_matmul_group_run(_ptr(self.plan_dev), ctypes.byref(self.info), stream),
+              "blaz_matmul_group_run")
+
+
 class BatchPlan:
     """A validated batch resident on the device; ``run()`` enqueues it."""
 

@@ -204,12 +204,13 @@ static bool matmul_fits_dispatch(int64_t m, int64_t n, int64_t k, bool b_compres
 
 // The library's tile choice: the 128 tile once it gives every compute unit a
 // workgroup, the 64 tile (four times as many workgroups) below that.
-static int default_gemm_tile(int64_t m, int64_t n)
+int blaz::detail::default_gemm_tile(int64_t m, int64_t n)
 {
     const int64_t tiles128 = ((m + 127) / 128) * ((n + 127) / 128);
     const int cus = blaz::detail::device_cu_count();
     return tiles128 >= (cus > 0 ? cus : 256) ? 128 : 64;
 }
+using blaz::detail::default_gemm_tile;
 
 static blaz_status matmul_impl(const blaz_matrix* a, const blaz_matrix* b, const double* bdense, int64_t n,
                                int64_t ldb, double* c, int64_t ldc, blaz_precision prec, void* workspace,

@@ -10,6 +10,35 @@
 #include "libblaz.h"
 
 namespace blaz {
+
+// One product of a grouped binary64 contraction (device image): C (M x N,
+// ldc) = A (M x K, lda) B (K x N, ldb), row-major binary64, owning the
+// workgroups tile0 .. tile0 + tiles - 1 of the launch (tile0 a multiple of 8).
+struct GemmGroupItem {
+    const double* A;
+    int64_t lda;
+    const double* B;
+    int64_t ldb;
+    double* C;
+    int64_t ldc;
+    int64_t M, N, K;
+    int64_t tile0;
+};
+
+// One matrix of a grouped rebuild (device image): its blocks decompressed
+// into out (leading dimension ld), by the waves wave0 .. wave0 + ceil(nblk /
+// 64) - 1 of the launch.
+struct RebuildJob {
+    const double* f;
+    const double* s;
+    const uint8_t* phi;
+    const uint32_t* codes;
+    int64_t nbc, nblk;
+    double* out;
+    int64_t ld;
+    int64_t wave0;
+};
+
 namespace detail {
 
 // Calls f(std::integral_constant<int, L>) for the kept lines L of a
@@ -32,6 +61,9 @@ inline hipError_t dispatch_lines(const blaz_matrix& m, F&& f)
 
 // Compute units of the current device (cached per device; 0 on error).
 int device_cu_count();
+// blaz_matmul's output tile for an m x n product (128 once that gives every
+// compute unit a workgroup, else 64).
+int default_gemm_tile(int64_t m, int64_t n);
 
 hipError_t launch_compress_f64(const double* A, int64_t lda, const blaz_matrix& m, uint8_t* psi, hipStream_t st);
 // Compression whose transform takes the predicted slopes (two kept lines).
@@ -66,6 +98,13 @@ hipError_t launch_dot_dense(const blaz_matrix& x, const int64_t* xrow, const dou
 // tile: 64 or 128 (the output tile of one workgroup).
 hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                            int64_t m, int64_t n, int64_t k, int tile, hipStream_t st);
+// Grouped binary64 products: workgroups = the last item's tile0 plus its
+// tiles; tile 64 or 128 for every item of the launch.
+hipError_t launch_gemm_group(const GemmGroupItem* items, int n_items, int64_t workgroups, int tile, hipStream_t st);
+// Grouped rebuild of the operands of grouped products (two kept lines,
+// 16-byte aligned rows with an even ld): waves = the last job's wave0 plus
+// its waves.
+hipError_t launch_rebuild_group(const RebuildJob* jobs, int n_jobs, int64_t waves, hipStream_t st);
 // The same product with FP32 operands on FP32 MFMA (FP32 accumulation):
 // A (m x k, lda) k-contiguous, B^T (n x k) in the blocked form of
 // launch_convert_f32_blocked.  k a multiple of 4, lda too.

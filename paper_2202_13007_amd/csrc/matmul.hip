@@ -83,12 +83,13 @@ struct Mfma16x16x4<double> {
     __device__ static int row(int g, int r) { return 4 * r + g; }
 };
 
-// C = A B with A (M x K, lda) and B (K x N, ldb) row-major binary64; C
-// binary64.  LDS rows hold kBM + kPadA64 (A) and kBN + kPadB64 (B) elements.
+// Output tile (tm, tn) of C = A B with A (M x K, lda) and B (K x N, ldb)
+// row-major binary64; C binary64.  Run by one 256-thread workgroup.  LDS
+// rows hold kBM + kPadA64 (A) and kBN + kPadB64 (B) elements.
 template <typename T, int kBM>
-__global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
-                                                   int64_t ldb, double* __restrict__ C, int64_t ldc, int64_t M,
-                                                   int64_t N, int64_t K)
+__device__ __forceinline__ void gemm_tile(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
+                                          double* __restrict__ C, int64_t ldc, int64_t M, int64_t N, int64_t K,
+                                          int tm, int tn)
 {
     using MF = Mfma16x16x4<T>;
     using acc_t = typename MF::acc_t;
@@ -106,10 +107,6 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
     __shared__ __align__(16) T Bs[2][BK][kBN + kPadB64];  // 16-byte row stores
     static_assert((kBN + kPadB64) * sizeof(T) % 16 == 0, "B rows keep 16-byte alignment");
 
-    const int ntm = (int)((M + kBM - 1) / kBM);
-    const int ntn = (int)((N + kBN - 1) / kBN);
-    int tm, tn;
-    tile_of(blockIdx.x, gridDim.x, ntm, ntn, tm, tn);
     const int64_t row0 = (int64_t)tm * kBM, col0 = (int64_t)tn * kBN;
 
     const int tid = threadIdx.x;
@@ -191,6 +188,43 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int6
                 if (gr < M && gc < N) C[gr * ldc + gc] = (double)acc[i][j][r];
             }
         }
+}
+
+template <typename T, int kBM>
+__global__ __launch_bounds__(256) void gemm_kernel(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+                                                   int64_t ldb, double* __restrict__ C, int64_t ldc, int64_t M,
+                                                   int64_t N, int64_t K)
+{
+    const int ntm = (int)((M + kBM - 1) / kBM);
+    const int ntn = (int)((N + kBM - 1) / kBM);
+    int tm, tn;
+    tile_of(blockIdx.x, gridDim.x, ntm, ntn, tm, tn);
+    gemm_tile<T, kBM>(A, lda, B, ldb, C, ldc, M, N, K, tm, tn);
+}
+
+// Many binary64 products in one launch: product p owns the workgroups
+// tile0 .. tile0 + ntm * ntn - 1, tile0 a multiple of 8, so that the
+// XCD-aware tile order of each product is the standalone kernel's (the
+// workgroups between two products exit at once).  A workgroup finds its
+// product by binary search over tile0.
+template <int kBM>
+__global__ __launch_bounds__(256) void gemm_group_kernel(const GemmGroupItem* __restrict__ items, int n_items)
+{
+    const int64_t wg = blockIdx.x;
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].tile0 <= wg) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmGroupItem it = items[lo];
+    const int ntm = (int)((it.M + kBM - 1) / kBM);
+    const int ntn = (int)((it.N + kBM - 1) / kBM);
+    const int64_t local = wg - it.tile0;
+    if (local >= (int64_t)ntm * ntn) return;  // padding up to the next product's multiple of 8
+    int tm, tn;
+    tile_of((int)local, ntm * ntn, ntm, ntn, tm, tn);
+    gemm_tile<double, kBM>(it.A, it.lda, it.B, it.ldb, it.C, it.ldc, it.M, it.N, it.K, tm, tn);
 }
 
 // FP32: A (M x K, lda) with k contiguous and B^T (N x K) in blocked form:
@@ -656,6 +690,16 @@ hipError_t launch_gemm_f64(const double* A, int64_t lda, const double* B, int64_
         gemm_kernel<double, 64><<<gemm_grid(m, n, 64), 256, 0, st>>>(A, lda, B, ldb, C, ldc, m, n, k);
     else
         gemm_kernel<double, 128><<<gemm_grid(m, n, 128), 256, 0, st>>>(A, lda, B, ldb, C, ldc, m, n, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_group(const GemmGroupItem* items, int n_items, int64_t workgroups, int tile, hipStream_t st)
+{
+    if (n_items == 0 || workgroups == 0) return hipSuccess;
+    if (tile == 64)
+        gemm_group_kernel<64><<<(unsigned)workgroups, 256, 0, st>>>(items, n_items);
+    else
+        gemm_group_kernel<128><<<(unsigned)workgroups, 256, 0, st>>>(items, n_items);
     return hipGetLastError();
 }
 

@@ -12,8 +12,10 @@ device (and, for compress, dense matrices resident in HBM).  Two forms:
   one batch -- one persistent launch over a flat chunk queue -- on one
   stream, and launches the admitted matmuls on a few more streams (those
   that fill the GPU alone in order on one of them, the small ones
-  round-robin on the others), so the batch and the contractions overlap on
-  the device.  Ticks do not wait for each other: up
+  round-robin on the others; with ``group_products`` and binary64
+  contractions the tick's products of side <= 512 form one group -- one
+  rebuild launch and one contraction launch per tile class for all of them),
+  so the batch and the contractions overlap on the device.  Ticks do not wait for each other: up
   to ``max_inflight`` ticks run at once, and requests arriving meanwhile are
   admitted into the next tick as memory frees up.  The matmul contraction
   may run in FP64, FP32 or BF16x3 (``matmul_prec``).
@@ -100,8 +102,10 @@ def fp64_equiv_bytes(op: str, n: int) -> int:
 
 class Server:
     def __init__(self, pool: OperandPool, hbm_budget: int = 16 << 30, matmul_prec: str = "fp64",
-                 max_inflight: int = 4, tuner=None, keep_results: bool = False, matmul_streams: int = 4):
+                 max_inflight: int = 4, tuner=None, keep_results: bool = False, matmul_streams: int = 4,
+                 group_products: bool = False):
         self.pool = pool
+        self.group_products = group_products
         self.budget = int(hbm_budget)
         self.matmul_prec = matmul_prec
         self.max_inflight = max_inflight
@@ -263,6 +267,22 @@ class Server:
                 ev = torch.cuda.Event(enable_timing=True)
                 ev.record(self.s_block)
             units.append((ev, blocks, [plan]))
+        tiny = [r for r in mms if r.n <= self.GROUP_MAX_SIDE]
+        if self.group_products and self.matmul_prec == "fp64" and len(tiny) > 1:
+            # the tick's small binary64 products as one group: one rebuild
+            # launch and one contraction launch per tile class for all of them
+            grp = api.MatmulGroup()
+            for r in tiny:
+                grp.add(self.pool.x[r.n], self.pool.y[r.n], r.result)
+            st = self.s_mm[1 + self._next_mm % (len(self.s_mm) - 1)]
+            self._next_mm += 1
+            with torch.cuda.stream(st):
+                plan = grp.plan(workspace=self._group_workspace(tiny))
+                plan.run()
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record(st)
+            units.append((ev, tiny, [plan]))
+            mms = [r for r in mms if r.n > self.GROUP_MAX_SIDE]
         for r in mms:
             if ((r.n + 127) // 128) ** 2 >= self.cus:
                 st = self.s_mm[0]
@@ -275,6 +295,18 @@ class Server:
                 ev.record(st)
             units.append((ev, [r], []))
         return units
+
+    GROUP_MAX_SIDE = 512  # products grouped per tick: those whose launch costs more than their work
+
+    @staticmethod
+    def _group_workspace(reqs):
+        """The group's rebuilt operands live in the workspaces the requests
+        were admitted with; one tensor of their summed size (each request's
+        workspace is at least its rebuilds' size) is taken for the group."""
+        need = sum(api.matmul_workspace_bytes(r.n, r.n, r.n, True, "fp64") for r in reqs)
+        for r in reqs:
+            r._hold.clear()
+        return torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
 
     def _report(self, requests, mode, ticks) -> dict:
         lat = np.array([(r.done - r.arrival) * 1e3 for r in requests])

@@ -118,12 +118,13 @@ class OracleOperands:
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
-def test_results_same_alone_and_in_the_mix(prec):
+@pytest.mark.parametrize("prec,group", [("fp64", False), ("fp64", True), ("bf16x3", False)])
+def test_results_same_alone_and_in_the_mix(prec, group):
     """Every request of a 300-request mix (sides 8..512, arriving faster than
     they are served, so ticks batch many of them and the batch and the
-    contractions overlap) matches the oracle under the parity rules, and
-    equals the same request run alone bit for bit."""
+    contractions overlap; with `group` each tick's products run as one
+    grouped launch) matches the oracle under the parity rules, and equals
+    the same request run alone bit for bit."""
     import torch
     from paper_2202_13007_amd.serve import OperandPool, Server
     from paper_2202_13007_amd.tune import Autotuner
@@ -131,7 +132,8 @@ def test_results_same_alone_and_in_the_mix(prec):
     reqs = make_requests(300, rate=20000.0, seed=11, n_min=8, n_max=512)
     pool = OperandPool(A, B, [r.n for r in reqs])
     orc = OracleOperands(pool, [r.n for r in reqs])
-    srv = Server(pool, hbm_budget=1 << 30, matmul_prec=prec, tuner=Autotuner(path=None), keep_results=True)
+    srv = Server(pool, hbm_budget=1 << 30, matmul_prec=prec, tuner=Autotuner(path=None), keep_results=True,
+                 group_products=group)
     srv.prepare(reqs)
     rep = srv.run(reqs, "batched")
     assert rep["requests"] == 300 and rep["ticks"] < 300  # requests were batched together
