@@ -112,7 +112,9 @@ __global__ __launch_bounds__(kWave, 2) void compress_mixed_kernel(const double* 
             dacc[G] = d;
         }
     } else {
-        // Delta' = hi + lo, hi = bf16(Delta'), lo = bf16(Delta' - hi)
+        // Delta' = hi + lo, hi = bf16(Delta'), lo = bf16(Delta' - hi), split in
+        // FP32 (Delta' - hi is exact there; |Delta' - hi - lo| <= (2^-16 +
+        // 2^-24) |Delta'|)
         __bf16* sh = reinterpret_cast<__bf16*>(smem);
         __bf16* sl = sh + 64 * kPitchH;
         __syncthreads();  // the row staging is done with the buffer
@@ -121,12 +123,12 @@ __global__ __launch_bounds__(kWave, 2) void compress_mixed_kernel(const double* 
             bf16x8 h, l;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const double xv = x[8 * u + q];
-                const __bf16 hq = (__bf16)(float)xv;
+                const float xv = (float)x[8 * u + q];
+                const __bf16 hq = (__bf16)xv;
                 // slot of value q: its half q / 4 lands in position (q / 4) ^ ((u >> 1) & 1)
                 const int pos = 4 * ((q >> 2) ^ ((u >> 1) & 1)) + (q & 3);
                 h[pos] = hq;
-                l[pos] = (__bf16)(float)(xv - (double)(float)hq);
+                l[pos] = (__bf16)(xv - (float)hq);
             }
             *reinterpret_cast<bf16x8*>(&sh[lane * kPitchH + 8 * u]) = h;
             *reinterpret_cast<bf16x8*>(&sl[lane * kPitchH + 8 * u]) = l;

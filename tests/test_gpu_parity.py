@@ -692,8 +692,9 @@ def test_matmul_full_size_4096_sampled():
 # and |T| |R| <= |T| |Delta'| |T|^T, so the two passes' relative bounds add:
 # FP32: operand rounding (Delta', T: 2 u32) and the 8-term FP32 sums of
 # each pass, within 66 u32; BF16x3: each pass 3 * 2^-16 (the split of both
-# operands and the dropped lo * lo product), plus 2^-16 for the split of R
-# into hi + lo between the passes, plus the FP32 sums.
+# operands, done in FP32, and the dropped lo * lo product), plus 2^-16 for
+# the split of R into hi + lo between the passes, plus the FP32 roundings
+# and sums.
 MIXED_EPS = {"fp32": 66 * 2.0 ** -24, "bf16x3": 7 * 2.0 ** -16 + 66 * 2.0 ** -24}
 D_ERR = {k: v * 63 / 4 for k, v in MIXED_EPS.items()}
 
