@@ -351,10 +351,12 @@ blaz_status blaz_batch_plan(const blaz_batch_item *items, int64_t n_items, void 
  * aligned).  counter: 8 bytes of device memory owned by the caller, reset
  * by the run itself; concurrent runs need distinct counters.  workgroups:
  * number of persistent workgroups (one wave each); 0 picks 8 per compute
- * unit of the current device.  n_plan and total_chunks as returned by
- * blaz_batch_plan. */
+ * unit of the current device.  chunks_per_claim: consecutive chunks a wave
+ * takes per pop of the counter, 1..64 (0 means 1): fewer atomics against
+ * coarser load balance; results do not depend on it.  n_plan and
+ * total_chunks as returned by blaz_batch_plan. */
 blaz_status blaz_batch_run(const void *plan_dev, int64_t n_plan, int64_t total_chunks, uint64_t *counter,
-                           int64_t workgroups, hipStream_t stream);
+                           int64_t workgroups, int32_t chunks_per_claim, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Grouped products: many binary64 matrix multiplications (last paragraph of

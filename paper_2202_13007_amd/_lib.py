@@ -143,7 +143,7 @@ def lib():
         "blaz_status_string": ([I], ctypes.c_char_p),
         "blaz_batch_plan_bytes": ([I64], ctypes.c_size_t),
         "blaz_batch_plan": ([P, I64, P, ctypes.c_size_t, P, P], I),
-        "blaz_batch_run": ([P, I64, I64, P, I64, P], I),
+        "blaz_batch_run": ([P, I64, I64, P, I64, ctypes.c_int32, P], I),
         "blaz_matmul_group_plan_bytes": ([I64], ctypes.c_size_t),
         "blaz_matmul_group_plan": ([P, I64, P, ctypes.c_size_t, P, ctypes.c_size_t, P], I),
         "blaz_matmul_group_run": ([P, P, P], I),

@@ -531,10 +531,10 @@ class BatchPlan:
         self.counter = counter
         self._keep = keep
 
-    def run(self, workgroups: int = 0):
+    def run(self, workgroups: int = 0, chunks_per_claim: int = 0):
         stream, dev = _stream_dev()
         if not _on_device(self.plan_dev, dev):
             raise ValueError(f"BatchPlan.run: the plan lives on {self.plan_dev.device}, the current stream on "
                              f"device {dev}")
         check(_lib.lib().blaz_batch_run(_ptr(self.plan_dev), self.n_plan, self.total_chunks, _ptr(self.counter),
-                                        int(workgroups), stream), "blaz_batch_run")
+                                        int(workgroups), int(chunks_per_claim), stream), "blaz_batch_run")

@@ -68,15 +68,20 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t v)
 }
 
 __global__ __launch_bounds__(kWave, 2) void batch_kernel(const BatchItemDev* __restrict__ items, int32_t n_items,
-                                                         int64_t total, unsigned long long* __restrict__ counter)
+                                                         int64_t total, unsigned long long* __restrict__ counter,
+                                                         int32_t per_claim)
 {
     __shared__ __align__(16) double tile[kWave * kSlot];
     const int lane = threadIdx.x;
+    int64_t chunk = 0, claim_end = 0;
     for (;;) {
         __syncthreads();  // the previous chunk is done with the LDS tile
-        unsigned long long got = 0;
-        if (lane == 0) got = atomicAdd(counter, 1ull);
-        const int64_t chunk = wave_uniform((int64_t)got);
+        if (chunk >= claim_end) {  // claim the next per_claim consecutive chunks
+            unsigned long long got = 0;
+            if (lane == 0) got = atomicAdd(counter, (unsigned long long)per_claim);
+            chunk = wave_uniform((int64_t)got);
+            claim_end = chunk + per_claim;
+        }
         if (chunk >= total) return;
         // last item whose first chunk is <= chunk
         int lo = 0, hi = n_items - 1;
@@ -120,6 +125,7 @@ __global__ __launch_bounds__(kWave, 2) void batch_kernel(const BatchItemDev* __r
                                          it.nbr_x, it.nbc, it.xrow, it.dense, it.ld, it.out);
                 break;
         }
+        ++chunk;
     }
 }
 
@@ -248,9 +254,11 @@ BLAZ_API blaz_status blaz_batch_plan(const blaz_batch_item* items, int64_t n_ite
 }
 
 BLAZ_API blaz_status blaz_batch_run(const void* plan_dev, int64_t n_plan, int64_t total_chunks, uint64_t* counter,
-                                    int64_t workgroups, hipStream_t stream)
+                                    int64_t workgroups, int32_t chunks_per_claim, hipStream_t stream)
 {
     if (n_plan < 0 || total_chunks < 0 || workgroups < 0 || n_plan > (int64_t(1) << 30)) return BLAZ_ERR_ARG;
+    if (chunks_per_claim < 0 || chunks_per_claim > 64) return BLAZ_ERR_ARG;
+    if (chunks_per_claim == 0) chunks_per_claim = 1;
     if (n_plan == 0 || total_chunks == 0) return BLAZ_OK;
     if (!plan_dev || !counter) return BLAZ_ERR_NULL;
     if (!aligned(plan_dev, 8) || !aligned(counter, 8)) return BLAZ_ERR_ALIGN;
@@ -265,6 +273,6 @@ BLAZ_API blaz_status blaz_batch_run(const void* plan_dev, int64_t n_plan, int64_
     batch_reset_kernel<<<1, 1, 0, stream>>>(cnt);
     if (hipGetLastError() != hipSuccess) return BLAZ_ERR_HIP;
     batch_kernel<<<(unsigned)workgroups, kWave, 0, stream>>>(static_cast<const BatchItemDev*>(plan_dev),
-                                                             (int32_t)n_plan, total_chunks, cnt);
+                                                             (int32_t)n_plan, total_chunks, cnt, chunks_per_claim);
     return hipGetLastError() == hipSuccess ? BLAZ_OK : BLAZ_ERR_HIP;
 }

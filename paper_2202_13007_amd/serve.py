@@ -167,7 +167,7 @@ class Server:
         for n in sorted({r.n for r in requests if r.op == "matmul"}):
             self.tuner.matmul_tile(n, n, n, self.matmul_prec, True)
         for c in range(0, 15):
-            self.tuner.batch_workgroups(1 << c)
+            self.tuner.batch_launch(1 << c)
 
     def run(self, requests: list[Request], mode: str = "batched") -> dict:
         assert mode in ("plain", "batched")
@@ -262,8 +262,8 @@ class Server:
                 self._add_to_batch(batch, r)
             with torch.cuda.stream(self.s_block):
                 plan = batch.plan()
-                wg = self.tuner.batch_workgroups(plan.total_chunks) if self.tuner else 0
-                plan.run(wg)
+                wg, claim = self.tuner.batch_launch(plan.total_chunks) if self.tuner else (0, 0)
+                plan.run(wg, claim)
                 ev = torch.cuda.Event(enable_timing=True)
                 ev.record(self.s_block)
             units.append((ev, blocks, [plan]))

@@ -1,16 +1,19 @@
 """Autotuner for the launch shapes the library exposes.
 
-Two knobs are tuned by timing the candidates on the device and caching the
+Three knobs are tuned by timing the candidates on the device and caching the
 winner per (GPU architecture, operation, size class) in a JSON file:
 
 * the output tile of the matmul contraction (``blaz_matmul_tiled``: 64 or
   128), per precision, B form and size class (powers of two of m*n and k);
-* the number of persistent workgroups of a batch run (``blaz_batch_run``),
-  per size class of the work queue (powers of two of the chunk count).
+* the number of persistent workgroups of a batch run (``blaz_batch_run``)
+  and, jointly with it,
+* the chunks a wave claims per pop of the work counter (1, 2 or 4, i.e.
+  64, 128 or 256 blocks per claim), both per size class of the work queue
+  (powers of two of the chunk count).
 
 Every candidate computes the same result (the tile does not change the
-summation order; the grid only changes which workgroup takes which chunk),
-so tuning never changes numbers, only time.
+summation order; the grid and the claim size only change which workgroup
+takes which chunk), so tuning never changes numbers, only time.
 """
 from __future__ import annotations
 
@@ -35,6 +38,7 @@ class Autotuner:
 
     MATMUL_TILES = (64, 128)
     WG_PER_CU = (2, 4, 8, 16)
+    CHUNKS_PER_CLAIM = (1, 2, 4)
 
     def __init__(self, path: str | None = _DEFAULT_PATH, reps: int = 3):
         self.path = path
@@ -103,22 +107,28 @@ class Autotuner:
     def batch_key(self, total_chunks: int) -> str:
         return f"{self.arch}|batch|chunks{_pow2_class(total_chunks)}"
 
-    def batch_workgroups(self, total_chunks: int) -> int:
-        """Workgroups for a batch run whose queue holds total_chunks chunks,
-        tuned on a synthetic batch of that size class (compressions of a
-        random matrix, one 64-block chunk per block row of 512 columns)."""
+    def batch_launch(self, total_chunks: int) -> tuple[int, int]:
+        """(workgroups, chunks per claim) for a batch run whose queue holds
+        total_chunks chunks, tuned jointly on a synthetic batch of that size
+        class (compressions of a random matrix, one 64-block chunk per block
+        row of 512 columns)."""
         key = self.batch_key(total_chunks)
         with self._lock:
-            if key in self.cache:
-                return self.cache[key]
+            if key + "|wg" in self.cache and key + "|claim" in self.cache:
+                return self.cache[key + "|wg"], self.cache[key + "|claim"]
         chunks = min(1 << _pow2_class(max(total_chunks, 1)), 1 << 14)
         dev = torch.device("cuda")
         dense = torch.randn((8 * chunks, 512), dtype=torch.float64, device=dev)
         out = api.BlazMatrix.empty(8 * chunks, 512, dev)
         plan = api.Batch().compress(dense, out).plan(dev)
-        times = {w * self.cus: self._time(lambda w=w: plan.run(w * self.cus)) for w in self.WG_PER_CU}
+        times = {(w * self.cus, c): self._time(lambda w=w, c=c: plan.run(w * self.cus, c))
+                 for w in self.WG_PER_CU for c in self.CHUNKS_PER_CLAIM}
         best = min(times, key=times.get)
         with self._lock:
-            self.cache[key] = best
+            self.cache[key + "|wg"], self.cache[key + "|claim"] = best
             self._save()
         return best
+
+    def batch_workgroups(self, total_chunks: int) -> int:
+        """The tuned workgroup count alone (see batch_launch)."""
+        return self.batch_launch(total_chunks)[0]

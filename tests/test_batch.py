@@ -97,6 +97,14 @@ def test_plan_rejects_other_rates():
     assert st == -6 and n_plan == 0
 
 
+@pytest.mark.parametrize("claim", [-1, 65])
+def test_run_rejects_claim_size_out_of_range(claim):
+    """chunks_per_claim is 1..64 (0 means 1); anything else is refused before
+    the counter reset or the kernel is enqueued."""
+    st = _lib().lib().blaz_batch_run(0x1000000, 1, 10, 0x2000000, 4, claim, None)
+    assert st == -5
+
+
 def test_plan_rejects_partial_overlap():
     x = fake_matrix(8, 64, 0x2000000)
     z = fake_matrix(8, 64, 0x2000000 + 8)
@@ -233,13 +241,13 @@ def clear(a):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("workgroups", [0, 1, 7, 100000])
-def test_batch_matches_standalone(workgroups):
+@pytest.mark.parametrize("workgroups,claim", [(0, 0), (1, 1), (7, 3), (100000, 1), (13, 64)])
+def test_batch_matches_standalone(workgroups, claim):
     import torch
     import paper_2202_13007_amd as blaz
     B, expect = make_workload(torch, blaz)
     P = B.plan()
-    P.run(workgroups)
+    P.run(workgroups, claim)
     torch.cuda.synchronize()
     for got, want, check in expect:
         check(got)
