@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=768, help="rows of each field the oracle times")
     ap.add_argument("--serve-requests", type=int, default=20000, help="requests of the serving mix (0 skips it)")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="HBM budget of the serving loop")
+    ap.add_argument("--serve-step", default="resident", choices=("fresh", "resident", "graph"),
+                    help="form of the batched serving loop's request step: a fresh plan, a resident plan buffer "
+                         "and one launch, or a resident buffer and a graph replay")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 64x64 latency, cold-cache, tunable-rate and 16384x16384 mixed-precision legs")
     ap.add_argument("--only", default="",
@@ -523,7 +526,54 @@ def mixed_leg(blaz, torch, workload_inputs, reps=10):
     return res
 
 
-def serving_leg(torch, dA, dB, count, budget_gib, loads=(0.5, 0.8, 1.2)):
+def request_step_cost(torch, pool, ticks=400):
+    """Host-inclusive cost of one tick's block-level request step, for a
+    tick of one small request (scale of the smallest resident operand): a
+    fresh plan (pinned staging, plan copy, counter fill, reset and batch
+    kernels); a copy into a resident plan buffer plus one replay of the
+    graph captured for it; the same copy plus the resident run launched
+    directly (one kernel).  Four rotating outputs and buffers, one stream,
+    synchronized at the end; the second of two passes counts."""
+    import time
+    from paper_2202_13007_amd import api
+    n = min(pool.x)
+    x = pool.x[n]
+    outs = [api.BlazMatrix.empty(n, n) for _ in range(4)]
+    slots = [api.ResidentBatch(16) for _ in range(4)]
+
+    def fresh(i):
+        api.Batch().scale(x, 1.7, outs[i % 4]).plan().run()
+
+    def replay(i):
+        rb = slots[i % 4]
+        rb.load(api.Batch().scale(x, 1.7, outs[i % 4]))
+        rb.graph(1, 1).replay()  # one chunk: one workgroup, as the fresh plan's run trims it
+
+    def direct(i):
+        rb = slots[i % 4]
+        rb.load(api.Batch().scale(x, 1.7, outs[i % 4]))
+        rb.run(1, 1)
+
+    s = torch.cuda.Stream()
+    res = {}
+    with torch.cuda.stream(s):
+        for rb in slots:
+            rb.graph(1, 1)
+        for name, f in (("fresh_plan_us", fresh), ("graph_replay_us", replay), ("resident_launch_us", direct)) * 2:
+            for i in range(20):
+                f(i)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(ticks):
+                f(i)
+            torch.cuda.synchronize()
+            res[name] = round((time.perf_counter() - t0) / ticks * 1e6, 2)
+    res["side"] = n
+    res["note"] = "host-inclusive time per tick over a stream of one-request ticks"
+    return res
+
+
+def serving_leg(torch, dA, dB, count, budget_gib, loads=(0.5, 0.8, 1.2), step="resident"):
     """The serving mix: `count` requests (compress 30%, add 25%, scale 15%,
     dot 15%, matmul 15%), sides log-uniform in [64, 8192], on the two 8192^2
     fields (each side n uses their n x n corners).  The plain form's capacity
@@ -531,7 +581,8 @@ def serving_leg(torch, dA, dB, count, budget_gib, loads=(0.5, 0.8, 1.2)):
     the Poisson stream then arrives at 0.5x, 0.8x and 1.2x that rate and is
     served in the plain form, batched with FP64 matmuls (standalone, and
     with each tick's products of side <= 512 as one group), and batched with
-    BF16x3 matmuls."""
+    BF16x3 matmuls; `step` is the batched forms' request-step form (see
+    paper_2202_13007_amd.serve)."""
     from paper_2202_13007_amd.serve import OperandPool, Server, make_requests
     from paper_2202_13007_amd.tune import Autotuner
 
@@ -543,10 +594,11 @@ def serving_leg(torch, dA, dB, count, budget_gib, loads=(0.5, 0.8, 1.2)):
     budget = int(budget_gib * (1 << 30))
     out = {"requests": count, "hbm_budget_GiB": budget_gib, "mix": "compress .30 add .25 scale .15 dot .15 matmul .15",
            "sides": "log-uniform in [64, 8192], multiples of 8"}
+    out["request_step_form"] = step
     servers = {"plain": Server(pool, budget, "fp64", tuner=tuner),
-               "batched_fp64": Server(pool, budget, "fp64", tuner=tuner),
-               "batched_fp64_grouped": Server(pool, budget, "fp64", tuner=tuner, group_products=True),
-               "batched_bf16x3": Server(pool, budget, "bf16x3", tuner=tuner)}
+               "batched_fp64": Server(pool, budget, "fp64", tuner=tuner, step=step),
+               "batched_fp64_grouped": Server(pool, budget, "fp64", tuner=tuner, group_products=True, step=step),
+               "batched_bf16x3": Server(pool, budget, "bf16x3", tuner=tuner, step=step)}
     for srv in servers.values():
         srv.prepare(calib)
     # warm-up and capacity (everything arrives at t = 0)
@@ -554,9 +606,10 @@ def serving_leg(torch, dA, dB, count, budget_gib, loads=(0.5, 0.8, 1.2)):
     for name, srv in servers.items():
         mode = "plain" if name == "plain" else "batched"
         srv.run(make_requests(200, rate=0.0, seed=503), mode)  # warm-up (same sides as `warm`)
-        # the first full-size run after the warm-up still pays first-use costs
-        # (up to 6 % in the batched forms): two runs, the better one counts
-        cap[name] = max(srv.run(make_requests(len(calib), rate=0.0, seed=502), mode)["req_per_s"] for _ in range(2))
+        # a capacity run is a handful of ticks, whose composition and timing
+        # vary from run to run, and the first full-size run after the warm-up
+        # still pays first-use costs: three runs, the best one counts
+        cap[name] = max(srv.run(make_requests(len(calib), rate=0.0, seed=502), mode)["req_per_s"] for _ in range(3))
     out["capacity_req_per_s"] = {k: round(v, 1) for k, v in cap.items()}
     out["capacity_speedup_vs_plain"] = {k: round(v / cap["plain"], 3) for k, v in cap.items()}
     # How much of the plain form's device time the binary64 products take:
@@ -571,6 +624,7 @@ def serving_leg(torch, dA, dB, count, budget_gib, loads=(0.5, 0.8, 1.2)):
         "matmul_requests": len(mm), "matmul_only_s": round(t_mm, 4), "all_requests_s": round(t_all, 4),
         "share": round(t_mm / t_all, 4), "max_gain_from_overlap": round(t_all / t_mm, 4),
         "note": "the calibration set's binary64 products alone in the plain form, against the whole set"}
+    out["request_step"] = request_step_cost(torch, pool)
     out["runs"] = {}
     for load in loads:
         rate = load * cap["plain"]
@@ -873,7 +927,8 @@ def main():
         print("# transform-input leg", file=sys.stderr, flush=True)
         result["transform_input_8192"] = transform_input_leg(blaz, torch, dA)
     if "serving" in legs:
-        result["serving"] = serving_leg(torch, dA, dB, args.serve_requests, args.serve_budget_gib)
+        result["serving"] = serving_leg(torch, dA, dB, args.serve_requests, args.serve_budget_gib,
+                                        step=args.serve_step)
     del dA, dB
 
     if "latency" in legs:

@@ -358,6 +358,33 @@ blaz_status blaz_batch_plan(const blaz_batch_item *items, int64_t n_items, void 
 blaz_status blaz_batch_run(const void *plan_dev, int64_t n_plan, int64_t total_chunks, uint64_t *counter,
                            int64_t workgroups, int32_t chunks_per_claim, hipStream_t stream);
 
+/* Run state of a resident plan buffer (device memory, 8-byte aligned). */
+typedef struct blaz_batch_state {
+    int64_t n_plan;        /* written by the caller: blaz_batch_plan's *n_plan         */
+    int64_t total_chunks;  /* written by the caller: blaz_batch_plan's *total_chunks   */
+    uint64_t counter;      /* work counter: 0 before a run, and 0 again after it       */
+    int64_t status;        /* written by each run: BLAZ_OK, or BLAZ_ERR_ARG when the   */
+                           /* counts are out of range (then the run does nothing else) */
+} blaz_batch_state;
+
+/* Run whatever plan was last copied into plan_dev, reading its counts from
+ * *state when the launch executes rather than when it is enqueued, so that
+ * one captured HIP graph of this call replays every later plan that is
+ * copied into the same buffers (a serving loop's request steps).  plan_dev:
+ * device buffer of `capacity` planned items (blaz_batch_plan_bytes(capacity)
+ * bytes, 8-byte aligned), 1 <= capacity <= 2^30; the caller copies a plan
+ * image and the whole state record (counter 0) stream-ordered before a
+ * run.  The run is one kernel launch and no memset or copy: the wave that
+ * makes its last claim resets the counter, so a plan can also be run again
+ * without a new copy.  Counts with n_plan or total_chunks negative, n_plan
+ * above capacity, or chunks without items are rejected on the device:
+ * status becomes BLAZ_ERR_ARG and no item runs.  workgroups and
+ * chunks_per_claim as blaz_batch_run (the grid is not trimmed to the chunk
+ * count, which is unknown at enqueue time: waves with no chunk left exit at
+ * once).  Concurrent runs need distinct states and plan buffers. */
+blaz_status blaz_batch_run_resident(const void *plan_dev, int64_t capacity, blaz_batch_state *state,
+                                    int64_t workgroups, int32_t chunks_per_claim, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Grouped products: many binary64 matrix multiplications (last paragraph of
  * Section "Basic Linear Algebra Algorithms": every block rebuilt once, then

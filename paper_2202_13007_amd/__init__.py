@@ -4,7 +4,7 @@ The library itself is the C ABI in include/libblaz.h, implemented by the HIP
 kernels under csrc/ and built into libblaz.so.  This package is its thin
 Python binding (``api``) and the build script (``_build``).
 """
-from .api import (DIAGNOSE_FIELDS, Batch, BatchPlan, BlazMatrix, MatmulGroup, MatmulGroupPlan, add, code_stride, compress,  # noqa: F401
+from .api import (DIAGNOSE_FIELDS, Batch, BatchPlan, BlazMatrix, MatmulGroup, MatmulGroupPlan, ResidentBatch, add, code_stride, compress,  # noqa: F401
                   compress_predicted, decompress,
                   diagnose, dot, dot_dense,
                   matmul, matmul_compressed, matmul_compressed_workspace_bytes, matmul_static,

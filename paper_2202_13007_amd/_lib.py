@@ -26,6 +26,7 @@ EXPORTS = (
     "blaz_sub", "blaz_scale", "blaz_dot", "blaz_dot_dense", "blaz_matmul_workspace_bytes",
     "blaz_matmul", "blaz_matmul_tiled", "blaz_matmul_static", "blaz_matmul_compressed_workspace_bytes", "blaz_matmul_compressed",
     "blaz_diagnose", "blaz_status_string", "blaz_batch_plan_bytes", "blaz_batch_plan", "blaz_batch_run",
+    "blaz_batch_run_resident",
     "blaz_matmul_group_plan_bytes", "blaz_matmul_group_plan", "blaz_matmul_group_run",
 )
 
@@ -58,6 +59,16 @@ class BatchItemC(ctypes.Structure):
         ("ycol", ctypes.c_void_p),
         ("count", ctypes.c_int64),
         ("out", ctypes.c_void_p),
+    ]
+
+
+class BatchStateC(ctypes.Structure):
+    """Mirror of ``blaz_batch_state``."""
+    _fields_ = [
+        ("n_plan", ctypes.c_int64),
+        ("total_chunks", ctypes.c_int64),
+        ("counter", ctypes.c_uint64),
+        ("status", ctypes.c_int64),
     ]
 
 
@@ -144,6 +155,7 @@ def lib():
         "blaz_batch_plan_bytes": ([I64], ctypes.c_size_t),
         "blaz_batch_plan": ([P, I64, P, ctypes.c_size_t, P, P], I),
         "blaz_batch_run": ([P, I64, I64, P, I64, ctypes.c_int32, P], I),
+        "blaz_batch_run_resident": ([P, I64, P, I64, ctypes.c_int32, P], I),
         "blaz_matmul_group_plan_bytes": ([I64], ctypes.c_size_t),
         "blaz_matmul_group_plan": ([P, I64, P, ctypes.c_size_t, P, ctypes.c_size_t, P], I),
         "blaz_matmul_group_run": ([P, P, P], I),

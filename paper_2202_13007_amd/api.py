@@ -434,21 +434,26 @@ class Batch:
         _check_tensor(out, "batch dot_dense out", torch.float64, count, dev)
         return self._add("dot_dense", x=x, dense=v, ld=ld, xrow=xrow, count=count, out=out)
 
-    def plan(self, device=None) -> "BatchPlan":
+    def _plan_into(self, host_ptr: int, nbytes: int):
+        """Write the plan image into host memory; returns (n_plan, total_chunks)."""
         n = len(self.items)
         arr = (_lib.BatchItemC * max(n, 1))(*self.items)
-        nbytes = int(_lib.lib().blaz_batch_plan_bytes(n))
-        host = torch.empty(max(nbytes, 8), dtype=torch.uint8, pin_memory=torch.cuda.is_available())
         n_plan = ctypes.c_int64()
         total = ctypes.c_int64()
-        st = _lib.lib().blaz_batch_plan(ctypes.cast(arr, ctypes.c_void_p), n, ctypes.c_void_p(host.data_ptr()),
-                                        host.numel(), ctypes.byref(n_plan), ctypes.byref(total))
+        st = _lib.lib().blaz_batch_plan(ctypes.cast(arr, ctypes.c_void_p), n, ctypes.c_void_p(host_ptr), nbytes,
+                                        ctypes.byref(n_plan), ctypes.byref(total))
         if st != _lib.BLAZ_OK:
             raise _lib.BlazError(st, f"blaz_batch_plan (item {n_plan.value})")
+        return n_plan.value, total.value
+
+    def plan(self, device=None) -> "BatchPlan":
+        nbytes = int(_lib.lib().blaz_batch_plan_bytes(len(self.items)))
+        host = torch.empty(max(nbytes, 8), dtype=torch.uint8, pin_memory=torch.cuda.is_available())
+        n_plan, total = self._plan_into(host.data_ptr(), host.numel())
         dev = torch.device("cuda") if device is None else torch.device(device)
         plan_dev = host.to(dev, non_blocking=True)
         counter = torch.zeros(1, dtype=torch.int64, device=dev)
-        return BatchPlan(plan_dev, host, n_plan.value, total.value, counter, list(self._keep))
+        return BatchPlan(plan_dev, host, n_plan, total, counter, list(self._keep))
 
 
 class MatmulGroup:
@@ -538,3 +543,81 @@ class BatchPlan:
                              f"device {dev}")
         check(_lib.lib().blaz_batch_run(_ptr(self.plan_dev), self.n_plan, self.total_chunks, _ptr(self.counter),
                                         int(workgroups), int(chunks_per_claim), stream), "blaz_batch_run")
+
+
+class ResidentBatch:
+    """A plan buffer of ``capacity`` items, its run state and a pinned host
+    staging area, for running successive batches through one captured HIP
+    graph (``blaz_batch_run_resident``).  ``load(batch)`` plans the batch into
+    the staging area and enqueues one copy of the counts and the plan image on
+    the current stream; ``run()``, or a replay of ``graph(...)`` on the same
+    stream, executes the plan loaded last.  Loads and runs on one stream are
+    ordered, so a load never overwrites a plan under an earlier run; a load
+    on another stream must wait for the earlier runs.  ``load`` waits until
+    the previous load's copy has executed before it rewrites the staging
+    area, which on one stream means until the earlier runs are done: rotate
+    several objects to keep the host from waiting."""
+
+    STATE_BYTES = ctypes.sizeof(_lib.BatchStateC)
+
+    def __init__(self, capacity: int, device=None):
+        if capacity < 1:
+            raise ValueError("ResidentBatch: capacity must be at least 1")
+        self.capacity = int(capacity)
+        self.plan_bytes = int(_lib.lib().blaz_batch_plan_bytes(self.capacity))
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        total = self.STATE_BYTES + self.plan_bytes
+        self.host = torch.zeros(total, dtype=torch.uint8, pin_memory=True)
+        self.dev = torch.zeros(total, dtype=torch.uint8, device=dev)
+        self.state = self.dev[:self.STATE_BYTES]
+        self.plan_dev = self.dev[self.STATE_BYTES:]
+        self._state_host = _lib.BatchStateC.from_address(self.host.data_ptr())
+        self._item_bytes = self.plan_bytes // self.capacity
+        self._copied = torch.cuda.Event()
+        self._loaded = False
+        self._graphs = {}
+        self._keep = []
+        self.n_plan = self.total_chunks = 0
+
+    def load(self, batch: Batch):
+        """Plan `batch` and enqueue the copy of its counts and plan image;
+        returns (n_plan, total_chunks)."""
+        if len(batch.items) > self.capacity:
+            raise ValueError(f"ResidentBatch.load: {len(batch.items)} items, capacity {self.capacity}")
+        if self._loaded:
+            self._copied.synchronize()
+        n_plan, total = batch._plan_into(self.host.data_ptr() + self.STATE_BYTES, self.plan_bytes)
+        st = self._state_host
+        st.n_plan, st.total_chunks, st.counter, st.status = n_plan, total, 0, 0
+        used = self.STATE_BYTES + n_plan * self._item_bytes
+        self.dev[:used].copy_(self.host[:used], non_blocking=True)
+        self._copied.record()
+        self._loaded = True
+        self._keep = list(batch._keep)
+        self.n_plan, self.total_chunks = n_plan, total
+        return n_plan, total
+
+    def run(self, workgroups: int = 0, chunks_per_claim: int = 0):
+        stream, dev = _stream_dev()
+        if not _on_device(self.dev, dev):
+            raise ValueError(f"ResidentBatch.run: the buffers live on {self.dev.device}, the current stream on "
+                             f"device {dev}")
+        check(_lib.lib().blaz_batch_run_resident(_ptr(self.plan_dev), self.capacity, _ptr(self.state),
+                                                 int(workgroups), int(chunks_per_claim), stream),
+              "blaz_batch_run_resident")
+
+    def graph(self, workgroups: int = 0, chunks_per_claim: int = 0) -> "torch.cuda.CUDAGraph":
+        """The run captured once per launch shape; replay it on the stream the
+        loads are enqueued on (or one ordered after it)."""
+        key = (int(workgroups), int(chunks_per_claim))
+        g = self._graphs.get(key)
+        if g is None:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                self.run(*key)
+            self._graphs[key] = g
+        return g
+
+    def status(self) -> int:
+        """The status the last executed run wrote (synchronizes)."""
+        return int(self.state.view(torch.int64)[3].item())

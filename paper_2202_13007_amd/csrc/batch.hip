@@ -67,22 +67,22 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t v)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-__global__ __launch_bounds__(kWave, 2) void batch_kernel(const BatchItemDev* __restrict__ items, int32_t n_items,
-                                                         int64_t total, unsigned long long* __restrict__ counter,
-                                                         int32_t per_claim)
+// Drains the queue; returns the value of the wave's last claim.
+__device__ __forceinline__ int64_t batch_body(const BatchItemDev* __restrict__ items, int32_t n_items, int64_t total,
+                                              unsigned long long* counter, int32_t per_claim)
 {
     __shared__ __align__(16) double tile[kWave * kSlot];
     const int lane = threadIdx.x;
-    int64_t chunk = 0, claim_end = 0;
+    int64_t chunk = 0, claim_end = 0, claimed = 0;
     for (;;) {
         __syncthreads();  // the previous chunk is done with the LDS tile
         if (chunk >= claim_end) {  // claim the next per_claim consecutive chunks
             unsigned long long got = 0;
             if (lane == 0) got = atomicAdd(counter, (unsigned long long)per_claim);
-            chunk = wave_uniform((int64_t)got);
+            chunk = claimed = wave_uniform((int64_t)got);
             claim_end = chunk + per_claim;
         }
-        if (chunk >= total) return;
+        if (chunk >= total) return claimed;
         // last item whose first chunk is <= chunk
         int lo = 0, hi = n_items - 1;
         while (lo < hi) {
@@ -127,6 +127,40 @@ __global__ __launch_bounds__(kWave, 2) void batch_kernel(const BatchItemDev* __r
         }
         ++chunk;
     }
+}
+
+__global__ __launch_bounds__(kWave, 2) void batch_kernel(const BatchItemDev* __restrict__ items, int32_t n_items,
+                                                         int64_t total, unsigned long long* __restrict__ counter,
+                                                         int32_t per_claim)
+{
+    batch_body(items, n_items, total, counter, per_claim);
+}
+
+// Resident runs read the plan's counts from a device state record written
+// before the launch executes, so one captured graph serves every plan that
+// is copied into the same buffers.  The run is a single launch: every wave
+// checks the counts against the plan buffer's capacity (workgroup 0
+// publishes the verdict), and the wave that made the run's last claim
+// resets the work counter, so the record is ready for the next run without
+// a reset launch.  Which claim is last follows from counting: with T
+// chunks, C chunks per claim and W waves, ceil(T / C) claims succeed; the
+// wave holding a claim that runs past T (there is one when C does not
+// divide T) leaves without claiming again, and every other wave leaves
+// after one claim at or past T.  So the run makes
+// N = ceil(T / C) + W - [C does not divide T] claims, the last one returning
+// (N - 1) C, and no claim can follow it.
+__global__ __launch_bounds__(kWave, 2) void batch_resident_kernel(const BatchItemDev* __restrict__ items,
+                                                                  blaz_batch_state* state, int64_t capacity,
+                                                                  int32_t per_claim)
+{
+    const int64_t np = state->n_plan, tot = state->total_chunks;
+    const bool ok = np >= 0 && np <= capacity && tot >= 0 && (np > 0 || tot == 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) state->status = ok ? BLAZ_OK : BLAZ_ERR_ARG;
+    if (!ok) return;
+    auto* counter = reinterpret_cast<unsigned long long*>(&state->counter);
+    const int64_t last = batch_body(items, (int32_t)np, tot, counter, per_claim);
+    const int64_t claims = (tot + per_claim - 1) / per_claim + (int64_t)gridDim.x - (tot % per_claim != 0 ? 1 : 0);
+    if (threadIdx.x == 0 && last == (claims - 1) * per_claim) atomicExch(counter, 0ull);
 }
 
 }  // namespace blaz
@@ -274,5 +308,25 @@ BLAZ_API blaz_status blaz_batch_run(const void* plan_dev, int64_t n_plan, int64_
     if (hipGetLastError() != hipSuccess) return BLAZ_ERR_HIP;
     batch_kernel<<<(unsigned)workgroups, kWave, 0, stream>>>(static_cast<const BatchItemDev*>(plan_dev),
                                                              (int32_t)n_plan, total_chunks, cnt, chunks_per_claim);
+    return hipGetLastError() == hipSuccess ? BLAZ_OK : BLAZ_ERR_HIP;
+}
+
+BLAZ_API blaz_status blaz_batch_run_resident(const void* plan_dev, int64_t capacity, blaz_batch_state* state,
+                                             int64_t workgroups,
+                                             int32_t chunks_per_claim, hipStream_t stream)
+{
+    if (capacity <= 0 || capacity > (int64_t(1) << 30) || workgroups < 0) return BLAZ_ERR_ARG;
+    if (chunks_per_claim < 0 || chunks_per_claim > 64) return BLAZ_ERR_ARG;
+    if (chunks_per_claim == 0) chunks_per_claim = 1;
+    if (!plan_dev || !state) return BLAZ_ERR_NULL;
+    if (!aligned(plan_dev, 8) || !aligned(state, 8)) return BLAZ_ERR_ALIGN;
+    if (workgroups == 0) {
+        const int cus = blaz::detail::device_cu_count();
+        if (cus == 0) return BLAZ_ERR_HIP;
+        workgroups = 8 * (int64_t)cus;
+    }
+    if (workgroups > (int64_t(1) << 20)) workgroups = int64_t(1) << 20;
+    batch_resident_kernel<<<(unsigned)workgroups, kWave, 0, stream>>>(static_cast<const BatchItemDev*>(plan_dev), state,
+                                                                      capacity, chunks_per_claim);
     return hipGetLastError() == hipSuccess ? BLAZ_OK : BLAZ_ERR_HIP;
 }

@@ -15,7 +15,13 @@ device (and, for compress, dense matrices resident in HBM).  Two forms:
   round-robin on the others; with ``group_products`` and binary64
   contractions the tick's products of side <= 512 form one group -- one
   rebuild launch and one contraction launch per tile class for all of them),
-  so the batch and the contractions overlap on the device.  Ticks do not wait for each other: up
+  so the batch and the contractions overlap on the device.  A tick's batch
+  (its request step) takes one of three forms, ``step``: ``fresh`` plans it
+  into new buffers and runs it (a counter fill, a reset and the batch
+  kernel); ``resident`` copies the plan and its counts into a resident plan
+  buffer owned by the tick and launches the one-kernel resident run, which
+  reads the counts on the device; ``graph`` does the same copy and replays a
+  HIP graph captured for that buffer and launch shape.  Ticks do not wait for each other: up
   to ``max_inflight`` ticks run at once, and requests arriving meanwhile are
   admitted into the next tick as memory frees up.  The matmul contraction
   may run in FP64, FP32 or BF16x3 (``matmul_prec``).
@@ -103,8 +109,11 @@ def fp64_equiv_bytes(op: str, n: int) -> int:
 class Server:
     def __init__(self, pool: OperandPool, hbm_budget: int = 16 << 30, matmul_prec: str = "fp64",
                  max_inflight: int = 4, tuner=None, keep_results: bool = False, matmul_streams: int = 4,
-                 group_products: bool = False):
+                 group_products: bool = False, step: str = "resident"):
+        if step not in ("fresh", "resident", "graph"):
+            raise ValueError(f"unknown request-step form {step!r}")
         self.pool = pool
+        self.step = step
         self.group_products = group_products
         self.budget = int(hbm_budget)
         self.matmul_prec = matmul_prec
@@ -120,6 +129,10 @@ class Server:
         self.s_mm = [torch.cuda.Stream() for _ in range(max(2, matmul_streams))]
         self._next_mm = 0
         self.cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+        # one resident plan buffer per tick that can be in flight; a tick
+        # takes a free one and gives it back when its batch has completed
+        self._slots = [api.ResidentBatch(self.SLOT_ITEMS) for _ in range(max_inflight)] if step != "fresh" else []
+        self._free_slots = list(range(len(self._slots)))
 
     # -- per-request work ------------------------------------------------------
     def _alloc(self, r: Request):
@@ -162,12 +175,27 @@ class Server:
     def prepare(self, requests: list[Request]):
         """Tune every size class the run will meet before it starts (tuning
         times kernels and would otherwise stall the loop)."""
-        if not self.tuner:
-            return
-        for n in sorted({r.n for r in requests if r.op == "matmul"}):
-            self.tuner.matmul_tile(n, n, n, self.matmul_prec, True)
-        for c in range(0, 15):
-            self.tuner.batch_launch(1 << c)
+        if self.tuner:
+            for n in sorted({r.n for r in requests if r.op == "matmul"}):
+                self.tuner.matmul_tile(n, n, n, self.matmul_prec, True)
+            for c in range(0, 15):
+                self.tuner.batch_launch(1 << c)
+        if self.step == "graph":  # capture the graphs of every launch shape up front
+            shapes = {self._resident_shape(1 << c) for c in range(0, 21)}
+            with torch.cuda.stream(self.s_block):
+                for rb in self._slots:
+                    for wg, claim in sorted(shapes):
+                        rb.graph(wg, claim)
+            torch.cuda.synchronize()
+
+    def _resident_shape(self, total_chunks: int):
+        """Launch shape of a resident run: the tuned one, with the grid cut
+        to the chunk count's power-of-two class (the run does not trim its
+        grid, whose waves beyond the queue only exit, and a captured grid is
+        fixed), so at most twice the needed waves are launched."""
+        wg, claim = self.tuner.batch_launch(total_chunks) if self.tuner else (8 * self.cus, 0)
+        cls = 1 << max(0, int(total_chunks - 1).bit_length())
+        return min(wg, cls), claim
 
     def run(self, requests: list[Request], mode: str = "batched") -> dict:
         assert mode in ("plain", "batched")
@@ -203,6 +231,9 @@ class Server:
                 if not ev.query():
                     still.append((ev, reqs, held, tick))
                     continue
+                for h in held:
+                    if isinstance(h, int):  # a resident plan buffer, free again
+                        self._free_slots.append(h)
                 t_done = start_ev.elapsed_time(ev) / 1e3
                 for r in reqs:
                     r.done = t_done
@@ -237,9 +268,14 @@ class Server:
                 ticks += 1
                 continue
             if not progressed:
-                # nothing to launch: wait briefly for an arrival or a completion
-                wait = pending[0].arrival - now if pending else 0.0
-                time.sleep(min(max(wait, 0.0), 2e-4) if (ready or units or wait > 0) else 0.0)
+                # Nothing to launch.  Poll without sleeping while requests wait
+                # for memory or a tick slot, or an arrival is due within
+                # SPIN_S (a sleep overshoots by tens of microseconds, which
+                # would land on those requests' latency); otherwise sleep
+                # until SPIN_S before the next arrival, 200 us at a time.
+                wait = pending[0].arrival - now if pending else math.inf
+                if not ready and wait > self.SPIN_S:
+                    time.sleep(min(wait - self.SPIN_S, 2e-4))
         torch.cuda.synchronize()
         return self._report(requests, mode, ticks)
 
@@ -261,12 +297,26 @@ class Server:
             for r in blocks:
                 self._add_to_batch(batch, r)
             with torch.cuda.stream(self.s_block):
-                plan = batch.plan()
-                wg, claim = self.tuner.batch_launch(plan.total_chunks) if self.tuner else (0, 0)
-                plan.run(wg, claim)
+                if self._slots and len(blocks) <= self.SLOT_ITEMS:
+                    # the tick's plan into its resident buffer, then one launch
+                    # or one graph replay
+                    slot = self._free_slots.pop()
+                    rb = self._slots[slot]
+                    _, total = rb.load(batch)
+                    shape = self._resident_shape(total)
+                    if self.step == "graph":
+                        rb.graph(*shape).replay()
+                    else:
+                        rb.run(*shape)
+                    held = [slot, batch]
+                else:
+                    plan = batch.plan()
+                    wg, claim = self.tuner.batch_launch(plan.total_chunks) if self.tuner else (0, 0)
+                    plan.run(wg, claim)
+                    held = [plan]
                 ev = torch.cuda.Event(enable_timing=True)
                 ev.record(self.s_block)
-            units.append((ev, blocks, [plan]))
+            units.append((ev, blocks, held))
         tiny = [r for r in mms if r.n <= self.GROUP_MAX_SIDE]
         if self.group_products and self.matmul_prec == "fp64" and len(tiny) > 1:
             # the tick's small binary64 products as one group: one rebuild
@@ -297,6 +347,8 @@ class Server:
         return units
 
     GROUP_MAX_SIDE = 512  # products grouped per tick: those whose launch costs more than their work
+    SLOT_ITEMS = 2048     # block-level requests per resident tick (larger ticks run a fresh plan)
+    SPIN_S = 1e-3         # poll without sleeping when the next arrival is this close
 
     @staticmethod
     def _group_workspace(reqs):

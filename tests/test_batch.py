@@ -5,8 +5,10 @@ empty items).  GPU tests check every batched result against the FP64 oracle
 under the parity rules (compress bit-exact except classified boundary ties,
 add/sub/scale bit-exact, decompression and dot products within 1e-12) and
 against the standalone entry point's result bit for bit, for several grid
-sizes and when the run is captured in a HIP graph and replayed; a captured
-sequence of the single-operation entry points replays bit for bit too.
+sizes and when the run is captured in a HIP graph and replayed -- also one
+graph captured on a resident plan buffer replaying successive plans; a
+captured sequence of the single-operation entry points replays bit for bit
+too.
 """
 import ctypes
 import types
@@ -103,6 +105,66 @@ def test_run_rejects_claim_size_out_of_range(claim):
     the counter reset or the kernel is enqueued."""
     st = _lib().lib().blaz_batch_run(0x1000000, 1, 10, 0x2000000, 4, claim, None)
     assert st == -5
+
+
+@pytest.mark.parametrize("capacity,claim,wg,plan,state,status", [
+    (0, 1, 4, 0x1000000, 0x2000000, -5),          # capacity below 1
+    ((1 << 30) + 1, 1, 4, 0x1000000, 0x2000000, -5),
+    (8, 65, 4, 0x1000000, 0x2000000, -5),         # claim size out of range
+    (8, 1, -1, 0x1000000, 0x2000000, -5),         # negative grid
+    (8, 1, 4, 0, 0x2000000, -1),                  # no plan buffer
+    (8, 1, 4, 0x1000000, 0, -1),                  # no state
+    (8, 1, 4, 0x1000004, 0x2000000, -4),          # misaligned plan buffer
+    (8, 1, 4, 0x1000000, 0x2000004, -4),          # misaligned state
+])
+def test_resident_run_validates_on_the_host(capacity, claim, wg, plan, state, status):
+    """Every host-side rule is checked before anything is enqueued."""
+    st = _lib().lib().blaz_batch_run_resident(plan, capacity, state, wg, claim, None)
+    assert st == status
+
+
+def _simulate_claims(total, per_claim, waves, rng):
+    """The persistent kernel's claim protocol under a random interleaving of
+    its waves: each wave claims per_claim chunks at a time, works through
+    them, and leaves once its position reaches the end of the queue (right
+    after a claim at or past it, or inside a claim that runs past it).
+    Returns the claim values in counter order and each wave's last claim."""
+    counter, order = 0, []
+    state = [dict(chunk=0, end=0, last=None, done=False) for _ in range(waves)]
+    while not all(w["done"] for w in state):
+        w = state[rng.choice([i for i, s in enumerate(state) if not s["done"]])]
+        if w["chunk"] >= w["end"]:
+            w["chunk"] = w["last"] = counter
+            w["end"] = counter + per_claim
+            order.append(counter)
+            counter += per_claim
+        if w["chunk"] >= total:
+            w["done"] = True
+        else:
+            w["chunk"] += 1
+    return order, [w["last"] for w in state]
+
+
+def test_resident_counter_reset_rule_names_the_last_claim():
+    """The resident run's counter reset: the wave whose last claim returned
+    (N - 1) C, N = ceil(T / C) + W - [C does not divide T], resets the
+    counter.  Under random interleavings that wave is unique and its claim
+    is the last one made."""
+    rng = np.random.default_rng(5)
+    for total, per_claim, waves in [(0, 1, 3), (1, 1, 1), (10, 4, 3), (8, 4, 3), (10, 4, 1), (7, 64, 5),
+                                    (64, 64, 1), (100, 3, 17), (5, 1, 9), (33, 8, 2)]:
+        for _ in range(20):
+            order, last = _simulate_claims(total, per_claim, waves, rng)
+            n = -(-total // per_claim) + waves - (1 if total % per_claim else 0)
+            assert len(order) == n
+            assert order[-1] == (n - 1) * per_claim
+            assert sum(v == (n - 1) * per_claim for v in last) == 1
+
+
+def test_batch_state_layout():
+    L = _lib()
+    assert ctypes.sizeof(L.BatchStateC) == 32
+    assert [f[0] for f in L.BatchStateC._fields_] == ["n_plan", "total_chunks", "counter", "status"]
 
 
 def test_plan_rejects_partial_overlap():
@@ -282,6 +344,85 @@ def test_batch_graph_capture_replays():
         for got, want, check in expect:
             check(got)
             assert_equal(got, want)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("workgroups,claim", [(0, 0), (5, 2), (7, 3), (1, 64), (64, 5)])
+def test_resident_batch_graph_replays_successive_plans(workgroups, claim):
+    """One graph captured on a resident plan buffer replays whatever plan was
+    loaded last: the whole workload, then the first seven of its items, then
+    the whole workload again.  Every replay is checked against the oracle and
+    the standalone results; outputs are cleared eagerly in between, and the
+    items left out of the smaller plan stay untouched."""
+    import torch
+    import paper_2202_13007_amd as blaz
+    B, expect = make_workload(torch, blaz)
+    small = blaz.Batch()
+    small.items, small._keep = B.items[:7], B._keep
+    rb = blaz.ResidentBatch(len(B.items) + 3)
+    g = rb.graph(workgroups, claim)
+    for batch, k in ((B, len(expect)), (small, 7), (B, len(expect))):
+        for got, _, _ in expect:
+            clear(got)
+        torch.cuda.synchronize()
+        n_plan, total = rb.load(batch)
+        assert n_plan == k and total > 0
+        assert rb.graph(workgroups, claim) is g
+        g.replay()
+        torch.cuda.synchronize()
+        assert rb.status() == 0
+        assert int(rb.state.view(torch.int64)[2]) == 0  # the run reset its counter
+        for got, want, check in expect[:k]:
+            check(got)
+            assert_equal(got, want)
+        for got, _, _ in expect[k:]:
+            parts = [got] if isinstance(got, torch.Tensor) else [got.f, got.s, got.phi, got.codes]
+            assert all(int(torch.count_nonzero(p)) == 0 for p in parts)
+    # the run leaves the counter at zero, so the last plan replays again
+    # without a new copy
+    assert int(rb.state.view(torch.int64)[2]) == 0
+    for got, _, _ in expect:
+        clear(got)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    for got, want, check in expect:
+        check(got)
+        assert_equal(got, want)
+
+
+@pytest.mark.gpu
+def test_resident_batch_rejects_counts_out_of_range_on_the_device():
+    """Counts that do not fit the plan buffer (set from the host after the
+    load) make the run publish BLAZ_ERR_ARG and touch no output; a load of
+    more items than the capacity is refused on the host."""
+    import torch
+    import paper_2202_13007_amd as blaz
+    B, expect = make_workload(torch, blaz)
+    small = blaz.Batch()
+    small.items, small._keep = B.items[:3], B._keep
+    rb = blaz.ResidentBatch(3)
+    with pytest.raises(ValueError):
+        rb.load(B)
+    for bad in ((4, 10), (-1, 10), (0, 3), (3, -1)):
+        for got, _, _ in expect[:3]:
+            clear(got)
+        rb.load(small)
+        torch.cuda.synchronize()
+        rb.state.view(torch.int64)[0:2] = torch.tensor(bad, dtype=torch.int64, device="cuda")
+        rb.run(4, 1)
+        torch.cuda.synchronize()
+        assert rb.status() == -5, bad
+        for got, _, _ in expect[:3]:
+            for p in [got.f, got.s, got.phi, got.codes]:
+                assert int(torch.count_nonzero(p)) == 0, bad
+    rb.load(small)
+    rb.run(4, 1)
+    torch.cuda.synchronize()
+    assert rb.status() == 0
+    for got, want, check in expect[:3]:
+        check(got)
+        assert_equal(got, want)
 
 
 @pytest.mark.gpu

@@ -118,13 +118,16 @@ class OracleOperands:
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("prec,group", [("fp64", False), ("fp64", True), ("bf16x3", False)])
-def test_results_same_alone_and_in_the_mix(prec, group):
+@pytest.mark.parametrize("prec,group,step", [("fp64", False, "fresh"), ("fp64", True, "graph"),
+                                             ("fp64", False, "resident"), ("bf16x3", False, "resident")])
+def test_results_same_alone_and_in_the_mix(prec, group, step):
     """Every request of a 300-request mix (sides 8..512, arriving faster than
     they are served, so ticks batch many of them and the batch and the
     contractions overlap; with `group` each tick's products run as one
-    grouped launch) matches the oracle under the parity rules, and equals
-    the same request run alone bit for bit."""
+    grouped launch; each tick's batch a fresh plan, a resident plan buffer's
+    one-kernel run, or a replay of a graph captured on that buffer) matches
+    the oracle under the parity rules, and equals the same request run alone
+    bit for bit."""
     import torch
     from paper_2202_13007_amd.serve import OperandPool, Server
     from paper_2202_13007_amd.tune import Autotuner
@@ -133,7 +136,7 @@ def test_results_same_alone_and_in_the_mix(prec, group):
     pool = OperandPool(A, B, [r.n for r in reqs])
     orc = OracleOperands(pool, [r.n for r in reqs])
     srv = Server(pool, hbm_budget=1 << 30, matmul_prec=prec, tuner=Autotuner(path=None), keep_results=True,
-                 group_products=group)
+                 group_products=group, step=step)
     srv.prepare(reqs)
     rep = srv.run(reqs, "batched")
     assert rep["requests"] == 300 and rep["ticks"] < 300  # requests were batched together
@@ -152,7 +155,8 @@ def test_tiny_budget_forces_queueing():
     biggest = max(output_bytes(r.op, r.n, "fp64") for r in reqs)
     pool = OperandPool(A, B, [r.n for r in reqs])
     orc = OracleOperands(pool, [r.n for r in reqs])
-    srv = Server(pool, hbm_budget=biggest, keep_results=True)
+    srv = Server(pool, hbm_budget=biggest, keep_results=True, step="graph")
+    srv.prepare(reqs)
     rep = srv.run(reqs, "batched")
     assert srv.peak_used <= biggest
     # every request is admitted in exactly one tick and a tick admits at most
