@@ -58,11 +58,12 @@ def parse():
                     help="skip the 64x64 latency, cold-cache, tunable-rate and 16384x16384 mixed-precision legs")
     ap.add_argument("--only", default="",
                     help="comma-separated legs to run after the step (cold, rates, transform, serving, latency, "
-                         "matmul, mixed, cpu); default: every leg the other flags leave on")
+                         "matmul, mixed, cpu; dots runs the dot products of the matmul leg alone); default: every "
+                         "leg the other flags leave on")
     args = ap.parse_args()
     args.legs = {"cold", "rates", "transform", "serving", "latency", "matmul", "mixed", "cpu"}
     if args.only:
-        args.legs &= set(args.only.split(","))
+        args.legs = (args.legs | {"dots"}) & set(args.only.split(","))
     if args.no_extra:
         args.legs -= {"cold", "rates", "transform", "latency", "mixed"}
     if args.no_matmul:
@@ -698,6 +699,35 @@ def summarize_pmc(d):
     return "\n".join(lines)
 
 
+def summarize_pmc_runs(d, name):
+    """Dispatches of kernels whose name contains `name`, cut into runs of
+    consecutive dispatches (a dispatch of another kernel in between ends a
+    run), with each counter's average per run: separates the cases of a
+    leg that launch the same kernel with the same grid (the dot leg's own
+    and shared vectors)."""
+    rows = read_csv(os.path.join(d, "run_counter_collection.csv"))
+    per = {}
+    for r in rows:
+        per.setdefault(int(r["Dispatch_Id"]), (r["Kernel_Name"], int(r["Grid_Size"]), {}))[2][r["Counter_Name"]] = \
+            float(r["Counter_Value"])
+    runs, cur = [], None
+    for i in sorted(per):
+        k, g, v = per[i]
+        if name not in k:
+            cur = None
+            continue
+        if cur is None or cur[0] != (short_kernel_name(k), g):
+            cur = ((short_kernel_name(k), g), [])
+            runs.append(cur)
+        cur[1].append(v)
+    counters = sorted({c for _, vs in runs for v in vs for c in v})
+    lines = [f"{'run':>3s} {'kernel':40s} {'grid':>9s} {'n':>4s} " + " ".join(f"{c:>20s}" for c in counters)]
+    for j, ((k, g), vs) in enumerate(runs):
+        lines.append(f"{j:3d} {k[:40]:40s} {g:9d} {len(vs):4d} " + " ".join(
+            f"{sum(v.get(c, 0.0) for v in vs) / len(vs):20.4g}" for c in counters))
+    return "\n".join(lines)
+
+
 STEP_KERNELS = {  # kernel -> (sources, algorithmic bytes read, written per block) on the plain-8192 step
     "compress_f64_kernel": (CODEC_SOURCES, BLOCK, RECORD),
     "decompress_kernel": (CODEC_SOURCES, RECORD, BLOCK),
@@ -752,12 +782,14 @@ def summarize_traffic(fetch_dir, write_dir, nblk=1 << 20, copy_bytes=1 << 29):
 
 
 def summarize_main(argv):
-    """python bench.py --summarize {trace DIR | pmc DIR | traffic FETCH_DIR WRITE_DIR}"""
-    kind = argv[0]
+    """python bench.py --summarize {trace DIR | pmc DIR | pmc-runs DIR NAME | traffic FETCH_DIR WRITE_DIR}"""
+    kind = argv[0] if argv else ""
     if kind == "trace":
         print(summarize_trace(argv[1]))
     elif kind == "pmc":
         print(summarize_pmc(argv[1]))
+    elif kind == "pmc-runs":
+        print(summarize_pmc_runs(argv[1], argv[2]))
     elif kind == "traffic":
         print(summarize_traffic(argv[1], argv[2]))
     else:
@@ -937,6 +969,12 @@ def main():
     if "matmul" in legs:
         print("# 4096 linear-algebra leg", file=sys.stderr, flush=True)
         result["matmul_4096"] = matmul_leg(blaz, torch, workload_inputs)
+    elif "dots" in legs:  # the dot products of the linear-algebra leg alone (for profiling)
+        print("# 4096 dot-product leg", file=sys.stderr, flush=True)
+        Am, Bm, Vm = workload_inputs("linalg-4096")
+        g = blaz.compress(torch.from_numpy(Am).cuda())
+        result["dots_4096"] = dot_leg(blaz, torch, g, blaz.decompress(g), torch.from_numpy(Bm).cuda(),
+                                      torch.from_numpy(Vm).cuda())
     if "mixed" in legs:
         print("# 16384 mixed-precision leg", file=sys.stderr, flush=True)
         result["mixed_16384"] = mixed_leg(blaz, torch, workload_inputs)

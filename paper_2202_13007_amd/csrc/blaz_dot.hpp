@@ -282,16 +282,38 @@ __device__ __forceinline__ void dot_dense_part(int w, int lane, int64_t q0, int6
         double acc[kDotGroup];
 #pragma unroll
         for (int t = 0; t < kDotGroup; ++t) acc[t] = 0.0;
-        for (int64_t kb = 64 * w + lane; kb < nbc; kb += kDotSlots) {
-            double coef[kKept], fb;
-            LineStream sx;
-            load_block<false>(X.f, X.s, X.phi, X.c, I * nbc + kb, coef, fb);
-            sx.init(coef, fb);
+        if (ldv == 0) {  // one shared vector: its 8 entries per block loaded once for the 8 lines
+            for (int64_t kb = 64 * w + lane; kb < nbc; kb += kDotSlots) {
+                double coef[kKept], fb, vb[8];
+                LineStream sx;
+                load_block<false>(X.f, X.s, X.phi, X.c, I * nbc + kb, coef, fb);
+                const double2* vp = reinterpret_cast<const double2*>(v + kb * 8);
 #pragma unroll
-            for (int u = 0; u < kDotGroup; ++u) {
-                double x[8];
-                sx.line(u, x);
-                acc[u] = dot8_global(acc[u], x, v + (q0 + u) * ldv + kb * 8);
+                for (int k = 0; k < 4; ++k) {
+                    const double2 vv = vp[k];
+                    vb[2 * k] = vv.x;
+                    vb[2 * k + 1] = vv.y;
+                }
+                sx.init(coef, fb);
+#pragma unroll
+                for (int u = 0; u < kDotGroup; ++u) {
+                    double x[8];
+                    sx.line(u, x);
+                    acc[u] = dot8(acc[u], x, vb);  // the order and roundings of dot8_global
+                }
+            }
+        } else {
+            for (int64_t kb = 64 * w + lane; kb < nbc; kb += kDotSlots) {
+                double coef[kKept], fb;
+                LineStream sx;
+                load_block<false>(X.f, X.s, X.phi, X.c, I * nbc + kb, coef, fb);
+                sx.init(coef, fb);
+#pragma unroll
+                for (int u = 0; u < kDotGroup; ++u) {
+                    double x[8];
+                    sx.line(u, x);
+                    acc[u] = dot8_global(acc[u], x, v + (q0 + u) * ldv + kb * 8);
+                }
             }
         }
 #pragma unroll
