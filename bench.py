@@ -870,6 +870,22 @@ def main():
     # an event pair around every launch, on the launching stream.
     ms_step = timed_steps(False)
     ms_step_instrumented = timed_steps(True)
+    # The same five launches replayed from a captured graph (launch overhead
+    # excluded); reported beside the eager step, which is `value`.
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step(False)
+    for _ in range(2):
+        graph.replay()
+    torch.cuda.synchronize()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record()
+    for _ in range(args.steps):
+        graph.replay()
+    g1.record()
+    torch.cuda.synchronize()
+    ms_step_graph = g0.elapsed_time(g1) / args.steps
+    del graph
 
     per = {k: float(np.mean(elapsed_ms(v))) for k, v in ev.items()}
     bytes_actual = {"compress": (BLOCK + RECORD) * nblk, "add": 3 * RECORD * nblk,
@@ -904,6 +920,21 @@ def main():
         if name in per:
             plain[name]["blaz_speedup"] = round(ms / per[name], 2)
     del C
+    # A 2 GiB device-to-device copy: the achievable streaming rate, beside the
+    # datasheet peak.
+    src = torch.empty(1 << 28, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * (1 << 31) / (c0.elapsed_time(c1) / 5) / 1e6
+    del src, dst
 
     # Roofline of the dominant kernel: compress, 557 algorithmic bytes per block.
     comp_ms = (per["compress_x"] + per["compress_y"]) / 2
@@ -911,7 +942,8 @@ def main():
     traffic = traffic_for("compress_f64_kernel", CODEC_SOURCES)
     roofline = {"kernel": "compress_f64_kernel", "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic}
+                "traffic": traffic, "copy_2GiB_GBps": round(copy_gbs, 1),
+                "frac_vs_copy": round(achieved / copy_gbs, 4)}
 
     result = {
         "metric": "blaz compress+add GB/s (FP64-equiv) vs plain; matmul TFLOP/s; p99 latency",
@@ -922,6 +954,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 5),
         "ms_per_step_with_per_op_events": round(ms_step_instrumented, 5),
+        "ms_per_step_graph": round(ms_step_graph, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
