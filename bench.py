@@ -750,11 +750,16 @@ def summarize_traffic(fetch_dir, write_dir, nblk=1 << 20, copy_bytes=1 << 29):
             name = short_kernel_name(r["Kernel_Name"])
             if int(r["Grid_Size"]) == 1048576 and name.startswith("blaz::"):
                 base = name.split("::")[1].split("<")[0]
-            elif "copyBuffer" in name and int(r["Grid_Size"]) == 131072:  # the 512 MiB copy
+            elif "copyBuffer" in name:
                 base = "copy"
             else:
                 continue
             acc.setdefault(base, []).append(float(r["Counter_Value"]))
+        # the run copies 512 MiB (the dense comparison) and 2 GiB (the copy
+        # rate); the smaller copies are the calibration
+        if "copy" in acc:
+            small = min(acc["copy"])
+            acc["copy"] = [v for v in acc["copy"] if v < 2 * small]
         return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
     fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
     ff = copy_bytes / (fetch["copy"][0] * 1024)

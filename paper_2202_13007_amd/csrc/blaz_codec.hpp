@@ -288,19 +288,41 @@ __device__ __forceinline__ void quantize_store(const double D[64], const SlopeOu
     if (b < nblk) {
         fo[b] = so_.f;
         so[b] = so_.s;
-        phio[b] = (uint8_t)phi;
     }
+    // The wave's codes (1792 bytes) and phi bytes (64) packed in LDS, then
+    // written as 16-byte runs (4-byte ones when the destination is not
+    // 16-byte aligned, and for a ragged last wave's tail).
     uint32_t* ct = reinterpret_cast<uint32_t*>(tile);
+    uint8_t* pt = reinterpret_cast<uint8_t*>(ct + kWave * kCodeWords);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kCodeWords; ++q) ct[lane * kCodeWords + q] = w[q];
+    pt[lane] = (uint8_t)phi;
     __syncthreads();
-    const int64_t nwords = (nblk - wave_base < kWave ? nblk - wave_base : kWave) * kCodeWords;
+    const int64_t nb = nblk - wave_base < kWave ? nblk - wave_base : kWave;
+    const int64_t nwords = nb * kCodeWords;
     uint32_t* cdst = codes + wave_base * kCodeWords;
+    if ((reinterpret_cast<uintptr_t>(cdst) & 15) == 0) {
+        const int64_t nvec = nwords >> 2;
 #pragma unroll
-    for (int k = 0; k < kCodeWords; ++k) {
-        const int idx = lane + kWave * k;
-        if (idx < nwords) cdst[idx] = ct[idx];
+        for (int k = 0; k < (kWave * kCodeWords + 4 * kWave - 1) / (4 * kWave); ++k) {
+            const int idx = lane + kWave * k;
+            if (idx < nvec) reinterpret_cast<uint4*>(cdst)[idx] = reinterpret_cast<const uint4*>(ct)[idx];
+        }
+        const int64_t rest = 4 * nvec + lane;
+        if (rest < nwords && lane < 4) cdst[rest] = ct[rest];
+    } else {
+#pragma unroll
+        for (int k = 0; k < kCodeWords; ++k) {
+            const int idx = lane + kWave * k;
+            if (idx < nwords) cdst[idx] = ct[idx];
+        }
+    }
+    uint8_t* pdst = phio + wave_base;
+    if (nb == kWave && (reinterpret_cast<uintptr_t>(pdst) & 3) == 0) {
+        if (lane < kWave / 4) reinterpret_cast<uint32_t*>(pdst)[lane] = reinterpret_cast<const uint32_t*>(pt)[lane];
+    } else if (lane < nb) {
+        pdst[lane] = pt[lane];
     }
 }
 
