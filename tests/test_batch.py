@@ -426,6 +426,66 @@ def test_resident_batch_rejects_counts_out_of_range_on_the_device():
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("resident", [False, True])
+def test_many_small_items(resident):
+    """1,500 operations on matrices of 8 to 200 rows and columns (every op,
+    ragged block counts, most items one partial chunk): the queue's item
+    search and claims over a long plan.  Every result equals its standalone
+    call bit for bit; a sample is checked against the oracle."""
+    import torch
+    import oracle
+    import paper_2202_13007_amd as blaz
+    from oracle.parity import assert_same_compressed
+    rng = np.random.default_rng(41)
+    B = blaz.Batch()
+    outs, wants, samples = [], [], []
+    pool = {}
+    for i in range(1500):
+        r, c = 8 * int(rng.integers(1, 26)), 8 * int(rng.integers(1, 26))
+        if (r, c) not in pool:  # operands: the oracle's records of seeded fields, uploaded
+            h = smooth_field(r, 4, 2.0, 1e-3, 3000 + len(pool), cols=c)
+            o = oracle.compress(h)
+            pool[(r, c)] = (h, torch.from_numpy(h).cuda(), o,
+                            blaz.BlazMatrix.from_host(r, c, o.f, o.s, o.phi, o.codes))
+        h, d, o, x = pool[(r, c)]
+        op = int(rng.integers(0, 4))
+        if op == 0:
+            z = blaz.BlazMatrix.empty(r, c)
+            B.compress(d, z)
+            outs.append(z)
+            wants.append(blaz.compress(d))
+        elif op == 1:
+            z = blaz.BlazMatrix.empty(r, c)
+            B.add(x, x, z)
+            outs.append(z)
+            wants.append(blaz.add(x, x))
+            if len(samples) < 5:
+                samples.append((z, o))
+        elif op == 2:
+            z = blaz.BlazMatrix.empty(r, c)
+            B.scale(x, -0.5, z)
+            outs.append(z)
+            wants.append(blaz.scale(x, -0.5))
+        else:
+            D = torch.empty((r, c), dtype=torch.float64, device="cuda")
+            B.decompress(x, D)
+            outs.append(D)
+            wants.append(blaz.decompress(x))
+    if resident:
+        rb = blaz.ResidentBatch(len(B.items))
+        rb.load(B)
+        rb.run(37, 3)
+    else:
+        B.plan().run(37, 3)
+    torch.cuda.synchronize()
+    for got, want in zip(outs, wants):
+        assert_equal(got, want)
+    for z, o in samples:
+        s = oracle.add(o, o)
+        assert_same_compressed(z.to_host(), (s.f, s.s, s.phi, s.codes), "add in a long batch")
+
+
+@pytest.mark.gpu
 def test_batch_rejects_invalid_item_without_launching():
     import torch
     import paper_2202_13007_amd as blaz
