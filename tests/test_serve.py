@@ -139,6 +139,7 @@ def test_results_same_alone_and_in_the_mix(prec, group, step):
                  group_products=group, step=step)
     srv.prepare(reqs)
     rep = srv.run(reqs, "batched")
+    print(f"{prec} group={group} step={step}: {rep['ticks']} ticks for 300 requests")
     assert rep["requests"] == 300 and rep["ticks"] < 300  # requests were batched together
     for r in reqs:
         assert np.isfinite(r.done) and r.done >= r.arrival
