@@ -261,11 +261,29 @@ __device__ __forceinline__ void predict_block(double x[64], SlopeOut& o, uint8_t
     }
 }
 
+// phi of Eq. eqphi from m, the max over the block's 64 |D|: trunc(127/m)
+// clamped to 255.
+__device__ __forceinline__ int phi_of(double m)
+{
+    const double px = 127.0 / m;  // +inf when m == 0
+    return px < 255.0 ? (int)px : 255;
+}
+
+// Code t (trunc(phi D), toward zero) into its byte of the packed words.
+__device__ __forceinline__ void pack_code(uint32_t w[kCodeWords], int t, double phid, double d)
+{
+    const int c = (int)(phid * d);
+    w[t / 4] |= ((uint32_t)c & 0xffu) << (8 * (t % 4));
+}
+
+__device__ __forceinline__ void store_record(const uint32_t w[kCodeWords], int phi, const SlopeOut& so_,
+                                             int64_t nblk, int64_t wave_base, int lane, void* tile, double* fo,
+                                             double* so, uint8_t* phio, uint32_t* codes);
+
 // Quantization (Eq. eqphi) and the stores of one wave's records.  D holds
 // the 64 DCT coefficients of the lane's block (binary64).  m is the max over
 // all 64, phi = trunc(127/m) clamped to 255, codes = trunc(phi D) at the 28
-// kept positions.  The wave's codes are one contiguous run of 64 * 28 bytes:
-// packed in LDS (tile, >= 1792 bytes), then written as consecutive dwords.
+// kept positions.
 __device__ __forceinline__ void quantize_store(const double D[64], const SlopeOut& so_, int64_t nblk,
                                                int64_t wave_base, int lane, void* tile, double* fo, double* so,
                                                uint8_t* phio, uint32_t* codes)
@@ -273,17 +291,23 @@ __device__ __forceinline__ void quantize_store(const double D[64], const SlopeOu
     double m = 0.0;
 #pragma unroll
     for (int e = 0; e < 64; ++e) m = fmax(m, fabs(D[e]));
-    const double px = 127.0 / m;  // +inf when m == 0
-    const int phi = px < 255.0 ? (int)px : 255;
+    const int phi = phi_of(m);
     const double phid = (double)phi;
     uint32_t w[kCodeWords];
 #pragma unroll
     for (int q = 0; q < kCodeWords; ++q) w[q] = 0;
 #pragma unroll
-    for (int t = 0; t < kKept; ++t) {
-        const int c = (int)(phid * D[kept_row(t) * 8 + kept_col(t)]);  // truncation toward zero
-        w[t / 4] |= ((uint32_t)c & 0xffu) << (8 * (t % 4));
-    }
+    for (int t = 0; t < kKept; ++t) pack_code(w, t, phid, D[kept_row(t) * 8 + kept_col(t)]);
+    store_record(w, phi, so_, nblk, wave_base, lane, tile, fo, so, phio, codes);
+}
+
+// The record of the lane's block: f and s, then the wave's codes and phi
+// bytes.  The codes are one contiguous run of 64 * 28 bytes: packed in LDS
+// (tile, >= 1856 bytes) with the phi bytes, then written out.
+__device__ __forceinline__ void store_record(const uint32_t w[kCodeWords], int phi, const SlopeOut& so_,
+                                             int64_t nblk, int64_t wave_base, int lane, void* tile, double* fo,
+                                             double* so, uint8_t* phio, uint32_t* codes)
+{
     const int64_t b = wave_base + lane;
     if (b < nblk) {
         fo[b] = so_.f;

@@ -174,17 +174,35 @@ __global__ __launch_bounds__(kWave, 2) void compress_mixed_kernel(const double* 
     for (int G = 0; G < 16; ++G)
         *reinterpret_cast<f32x4*>(&df[f32_slot(4 * G + 2 * (g >> 1) + (l16 >> 3), l16 & 7, g & 1)]) = dacc[G];
     __syncthreads();
+    float dv[64];  // D of the lane's block, row-major
 #pragma unroll
     for (int j = 0; j < 8; ++j)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const f32x4 v = *reinterpret_cast<const f32x4*>(&df[f32_slot(lane, j, h)]);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) x[8 * (4 * h + q) + j] = (double)v[q];
+            for (int q = 0; q < 4; ++q) dv[8 * (4 * h + q) + j] = v[q];
         }
-    x[0] = so_.dc;
 
-    quantize_store(x, so_, nblk, wave_base, lane, smem, fo, so, phio, codes);
+    // Quantization with quantize_store's values: m over the 63 non-DC
+    // coefficients is taken in FP32 (widening to binary64 is exact and keeps
+    // the order, so it is the binary64 max of the widened values) and joined
+    // with |DC| in binary64; the codes are trunc(phi D) in binary64 of the
+    // widened coefficients, the DC code of the binary64 DC.
+    float mf = 0.0f;
+#pragma unroll
+    for (int e = 1; e < 64; ++e) mf = fmaxf(mf, fabsf(dv[e]));
+    const int phi = phi_of(fmax((double)mf, fabs(so_.dc)));
+    const double phid = (double)phi;
+    uint32_t w[kCodeWords];
+#pragma unroll
+    for (int q = 0; q < kCodeWords; ++q) w[q] = 0;
+#pragma unroll
+    for (int t = 0; t < kKept; ++t) {
+        const int e = kept_row(t) * 8 + kept_col(t);
+        pack_code(w, t, phid, e == 0 ? so_.dc : (double)dv[e]);
+    }
+    store_record(w, phi, so_, nblk, wave_base, lane, smem, fo, so, phio, codes);
 }
 
 namespace detail {
