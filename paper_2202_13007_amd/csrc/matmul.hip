@@ -55,11 +55,11 @@ constexpr int kPadA64 = 3;
 constexpr int kPadB64 = 2;
 
 // Tile (tm, tn) for workgroup `wg` of `nwg`: contiguous ranges per XCD, then
-// groups of 8 tile rows walked column by column for L2 reuse.
+// groups of 4 tile rows walked column by column for L2 reuse.
 __device__ __forceinline__ void tile_of(int wg, int nwg, int ntm, int ntn, int& tm, int& tn)
 {
     if (nwg % 8 == 0) wg = (wg % 8) * (nwg / 8) + wg / 8;
-    constexpr int kGroup = 8;
+    constexpr int kGroup = 4;
     const int per_group = kGroup * ntn;
     const int g = wg / per_group;
     const int first = g * kGroup;
