@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=768, help="rows of each field the oracle times")
     ap.add_argument("--serve-requests", type=int, default=20000, help="requests of the serving mix (0 skips it)")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0, help="HBM budget of the serving loop")
+    ap.add_argument("--serve-trace", action="store_true",
+                    help="a roctx range around every serving tick (for rocprofv3 --marker-trace)")
     ap.add_argument("--serve-step", default="resident", choices=("fresh", "resident", "graph"),
                     help="form of the batched serving loop's request step: a fresh plan, a resident plan buffer "
                          "and one launch, or a resident buffer and a graph replay")
@@ -574,7 +576,7 @@ def request_step_cost(torch, pool, ticks=400):
     return res
 
 
-def serving_leg(torch, dA, dB, count, budget_gib, loads=(0.5, 0.8, 1.2), step="resident"):
+def serving_leg(torch, dA, dB, count, budget_gib, loads=(0.5, 0.8, 1.2), step="resident", trace=False):
     """The serving mix: `count` requests (compress 30%, add 25%, scale 15%,
     dot 15%, matmul 15%), sides log-uniform in [64, 8192], on the two 8192^2
     fields (each side n uses their n x n corners).  The plain form's capacity
@@ -596,10 +598,11 @@ def serving_leg(torch, dA, dB, count, budget_gib, loads=(0.5, 0.8, 1.2), step="r
     out = {"requests": count, "hbm_budget_GiB": budget_gib, "mix": "compress .30 add .25 scale .15 dot .15 matmul .15",
            "sides": "log-uniform in [64, 8192], multiples of 8"}
     out["request_step_form"] = step
-    servers = {"plain": Server(pool, budget, "fp64", tuner=tuner),
-               "batched_fp64": Server(pool, budget, "fp64", tuner=tuner, step=step),
-               "batched_fp64_grouped": Server(pool, budget, "fp64", tuner=tuner, group_products=True, step=step),
-               "batched_bf16x3": Server(pool, budget, "bf16x3", tuner=tuner, step=step)}
+    servers = {"plain": Server(pool, budget, "fp64", tuner=tuner, trace=trace),
+               "batched_fp64": Server(pool, budget, "fp64", tuner=tuner, step=step, trace=trace),
+               "batched_fp64_grouped": Server(pool, budget, "fp64", tuner=tuner, group_products=True, step=step,
+                                              trace=trace),
+               "batched_bf16x3": Server(pool, budget, "bf16x3", tuner=tuner, step=step, trace=trace)}
     for srv in servers.values():
         srv.prepare(calib)
     # warm-up and capacity (everything arrives at t = 0)
@@ -728,6 +731,32 @@ def summarize_pmc_runs(d, name):
     return "\n".join(lines)
 
 
+def summarize_markers(d):
+    """The serving loop's tick ranges (roctx, run_marker_api_trace.csv): host
+    time to launch a tick, by the number of requests in it."""
+    import re
+    rows = read_csv(os.path.join(d, "run_marker_api_trace.csv"))
+    buckets = {}
+    for r in rows:
+        m = re.match(r"tick \d+: (\d+) requests, (\d+) matmul", r["Function"])
+        if not m:
+            continue
+        n = int(m.group(1))
+        key = "1" if n == 1 else "2-9" if n < 10 else "10-99" if n < 100 else ">=100"
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        buckets.setdefault(key, []).append((us, n))
+    lines = [f"{'requests per tick':>17s} {'ticks':>7s} {'median_us':>10s} {'p90_us':>9s} {'p99_us':>9s} "
+             f"{'max_us':>9s} {'us_per_request':>14s}"]
+    for key in ("1", "2-9", "10-99", ">=100"):
+        if key not in buckets:
+            continue
+        v = sorted(u for u, _ in buckets[key])
+        per = sum(u for u, _ in buckets[key]) / sum(n for _, n in buckets[key])
+        lines.append(f"{key:>17s} {len(v):7d} {v[len(v) // 2]:10.1f} {v[int(0.9 * (len(v) - 1))]:9.1f} "
+                     f"{v[int(0.99 * (len(v) - 1))]:9.1f} {v[-1]:9.1f} {per:14.1f}")
+    return "\n".join(lines)
+
+
 STEP_KERNELS = {  # kernel -> (sources, algorithmic bytes read, written per block) on the plain-8192 step
     "compress_f64_kernel": (CODEC_SOURCES, BLOCK, RECORD),
     "decompress_kernel": (CODEC_SOURCES, RECORD, BLOCK),
@@ -787,7 +816,8 @@ def summarize_traffic(fetch_dir, write_dir, nblk=1 << 20, copy_bytes=1 << 29):
 
 
 def summarize_main(argv):
-    """python bench.py --summarize {trace DIR | pmc DIR | pmc-runs DIR NAME | traffic FETCH_DIR WRITE_DIR}"""
+    """python bench.py --summarize {trace DIR | pmc DIR | pmc-runs DIR NAME | markers DIR |
+    traffic FETCH_DIR WRITE_DIR}"""
     kind = argv[0] if argv else ""
     if kind == "trace":
         print(summarize_trace(argv[1]))
@@ -795,6 +825,8 @@ def summarize_main(argv):
         print(summarize_pmc(argv[1]))
     elif kind == "pmc-runs":
         print(summarize_pmc_runs(argv[1], argv[2]))
+    elif kind == "markers":
+        print(summarize_markers(argv[1]))
     elif kind == "traffic":
         print(summarize_traffic(argv[1], argv[2]))
     else:
@@ -998,7 +1030,7 @@ def main():
         result["transform_input_8192"] = transform_input_leg(blaz, torch, dA)
     if "serving" in legs:
         result["serving"] = serving_leg(torch, dA, dB, args.serve_requests, args.serve_budget_gib,
-                                        step=args.serve_step)
+                                        step=args.serve_step, trace=args.serve_trace)
     del dA, dB
 
     if "latency" in legs:

@@ -43,6 +43,7 @@ import numpy as np
 import torch
 
 from . import api
+from .trace import Range
 
 OPS = ("compress", "add", "scale", "dot", "matmul")
 SCALE_C = 1.7
@@ -56,6 +57,7 @@ class Request:
     arrival: float                  # seconds after the start of the run
     done: float = math.nan          # seconds after the start (device clock)
     nbytes: int = 0                 # device memory held while in flight
+    cancelled: bool = False         # dropped from the queue past its deadline
     result: object = None
     _hold: list = field(default_factory=list, repr=False)
 
@@ -109,11 +111,12 @@ def fp64_equiv_bytes(op: str, n: int) -> int:
 class Server:
     def __init__(self, pool: OperandPool, hbm_budget: int = 16 << 30, matmul_prec: str = "fp64",
                  max_inflight: int = 4, tuner=None, keep_results: bool = False, matmul_streams: int = 4,
-                 group_products: bool = False, step: str = "resident"):
+                 group_products: bool = False, step: str = "resident", trace: bool = False):
         if step not in ("fresh", "resident", "graph"):
             raise ValueError(f"unknown request-step form {step!r}")
         self.pool = pool
         self.step = step
+        self.trace = trace  # a roctx range around each tick's launches
         self.group_products = group_products
         self.budget = int(hbm_budget)
         self.matmul_prec = matmul_prec
@@ -178,7 +181,7 @@ class Server:
         if self.tuner:
             for n in sorted({r.n for r in requests if r.op == "matmul"}):
                 self.tuner.matmul_tile(n, n, n, self.matmul_prec, True)
-            for c in range(0, 15):
+            for c in range(0, self.tuner.BATCH_MAX_CLASS + 1):  # every class a tick can meet
                 self.tuner.batch_launch(1 << c)
         if self.step == "graph":  # capture the graphs of every launch shape up front
             shapes = {self._resident_shape(1 << c) for c in range(0, 21)}
@@ -197,9 +200,16 @@ class Server:
         cls = 1 << max(0, int(total_chunks - 1).bit_length())
         return min(wg, cls), claim
 
-    def run(self, requests: list[Request], mode: str = "batched") -> dict:
+    def run(self, requests: list[Request], mode: str = "batched", deadline_ms: float | None = None) -> dict:
+        """Serve `requests` (arrival times relative to the start).  With
+        `deadline_ms`, a request still queued (arrived, not admitted) that
+        long after its arrival is cancelled: it is dropped without running,
+        marked `cancelled`, and left out of the latency figures; admitted
+        requests always run to completion, and the loop goes on."""
         assert mode in ("plain", "batched")
+        deadline = None if deadline_ms is None else deadline_ms / 1e3
         for r in requests:
+            r.cancelled, r.done = False, math.nan
             r.nbytes = output_bytes(r.op, r.n, self.matmul_prec)
             if r.nbytes > self.budget:
                 raise ValueError(f"request {r.rid} needs {r.nbytes} bytes, more than the whole budget")
@@ -254,6 +264,14 @@ class Server:
             while pending and pending[0].arrival <= now:
                 ready.append(pending.popleft())
             progressed = complete_ready()
+            # the queue is in arrival order: the first request within its
+            # deadline ends the cancellations
+            while deadline is not None and ready and now - ready[0].arrival > deadline:
+                r = ready.popleft()
+                r.cancelled = True
+                r.result = None
+                ndone += 1
+                progressed = True
             if ready and len(ticks_inflight) < limit and used + ready[0].nbytes <= self.budget:
                 admitted = []
                 while ready and used + ready[0].nbytes <= self.budget and (mode == "batched" or not admitted):
@@ -262,7 +280,12 @@ class Server:
                     self._alloc(r)
                     admitted.append(r)
                 self.peak_used = max(self.peak_used, used)
-                new_units = self._launch(admitted, mode)
+                if self.trace:
+                    with Range(f"tick {ticks}: {len(admitted)} requests, "
+                               f"{sum(r.op == 'matmul' for r in admitted)} matmul"):
+                        new_units = self._launch(admitted, mode)
+                else:
+                    new_units = self._launch(admitted, mode)
                 ticks_inflight[ticks] = len(new_units)
                 units.extend((ev, reqs, held, ticks) for ev, reqs, held in new_units)
                 ticks += 1
@@ -361,14 +384,16 @@ class Server:
         return torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
 
     def _report(self, requests, mode, ticks) -> dict:
-        lat = np.array([(r.done - r.arrival) * 1e3 for r in requests])
+        served = [r for r in requests if not r.cancelled]
+        lat = np.array([(r.done - r.arrival) * 1e3 for r in served]) if served else np.zeros(1)
         first = min(r.arrival for r in requests)
-        last = max(r.done for r in requests)
+        last = max((r.done for r in served), default=first)
         span = max(last - first, 1e-9)
-        eq = sum(fp64_equiv_bytes(r.op, r.n) for r in requests)
-        flop = sum(2 * r.n ** 3 for r in requests if r.op == "matmul")
-        return {"mode": mode, "requests": len(requests), "ticks": ticks,
+        eq = sum(fp64_equiv_bytes(r.op, r.n) for r in served)
+        flop = sum(2 * r.n ** 3 for r in served if r.op == "matmul")
+        return {"mode": mode, "requests": len(requests), "served": len(served),
+                "cancelled": len(requests) - len(served), "ticks": ticks,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                "mean_ms": float(lat.mean()), "makespan_s": span, "req_per_s": len(requests) / span,
+                "mean_ms": float(lat.mean()), "makespan_s": span, "req_per_s": len(served) / span,
                 "fp64_equiv_GBps": eq / span / 1e9, "matmul_TFLOPs": flop / span / 1e12,
                 "matmul_prec": self.matmul_prec}

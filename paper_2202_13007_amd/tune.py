@@ -104,8 +104,12 @@ class Autotuner:
         return best
 
     # -- persistent grid ------------------------------------------------------
+    # Queues of more chunks than this share one size class: the synthetic
+    # batch a class is tuned on is capped at this size anyway.
+    BATCH_MAX_CLASS = 14
+
     def batch_key(self, total_chunks: int) -> str:
-        return f"{self.arch}|batch|chunks{_pow2_class(total_chunks)}"
+        return f"{self.arch}|batch|chunks{min(_pow2_class(total_chunks), self.BATCH_MAX_CLASS)}"
 
     def batch_launch(self, total_chunks: int) -> tuple[int, int]:
         """(workgroups, chunks per claim) for a batch run whose queue holds
@@ -116,7 +120,7 @@ class Autotuner:
         with self._lock:
             if key + "|wg" in self.cache and key + "|claim" in self.cache:
                 return self.cache[key + "|wg"], self.cache[key + "|claim"]
-        chunks = min(1 << _pow2_class(max(total_chunks, 1)), 1 << 14)
+        chunks = 1 << min(_pow2_class(max(total_chunks, 1)), self.BATCH_MAX_CLASS)
         dev = torch.device("cuda")
         dense = torch.randn((8 * chunks, 512), dtype=torch.float64, device=dev)
         out = api.BlazMatrix.empty(8 * chunks, 512, dev)

@@ -1,6 +1,8 @@
 """Host-side checks of libblaz that need no GPU: the library loads, exports
 every entry point include/libblaz.h declares, and rejects invalid arguments
-before enqueuing anything (these calls never reach the HIP runtime).
+before enqueuing anything (these calls never reach the HIP runtime; one
+test, skipped where a GPU is present, checks that a launch the runtime
+refuses comes back as BLAZ_ERR_HIP).
 Also checks of the parity rules themselves."""
 import ctypes
 import os
@@ -338,6 +340,25 @@ def test_tie_classifier():
         compare_compressed((f, s, phi, codes_g), (f, s, phi, codes_o), code_x, np.array([20.5, 20.5]))
     with pytest.raises(AssertionError):    # s must be bit-exact
         compare_compressed((f, s + 1e-16 * 4, phi, codes), (f, s, phi, codes), code_x, np.array([20.5, 20.5]))
+
+
+def test_launch_refused_by_the_runtime_is_reported_as_hip_error(L):
+    """Where the HIP runtime cannot launch (here: no GPU), a call whose
+    arguments pass validation returns BLAZ_ERR_HIP, and the binding turns it
+    into a BlazError naming the status.  The fake addresses are never
+    dereferenced: the launch itself is what fails.  Skipped where a GPU is
+    present, since there the launch would run on the fake addresses."""
+    import torch
+    from paper_2202_13007_amd._lib import BLAZ_OK, BlazError, check
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present: the launch would run on fake addresses")
+    x, z = mat(64, 64, 1 << 30), mat(64, 64, 1 << 32)
+    st = L.blaz_scale(B(x), 2.0, B(z), None)
+    assert st == -8 and L.blaz_status_string(st).decode() != ""
+    assert L.blaz_add(B(x), B(x), B(z), None) == -8
+    with pytest.raises(BlazError, match="BLAZ_ERR_HIP"):
+        check(st, "blaz_scale")
+    check(BLAZ_OK, "nothing")  # BLAZ_OK passes
 
 
 def test_bench_refuses_more_than_one_gpu():

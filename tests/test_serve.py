@@ -4,8 +4,9 @@ GPU tests check every request's result against the FP64 oracle under the
 parity rules (the resident operands are the oracle's records, uploaded), and
 that it is the same alone and in the mix (bit for bit: the batched paths run
 the same device code); that a tiny
-budget forces queueing without exceeding it, and that a request larger than
-the budget is refused before anything runs.  The CPU test checks the
+budget forces queueing without exceeding it, that queued requests past a
+deadline are cancelled while the loop keeps serving the rest, and that a
+request larger than the budget is refused before anything runs.  The CPU test checks the
 request generator."""
 import numpy as np
 import pytest
@@ -168,6 +169,38 @@ def test_tiny_budget_forces_queueing():
     for r in reqs:
         orc.check(r, r.result, "fp64")
         assert _same(r.result, _alone(pool, r, "fp64")), (r.rid, r.op, r.n)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("mode", ["batched", "plain"])
+def test_queued_requests_past_their_deadline_are_cancelled(mode):
+    """200 requests arrive 20 us apart on average, faster than they are
+    served within a budget of the largest one, with a 0.2 ms deadline:
+    requests still queued past the deadline are dropped, the loop keeps
+    serving later arrivals, and every request it did run matches the oracle
+    (and its run alone)."""
+    from paper_2202_13007_amd.serve import OperandPool, Server, output_bytes
+    A, B = _setup(256)
+    reqs = make_requests(200, rate=50000.0, seed=14, n_min=8, n_max=256)
+    biggest = max(output_bytes(r.op, r.n, "fp64") for r in reqs)
+    pool = OperandPool(A, B, [r.n for r in reqs])
+    orc = OracleOperands(pool, [r.n for r in reqs])
+    srv = Server(pool, hbm_budget=biggest, keep_results=True)
+    rep = srv.run(reqs, mode, deadline_ms=0.2)
+    served = [r for r in reqs if not r.cancelled]
+    print(f"{mode}: {rep['served']} served, {rep['cancelled']} cancelled, {rep['ticks']} ticks")
+    assert rep["served"] == len(served) >= 1 and rep["cancelled"] >= 1
+    assert rep["served"] + rep["cancelled"] == len(reqs)
+    assert srv.peak_used <= biggest
+    first_cancel = min(r.arrival for r in reqs if r.cancelled)
+    assert any(r.arrival > first_cancel for r in served)  # served after a cancellation
+    for r in reqs:
+        if r.cancelled:
+            assert r.result is None and np.isnan(r.done)
+        else:
+            assert np.isfinite(r.done) and r.done >= r.arrival
+            orc.check(r, r.result, "fp64")
+            assert _same(r.result, _alone(pool, r, "fp64")), (r.rid, r.op, r.n)
 
 
 @pytest.mark.gpu
