@@ -342,6 +342,35 @@ def test_tie_classifier():
         compare_compressed((f, s + 1e-16 * 4, phi, codes), (f, s, phi, codes), code_x, np.array([20.5, 20.5]))
 
 
+def test_header_is_c99_and_links(L, tmp_path):
+    """include/libblaz.h compiles as C99, every function it declares links
+    against libblaz.so from a C program, and the host-only calls run."""
+    import shutil
+    import subprocess
+    from paper_2202_13007_amd import _lib
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    names = declared_functions()
+    src = tmp_path / "use_header.c"
+    src.write_text("#include <stdio.h>\n#include \"libblaz.h\"\n"
+                   "int main(void) {\n"
+                   + "".join(f"    printf(\"%p\\n\", (void *)&{n});\n" for n in names)
+                   + "    if (blaz_block_count(16, 24) != 6) return 1;\n"
+                   "    if (blaz_compressed_bytes(16, 24) != 6 * 45) return 2;\n"
+                   "    printf(\"%s\\n\", blaz_status_string(BLAZ_ERR_SHAPE));\n"
+                   "    return 0;\n}\n")
+    exe = tmp_path / "use_header"
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    cmd = [gcc, "-std=c99", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+           "-I", "/opt/rocm/include", str(src), "-o", str(exe), "-L", libdir, "-lblaz", f"-Wl,-rpath,{libdir}"]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, (r.returncode, r.stderr[-500:])
+    assert len(r.stdout.splitlines()) == len(names) + 1
+
+
 def test_launch_refused_by_the_runtime_is_reported_as_hip_error(L):
     """Where the HIP runtime cannot launch (here: no GPU), a call whose
     arguments pass validation returns BLAZ_ERR_HIP, and the binding turns it
