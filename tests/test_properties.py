@@ -1,0 +1,124 @@
+"""Property tests on small random matrices (hypothesis): invariants of the
+oracle's records and of Algorithms 1 and 2 on the CPU, and the GPU's
+compress / add / scale against the oracle on the same random inputs.
+
+Inputs are drawn per example from a structure (Gaussian, a single non-zero
+per block, constant blocks, affine ramps, huge or tiny magnitudes, mixed
+signs of slope) and a seed; hypothesis shrinks over those two choices."""
+import numpy as np
+import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
+
+import oracle
+from oracle.parity import TIE_RATE_MAX, assert_same_compressed, compare_compressed
+
+STRUCTURES = ("normal", "sparse", "constant", "affine", "huge", "tiny", "sign_mixed")
+
+
+def make_matrix(structure, seed, br, bc):
+    rng = np.random.default_rng(seed)
+    r, c = 8 * br, 8 * bc
+    if structure == "normal":
+        return rng.standard_normal((r, c))
+    if structure == "sparse":  # one non-zero per block: sparse Delta
+        A = np.zeros((r, c))
+        for I in range(br):
+            for J in range(bc):
+                A[8 * I + rng.integers(8), 8 * J + rng.integers(8)] = rng.standard_normal() * 10.0 ** rng.integers(-3, 4)
+        return A
+    if structure == "constant":
+        return np.kron(rng.standard_normal((br, bc)), np.ones((8, 8)))
+    if structure == "affine":
+        i, j = np.mgrid[0:r, 0:c]
+        return rng.standard_normal() + rng.standard_normal() * i + rng.standard_normal() * j
+    if structure == "huge":
+        return rng.standard_normal((r, c)) * 1e150
+    if structure == "tiny":
+        return rng.standard_normal((r, c)) * 1e-150
+    # alternating sign of the slope between neighbouring blocks
+    return np.cumsum(rng.standard_normal((r, c)), axis=1) * np.where((np.arange(c) // 8) % 2, -1.0, 1.0)
+
+
+matrices = st.tuples(st.sampled_from(STRUCTURES), st.integers(0, 2 ** 32 - 1), st.integers(1, 3), st.integers(1, 3))
+CPU = settings(max_examples=60, deadline=None, database=None, suppress_health_check=[HealthCheck.too_slow])
+
+
+@CPU
+@given(matrices)
+def test_records_are_well_formed(m):
+    A = make_matrix(*m)
+    x = oracle.compress(A)
+    blocks = A.reshape(A.shape[0] // 8, 8, A.shape[1] // 8, 8).transpose(0, 2, 1, 3).reshape(-1, 64)
+    assert np.array_equal(x.f.view(np.uint64), blocks[:, 0].copy().view(np.uint64))  # f = X_00, exactly
+    assert np.all(np.isfinite(x.s)) and np.all(x.s >= 0)
+    assert np.all(x.phi >= 1)
+    assert np.all(np.abs(x.codes.astype(int)) <= 127)
+    flat = np.all(blocks == blocks[:, :1], axis=1)  # constant blocks: no slope, no codes
+    assert np.all(x.s[flat] == 0) and not np.any(x.codes[flat])
+
+
+@CPU
+@given(matrices, matrices)
+def test_add_commutes_and_a_block_minus_itself_is_zero(m1, m2):
+    A = make_matrix(*m1)
+    B = make_matrix(m2[0], m2[1], m1[2], m1[3])
+    x, y = oracle.compress(A), oracle.compress(B)
+    xy, yx = oracle.add(x, y), oracle.add(y, x)
+    assert_same_compressed((xy.f, xy.s, xy.phi, xy.codes), (yx.f, yx.s, yx.phi, yx.codes), "x + y vs y + x")
+    z = oracle.add(x, oracle.scale(x, -1.0))
+    assert np.all(z.f == 0) and np.all(z.s == 0) and not np.any(z.codes)
+    assert np.all(z.phi >= 1)
+
+
+@CPU
+@given(matrices, st.floats(-1e3, 1e3, allow_nan=False).filter(lambda c: c != 0))
+def test_scale_keeps_codes_and_scales_the_block(m, c):
+    A = make_matrix(*m)
+    x = oracle.compress(A)
+    z = oracle.scale(x, c)
+    assert np.array_equal(z.codes, x.codes) and np.array_equal(z.phi, x.phi)
+    assert np.array_equal(z.f, c * x.f) and np.array_equal(z.s, c * x.s)
+    Dx, Dz = oracle.decompress(x), oracle.decompress(z)
+    scale_ref = np.abs(c * Dx).max() + 1e-300
+    assert np.abs(Dz - c * Dx).max() <= 1e-12 * scale_ref
+
+
+@CPU
+@given(matrices)
+def test_phi_halves_towards_one_under_repeated_self_addition(m):
+    x = oracle.compress(make_matrix(*m))
+    for _ in range(9):
+        z = oracle.add(x, x)
+        assert np.array_equal(z.phi, np.maximum(1, x.phi.astype(int) * x.phi // (2 * x.phi.astype(int))).astype(np.uint8))
+        assert np.all(np.abs(z.codes.astype(int)) <= 127)
+        x = z
+    assert np.all(x.phi == 1)
+
+
+# --------------------------------------------------------------------------
+# GPU against the oracle on the same random inputs
+# --------------------------------------------------------------------------
+
+GPU = settings(max_examples=40, deadline=None, database=None, suppress_health_check=[HealthCheck.too_slow])
+
+
+@pytest.mark.gpu
+@GPU
+@given(matrices, st.floats(-1e3, 1e3, allow_nan=False))
+def test_gpu_compress_add_scale_match_the_oracle(m, c):
+    import torch
+    import paper_2202_13007_amd as blaz
+    A = make_matrix(*m)
+    B = make_matrix(m[0], m[1] ^ 0x5A5A, m[2], m[3])
+    o, (_, code_x, phi_x) = oracle.compress(A, with_debug=True)
+    g = blaz.compress(torch.from_numpy(A).cuda())
+    ties = compare_compressed(g.to_host(), (o.f, o.s, o.phi, o.codes), code_x, phi_x, f"compress {m}")
+    assert ties <= max(1, TIE_RATE_MAX * o.codes.size), ties
+    ob = oracle.compress(B)
+    x = blaz.BlazMatrix.from_host(o.rows, o.cols, o.f, o.s, o.phi, o.codes)
+    y = blaz.BlazMatrix.from_host(ob.rows, ob.cols, ob.f, ob.s, ob.phi, ob.codes)
+    s = oracle.add(o, ob)
+    assert_same_compressed(blaz.add(x, y).to_host(), (s.f, s.s, s.phi, s.codes), f"add {m}")
+    k = oracle.scale(o, c)
+    assert_same_compressed(blaz.scale(x, c).to_host(), (k.f, k.s, k.phi, k.codes), f"scale {m} by {c}")
