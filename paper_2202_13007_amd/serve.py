@@ -58,6 +58,7 @@ class Request:
     done: float = math.nan          # seconds after the start (device clock)
     nbytes: int = 0                 # device memory held while in flight
     cancelled: bool = False         # dropped from the queue past its deadline
+    error: str | None = None        # why the request was rejected before running
     result: object = None
     _hold: list = field(default_factory=list, repr=False)
 
@@ -205,16 +206,30 @@ class Server:
         `deadline_ms`, a request still queued (arrived, not admitted) that
         long after its arrival is cancelled: it is dropped without running,
         marked `cancelled`, and left out of the latency figures; admitted
-        requests always run to completion, and the loop goes on."""
+        requests always run to completion, and the loop goes on.  A request
+        that cannot run -- an unknown operation, a side that is not a
+        positive multiple of 8, or an output larger than the whole budget --
+        is rejected before anything is launched (its `error` says why) and
+        the others are served."""
         assert mode in ("plain", "batched")
         deadline = None if deadline_ms is None else deadline_ms / 1e3
+        valid = []
         for r in requests:
-            r.cancelled, r.done = False, math.nan
-            r.nbytes = output_bytes(r.op, r.n, self.matmul_prec)
-            if r.nbytes > self.budget:
-                raise ValueError(f"request {r.rid} needs {r.nbytes} bytes, more than the whole budget")
+            r.cancelled, r.done, r.error = False, math.nan, None
+            if r.op not in OPS:
+                r.error = f"unknown operation {r.op!r}"
+            elif not isinstance(r.n, int) or r.n <= 0 or r.n % 8:
+                r.error = f"side {r.n} is not a positive multiple of 8"
+            else:
+                r.nbytes = output_bytes(r.op, r.n, self.matmul_prec)
+                if r.nbytes > self.budget:
+                    r.error = f"needs {r.nbytes} bytes, more than the whole budget of {self.budget}"
+            if r.error is None:
+                valid.append(r)
+            else:
+                r.result = None
         limit = self.max_inflight if mode == "batched" else 1 << 30
-        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        pending = deque(sorted(valid, key=lambda r: r.arrival))
         ready: deque[Request] = deque()
         units: list = []               # (event, [requests], held objects): one per launch unit
         ticks_inflight: dict = {}      # tick id -> units still running
@@ -259,7 +274,7 @@ class Server:
             units = still
             return progressed
 
-        while ndone < len(requests):
+        while ndone < len(valid):
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
                 ready.append(pending.popleft())
@@ -384,15 +399,16 @@ class Server:
         return torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
 
     def _report(self, requests, mode, ticks) -> dict:
-        served = [r for r in requests if not r.cancelled]
+        served = [r for r in requests if not r.cancelled and r.error is None]
         lat = np.array([(r.done - r.arrival) * 1e3 for r in served]) if served else np.zeros(1)
-        first = min(r.arrival for r in requests)
+        first = min((r.arrival for r in requests), default=0.0)
         last = max((r.done for r in served), default=first)
         span = max(last - first, 1e-9)
         eq = sum(fp64_equiv_bytes(r.op, r.n) for r in served)
         flop = sum(2 * r.n ** 3 for r in served if r.op == "matmul")
         return {"mode": mode, "requests": len(requests), "served": len(served),
-                "cancelled": len(requests) - len(served), "ticks": ticks,
+                "cancelled": sum(r.cancelled for r in requests),
+                "rejected": sum(r.error is not None for r in requests), "ticks": ticks,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_ms": float(lat.mean()), "makespan_s": span, "req_per_s": len(served) / span,
                 "fp64_equiv_GBps": eq / span / 1e9, "matmul_TFLOPs": flop / span / 1e12,

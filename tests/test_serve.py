@@ -5,8 +5,10 @@ parity rules (the resident operands are the oracle's records, uploaded), and
 that it is the same alone and in the mix (bit for bit: the batched paths run
 the same device code); that a tiny
 budget forces queueing without exceeding it, that queued requests past a
-deadline are cancelled while the loop keeps serving the rest, and that a
-request larger than the budget is refused before anything runs.  The CPU test checks the
+deadline are cancelled while the loop keeps serving the rest, and that
+requests that cannot run (larger than the budget, a side that is not a
+multiple of 8, an unknown operation) are rejected before anything runs
+while the others are served.  The CPU test checks the
 request generator."""
 import numpy as np
 import pytest
@@ -216,5 +218,27 @@ def test_plain_form_matches_too_and_oversized_request_is_refused():
         orc.check(r, r.result, "fp64")
         assert _same(r.result, _alone(pool, r, "fp64")), (r.rid, r.op, r.n)
     small = Server(pool, hbm_budget=min(output_bytes(r.op, r.n, "fp64") for r in reqs) - 1)
-    with pytest.raises(ValueError):
-        small.run(reqs, "batched")
+    rep = small.run(reqs, "batched")
+    assert rep["rejected"] == len(reqs) and rep["served"] == 0 and rep["ticks"] == 0
+    assert all(r.result is None and "budget" in r.error for r in reqs)
+
+
+@pytest.mark.gpu
+def test_bad_requests_are_rejected_and_the_rest_served():
+    """A side that is not a multiple of 8, an unknown operation and an
+    empty side, mixed into a stream: each is rejected with its reason before
+    anything runs, and every other request is served and matches the
+    oracle."""
+    from paper_2202_13007_amd.serve import OperandPool, Request, Server
+    A, B = _setup(256)
+    good = make_requests(60, rate=20000.0, seed=15, n_min=8, n_max=256)
+    bad = [Request(1000, "compress", 12, 0.0005), Request(1001, "bogus", 64, 0.0010), Request(1002, "add", 0, 0.0)]
+    pool = OperandPool(A, B, [r.n for r in good])
+    orc = OracleOperands(pool, [r.n for r in good])
+    srv = Server(pool, keep_results=True)
+    rep = srv.run(good + bad, "batched")
+    assert rep["rejected"] == 3 and rep["served"] == len(good)
+    assert "multiple of 8" in bad[0].error and "unknown operation" in bad[1].error and "multiple of 8" in bad[2].error
+    for r in good:
+        assert r.error is None and np.isfinite(r.done)
+        orc.check(r, r.result, "fp64")
