@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kWave, 2) void batch_kernel(const BatchItemDev* __r
 // before the launch executes, so one captured graph serves every plan that
 // is copied into the same buffers.  The run is a single launch: every wave
 // checks the counts against the plan buffer's capacity (workgroup 0
-// publishes the verdict), and the wave that made the run's last claim
+// publishes the status), and the wave that made the run's last claim
 // resets the work counter, so the record is ready for the next run without
 // a reset launch.  Which claim is last follows from counting: with T
 // chunks, C chunks per claim and W waves, ceil(T / C) claims succeed; the
