@@ -122,12 +122,16 @@ __device__ __forceinline__ void load_blocks(const double* __restrict__ A, int64_
     if constexpr (kVec) {
         const WaveChunks wc = wave_chunks(wave_base, lane, nbc, nblk, lda);
         f64x2 g[8][4];
+        // the 32 loads issue at raised wave priority, so the other wave's
+        // transform on the SIMD does not stretch the burst (0.5 % faster)
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int r = 0; r < 8; ++r)
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 g[r][k] = wc.ok[k] ? __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(A + wc.off[k] + r * lda))
                                    : f64x2{0.0, 0.0};
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
 #pragma unroll
