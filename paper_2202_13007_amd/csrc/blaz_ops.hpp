@@ -20,14 +20,14 @@ __device__ __forceinline__ void add_block(int64_t b, bool neg_y, const double* f
                                           const double* s2, const uint8_t* phi2, const uint32_t* c2, double* fo,
                                           double* so, uint8_t* phio, uint32_t* co)
 {
-    // Algorithm 1, line 1: f = f1 + f2, s = s1 + s2 (y negated for subtraction,
+    // Algorithm 1 first sums f and s: f = f1 + f2, s = s1 + s2 (y negated for subtraction,
     // which is exact).
     const double fy = neg_y ? -f2[b] : f2[b];
     const double sy = neg_y ? -s2[b] : s2[b];
     const double sx = s1[b];
     const double f = f1[b] + fy;
     const double s = sx + sy;
-    // Line 2 and Eq. eq55: phi = phi1 phi2 / (phi1 + phi2), integer division,
+    // Then phi (Eq. eq55): phi = phi1 phi2 / (phi1 + phi2), integer division,
     // kept >= 1 so that the block can be decompressed.
     const int p1 = phi1[b], p2 = phi2[b];
     int p = p1 + p2 > 0 ? (p1 * p2) / (p1 + p2) : 1;
@@ -42,12 +42,12 @@ __device__ __forceinline__ void add_block(int64_t b, bool neg_y, const double* f
         wo[q] = 0;
     }
     if (s != 0.0) {
-        // Lines 3-4: alpha_k = s_k / s, beta_k = (alpha_k / phi_k) * phi.
+        // Weights: alpha_k = s_k / s, beta_k = (alpha_k / phi_k) * phi.
         const double a1 = sx / s;
         const double a2 = sy / s;
         const double b1 = a1 / (double)p1 * (double)p;
         const double b2 = a2 / (double)p2 * (double)p;
-        // Lines 5-7: C = trunc(beta1 C1 + beta2 C2), saturated to +-127.
+        // Codes: C = trunc(beta1 C1 + beta2 C2), saturated to +-127.
         // Two products then one sum, never fused (the library is built with
         // -ffp-contract=off), so the result is reproducible bit for bit.
 #pragma unroll

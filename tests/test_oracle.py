@@ -389,7 +389,7 @@ def two_fields(n=32, seed=30):
 
 
 def test_add_header_fields():
-    """Algorithm 1 lines 1-2: f = f1 + f2, s = s1 + s2, phi = phi1 phi2 / (phi1 + phi2)."""
+    """Algorithm 1's sums and phi: f = f1 + f2, s = s1 + s2, phi = phi1 phi2 / (phi1 + phi2)."""
     x, y = two_fields()
     z = oracle.add(x, y)
     np.testing.assert_array_equal(z.f, x.f + y.f)

@@ -7,11 +7,11 @@ per block, constant blocks, affine ramps, huge or tiny magnitudes, mixed
 signs of slope) and a seed; hypothesis shrinks over those two choices."""
 import numpy as np
 import pytest
-from hypothesis import HealthCheck, given, settings
+from hypothesis import HealthCheck, example, given, settings
 from hypothesis import strategies as st
 
 import oracle
-from oracle.parity import TIE_RATE_MAX, assert_same_compressed, compare_compressed
+from oracle.parity import assert_same_compressed, compare_compressed, near_integer
 
 STRUCTURES = ("normal", "sparse", "constant", "affine", "huge", "tiny", "sign_mixed")
 
@@ -106,6 +106,7 @@ GPU = settings(max_examples=40, deadline=None, database=None, suppress_health_ch
 @pytest.mark.gpu
 @GPU
 @given(matrices, st.floats(-1e3, 1e3, allow_nan=False))
+@example(("sparse", 39078084, 1, 1), 0.0)  # a single non-zero: two codes on a boundary
 def test_gpu_compress_add_scale_match_the_oracle(m, c):
     import torch
     import paper_2202_13007_amd as blaz
@@ -114,7 +115,13 @@ def test_gpu_compress_add_scale_match_the_oracle(m, c):
     o, (_, code_x, phi_x) = oracle.compress(A, with_debug=True)
     g = blaz.compress(torch.from_numpy(A).cuda())
     ties = compare_compressed(g.to_host(), (o.f, o.s, o.phi, o.codes), code_x, phi_x, f"compress {m}")
-    assert ties <= max(1, TIE_RATE_MAX * o.codes.size), ties
+    # Structured blocks (one non-zero, affine ramps) have exact rational
+    # coefficients that can sit on a truncation boundary, so ties are bounded
+    # by the number of such values, as for the designed blocks of the parity
+    # tests (compare_compressed has already checked each one is a boundary tie).
+    with np.errstate(invalid="ignore"):
+        boundary = int((near_integer(code_x) & (code_x != 0)).sum() + near_integer(phi_x).sum())
+    assert ties <= boundary, (ties, boundary)
     ob = oracle.compress(B)
     x = blaz.BlazMatrix.from_host(o.rows, o.cols, o.f, o.s, o.phi, o.codes)
     y = blaz.BlazMatrix.from_host(ob.rows, ob.cols, ob.f, ob.s, ob.phi, ob.codes)
