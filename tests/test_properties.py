@@ -100,7 +100,10 @@ def test_phi_halves_towards_one_under_repeated_self_addition(m):
 # GPU against the oracle on the same random inputs
 # --------------------------------------------------------------------------
 
-GPU = settings(max_examples=40, deadline=None, database=None, suppress_health_check=[HealthCheck.too_slow])
+# The GPU draws are derandomized (the same 40 examples on every run) so that
+# a GPU run is reproducible; the CPU properties above draw afresh each time.
+GPU = settings(max_examples=40, deadline=None, database=None, derandomize=True,
+               suppress_health_check=[HealthCheck.too_slow])
 
 
 @pytest.mark.gpu
