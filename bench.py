@@ -275,7 +275,11 @@ def matmul_leg(blaz, torch, workload_inputs):
     legs = {}
     runs = [(p, (lambda p=p: blaz.matmul(g, dB, out=outs[p], prec=p, workspace=ws))) for p in ("fp64", "fp32", "bf16x3")]
     runs.append(("plain", lambda: torch.matmul(Ad, dB, out=outs["plain"])))
-    peaks = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3, "plain": 78.6}
+    # the vendor library's plain BF16 product (FP32 output) of the rounded
+    # operands: the MFMA work rate a single BF16 GEMM reaches on this part
+    aB, bB = Ad.to(torch.bfloat16).contiguous(), dB.to(torch.bfloat16).contiguous()
+    runs.append(("vendor_bf16", lambda: torch.mm(aB, bB, out_dtype=torch.float32)))
+    peaks = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3, "plain": 78.6, "vendor_bf16": 2500.0}
     # three interleaved rounds of 5 back-to-back launches per variant, median
     # round: the clock drifts with the power draw of FP64 matrix work, so a
     # fixed order would favour whichever variant runs in the better state
@@ -319,7 +323,10 @@ def matmul_leg(blaz, torch, workload_inputs):
     method = torch.linalg.norm(ref - exact).item() / torch.linalg.norm(exact).item()
     legs["plain"]["what"] = "torch FP64 matmul of the decompressed A"
     legs["bf16x3"]["mfma_frac_note"] = "against 1/3 of the BF16 peak (three products)"
-    del outs, exact, ws
+    legs["vendor_bf16"]["what"] = ("one BF16 x BF16 -> FP32 product of the rounded operands by the vendor library "
+                                   "(torch.mm): the MFMA work rate of a plain BF16 GEMM, for reference")
+    legs["bf16x3"]["mfma_work_vs_vendor_bf16"] = round(3 * legs["bf16x3"]["TFLOPs"] / legs["vendor_bf16"]["TFLOPs"], 4)
+    del outs, exact, ws, aB, bB
     return {"legs": legs, "method_rel_err": float(f"{method:.3e}"),
             "note": "TFLOPs count 2 n^3 useful flops; times include decompressing A and preparing B",
             "dots": dot_leg(blaz, torch, g, Ad, dB, torch.from_numpy(Vm).cuda())}
