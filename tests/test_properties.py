@@ -1,6 +1,7 @@
 """Property tests on small random matrices (hypothesis): invariants of the
 oracle's records and of Algorithms 1 and 2 on the CPU, and the GPU's
-compress / add / scale against the oracle on the same random inputs.
+compress / add / scale, decompress, dots and products against the oracle on
+the same random inputs.
 
 Inputs are drawn per example from a structure (Gaussian, a single non-zero
 per block, constant blocks, affine ramps, huge or tiny magnitudes, mixed
@@ -132,3 +133,36 @@ def test_gpu_compress_add_scale_match_the_oracle(m, c):
     assert_same_compressed(blaz.add(x, y).to_host(), (s.f, s.s, s.phi, s.codes), f"add {m}")
     k = oracle.scale(o, c)
     assert_same_compressed(blaz.scale(x, c).to_host(), (k.f, k.s, k.phi, k.codes), f"scale {m} by {c}")
+
+
+@pytest.mark.gpu
+@GPU
+@given(matrices, st.integers(1, 3))
+def test_gpu_decompress_dot_matmul_match_the_oracle(m, bn):
+    """The partly decompressed operations on the same structures: the GPU
+    rebuilds, dots and products of the oracle's records (uploaded, so that
+    no compression tie enters) against the oracle's, within the parity rules
+    (1e-12 of each block's largest value, 1e-12 of sum |x_k y_k|)."""
+    import torch
+    import paper_2202_13007_amd as blaz
+    from oracle.parity import assert_blocks_close, assert_dots_close
+    A = make_matrix(*m)
+    B = make_matrix(m[0], m[1] ^ 0x3C3C, m[3], bn)  # rows of B = columns of A
+    o, ob = oracle.compress(A), oracle.compress(B)
+    x = blaz.BlazMatrix.from_host(o.rows, o.cols, o.f, o.s, o.phi, o.codes)
+    y = blaz.BlazMatrix.from_host(ob.rows, ob.cols, ob.f, ob.s, ob.phi, ob.codes)
+    Xd, Yd = oracle.decompress(o), oracle.decompress(ob)
+    assert_blocks_close(blaz.decompress(x).cpu().numpy(), Xd, what=f"decompress {m}")
+
+    # every line of X against every column of Y
+    rows, cols = np.meshgrid(np.arange(o.rows), np.arange(ob.cols), indexing="ij")
+    xrow, ycol = rows.ravel().astype(np.int64), cols.ravel().astype(np.int64)
+    mag = (np.abs(Xd)[xrow] * np.abs(Yd).T[ycol]).sum(axis=1)
+    got = blaz.dot(x, torch.from_numpy(xrow).cuda(), y, torch.from_numpy(ycol).cuda()).cpu().numpy()
+    assert_dots_close(got, oracle.dot(o, xrow, ob, ycol), mag, what=f"dot {m}")
+
+    absprod = np.abs(Xd) @ np.abs(Yd)
+    for b, ref, what in ((y, oracle.matmul(o, ob), "compressed B"),
+                         (torch.from_numpy(Yd).cuda(), oracle.matmul(o, bdense=Yd), "dense B")):
+        C = blaz.matmul(x, b).cpu().numpy()
+        assert_dots_close(C.ravel(), ref.ravel(), absprod.ravel(), what=f"matmul {what} {m}")
