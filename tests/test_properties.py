@@ -1,7 +1,7 @@
 """Property tests on small random matrices (hypothesis): invariants of the
 oracle's records and of Algorithms 1 and 2 on the CPU, and the GPU's
-compress / add / scale, decompress, dots and products against the oracle on
-the same random inputs.
+compress / add / scale, decompress, dots and products, and the tunable rate
+against the oracle on the same random inputs.
 
 Inputs are drawn per example from a structure (Gaussian, a single non-zero
 per block, constant blocks, affine ramps, huge or tiny magnitudes, mixed
@@ -166,3 +166,31 @@ def test_gpu_decompress_dot_matmul_match_the_oracle(m, bn):
                          (torch.from_numpy(Yd).cuda(), oracle.matmul(o, bdense=Yd), "dense B")):
         C = blaz.matmul(x, b).cpu().numpy()
         assert_dots_close(C.ravel(), ref.ravel(), absprod.ravel(), what=f"matmul {what} {m}")
+
+
+@pytest.mark.gpu
+@GPU
+@given(matrices, st.integers(1, 8), st.floats(-1e3, 1e3, allow_nan=False))
+def test_gpu_tunable_rate_matches_the_oracle(m, lines, c):
+    """The tunable rate (L kept lines) on the same structures: compress (ties
+    bounded by the boundary values), rebuild, add and scale of the oracle's
+    records against the oracle."""
+    import torch
+    import paper_2202_13007_amd as blaz
+    from oracle.parity import assert_blocks_close
+    A = make_matrix(*m)
+    B = make_matrix(m[0], m[1] ^ 0x0F0F, m[2], m[3])
+    o, (code_x, phi_x) = oracle.compress_lines(A, lines, with_debug=True)
+    g = blaz.compress(torch.from_numpy(A).cuda(), lines=lines)
+    ties = compare_compressed(g.to_host(), (o.f, o.s, o.phi, o.codes), code_x, phi_x, f"compress L={lines} {m}")
+    with np.errstate(invalid="ignore"):
+        boundary = int((near_integer(code_x) & (code_x != 0)).sum() + near_integer(phi_x).sum())
+    assert ties <= boundary, (ties, boundary)
+    ob = oracle.compress_lines(B, lines)
+    x = blaz.BlazMatrix.from_host(o.rows, o.cols, o.f, o.s, o.phi, o.codes, lines=lines)
+    y = blaz.BlazMatrix.from_host(ob.rows, ob.cols, ob.f, ob.s, ob.phi, ob.codes, lines=lines)
+    assert_blocks_close(blaz.decompress(x).cpu().numpy(), oracle.decompress(o), what=f"decompress L={lines} {m}")
+    s = oracle.add(o, ob)
+    assert_same_compressed(blaz.add(x, y).to_host(), (s.f, s.s, s.phi, s.codes), f"add L={lines} {m}")
+    k = oracle.scale(o, c)
+    assert_same_compressed(blaz.scale(x, c).to_host(), (k.f, k.s, k.phi, k.codes), f"scale L={lines} {m} by {c}")
