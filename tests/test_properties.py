@@ -1,7 +1,7 @@
 """Property tests on small random matrices (hypothesis): invariants of the
 oracle's records and of Algorithms 1 and 2 on the CPU, and the GPU's
-compress / add / scale, decompress, dots and products, and the tunable rate
-against the oracle on the same random inputs.
+compress / add / scale, decompress, dots and products, the tunable rate and
+the mixed-precision transform against the oracle on the same random inputs.
 
 Inputs are drawn per example from a structure (Gaussian, a single non-zero
 per block, constant blocks, affine ramps, huge or tiny magnitudes, mixed
@@ -194,3 +194,19 @@ def test_gpu_tunable_rate_matches_the_oracle(m, lines, c):
     assert_same_compressed(blaz.add(x, y).to_host(), (s.f, s.s, s.phi, s.codes), f"add L={lines} {m}")
     k = oracle.scale(o, c)
     assert_same_compressed(blaz.scale(x, c).to_host(), (k.f, k.s, k.phi, k.codes), f"scale L={lines} {m} by {c}")
+
+
+@pytest.mark.gpu
+@GPU
+@given(matrices, st.sampled_from(["fp32", "bf16x3"]))
+def test_gpu_mixed_precision_transform_matches_the_oracle(m, prec):
+    """The transform on the matrix cores on the same structures: f and s
+    bit-exact, phi and codes equal to the oracle's except where the oracle's
+    value lies within the arithmetic's error bound of an integer."""
+    import torch
+    import paper_2202_13007_amd as blaz
+    from test_gpu_parity import compare_mixed
+    A = make_matrix(*m)
+    o, (_, code_x, phi_x) = oracle.compress(A, with_debug=True)
+    g = blaz.compress(torch.from_numpy(A).cuda(), prec=prec)
+    compare_mixed(g.to_host(), (o.f, o.s, o.phi, o.codes), code_x, phi_x, prec)
