@@ -1,7 +1,8 @@
 """Property tests on small random matrices (hypothesis): invariants of the
 oracle's records and of Algorithms 1 and 2 on the CPU, and the GPU's
 compress / add / scale, decompress, dots and products, the tunable rate and
-the mixed-precision transform against the oracle on the same random inputs.
+the mixed-precision transform, a persistent batch and the predicted-slope
+input against the oracle on the same random inputs.
 
 Inputs are drawn per example from a structure (Gaussian, a single non-zero
 per block, constant blocks, affine ramps, huge or tiny magnitudes, mixed
@@ -101,6 +102,13 @@ def test_phi_halves_towards_one_under_repeated_self_addition(m):
 # GPU against the oracle on the same random inputs
 # --------------------------------------------------------------------------
 
+def _boundary_values(code_x, phi_x):
+    """Non-zero codes and phi whose value before truncation lies on (within
+    2^-40 of) an integer: the mismatches the tie rule can explain."""
+    with np.errstate(invalid="ignore"):
+        return int((near_integer(code_x) & (code_x != 0)).sum() + near_integer(phi_x).sum())
+
+
 # The GPU draws are derandomized (the same 40 examples on every run) so that
 # a GPU run is reproducible; the CPU properties above draw afresh each time.
 GPU = settings(max_examples=40, deadline=None, database=None, derandomize=True,
@@ -123,8 +131,7 @@ def test_gpu_compress_add_scale_match_the_oracle(m, c):
     # coefficients that can sit on a truncation boundary, so ties are bounded
     # by the number of such values, as for the designed blocks of the parity
     # tests (compare_compressed has already checked each one is a boundary tie).
-    with np.errstate(invalid="ignore"):
-        boundary = int((near_integer(code_x) & (code_x != 0)).sum() + near_integer(phi_x).sum())
+    boundary = _boundary_values(code_x, phi_x)
     assert ties <= boundary, (ties, boundary)
     ob = oracle.compress(B)
     x = blaz.BlazMatrix.from_host(o.rows, o.cols, o.f, o.s, o.phi, o.codes)
@@ -183,8 +190,7 @@ def test_gpu_tunable_rate_matches_the_oracle(m, lines, c):
     o, (code_x, phi_x) = oracle.compress_lines(A, lines, with_debug=True)
     g = blaz.compress(torch.from_numpy(A).cuda(), lines=lines)
     ties = compare_compressed(g.to_host(), (o.f, o.s, o.phi, o.codes), code_x, phi_x, f"compress L={lines} {m}")
-    with np.errstate(invalid="ignore"):
-        boundary = int((near_integer(code_x) & (code_x != 0)).sum() + near_integer(phi_x).sum())
+    boundary = _boundary_values(code_x, phi_x)
     assert ties <= boundary, (ties, boundary)
     ob = oracle.compress_lines(B, lines)
     x = blaz.BlazMatrix.from_host(o.rows, o.cols, o.f, o.s, o.phi, o.codes, lines=lines)
@@ -210,3 +216,45 @@ def test_gpu_mixed_precision_transform_matches_the_oracle(m, prec):
     o, (_, code_x, phi_x) = oracle.compress(A, with_debug=True)
     g = blaz.compress(torch.from_numpy(A).cuda(), prec=prec)
     compare_mixed(g.to_host(), (o.f, o.s, o.phi, o.codes), code_x, phi_x, prec)
+
+
+
+@pytest.mark.gpu
+@GPU
+@given(matrices, st.floats(-1e3, 1e3, allow_nan=False))
+def test_gpu_batch_and_predicted_input_match_the_oracle(m, c):
+    """One persistent batch (compress, add, scale, decompress) and the
+    predicted-slope transform input on the same structures, against the
+    oracle under the parity rules."""
+    import torch
+    import paper_2202_13007_amd as blaz
+    from oracle.parity import assert_blocks_close
+    A = make_matrix(*m)
+    B = make_matrix(m[0], m[1] ^ 0x7E7E, m[2], m[3])
+    o, (_, code_x, phi_x) = oracle.compress(A, with_debug=True)
+    ob = oracle.compress(B)
+    x = blaz.BlazMatrix.from_host(o.rows, o.cols, o.f, o.s, o.phi, o.codes)
+    y = blaz.BlazMatrix.from_host(ob.rows, ob.cols, ob.f, ob.s, ob.phi, ob.codes)
+    dA = torch.from_numpy(A).cuda()
+    cz, az, sz = (blaz.BlazMatrix.empty(o.rows, o.cols) for _ in range(3))
+    D = torch.empty_like(dA)
+    batch = blaz.Batch()
+    batch.compress(dA, cz)
+    batch.add(x, y, az)
+    batch.scale(x, c, sz)
+    batch.decompress(x, D)
+    batch.plan().run()
+    ties = compare_compressed(cz.to_host(), (o.f, o.s, o.phi, o.codes), code_x, phi_x, f"batch compress {m}")
+    assert ties <= _boundary_values(code_x, phi_x), ties
+    s = oracle.add(o, ob)
+    assert_same_compressed(az.to_host(), (s.f, s.s, s.phi, s.codes), f"batch add {m}")
+    k = oracle.scale(o, c)
+    assert_same_compressed(sz.to_host(), (k.f, k.s, k.phi, k.codes), f"batch scale {m} by {c}")
+    assert_blocks_close(D.cpu().numpy(), oracle.decompress(o), what=f"batch decompress {m}")
+
+    p = torch.empty((o.nblk, 64), dtype=torch.uint8, device="cuda")
+    g = blaz.compress_predicted(dA, psi=p)
+    w, (wpsi, wx, wphi) = oracle.compress(A, with_debug=True, predicted=True)
+    np.testing.assert_array_equal(p.cpu().numpy(), wpsi)
+    ties = compare_compressed(g.to_host(), (w.f, w.s, w.phi, w.codes), wx, wphi, f"predicted {m}")
+    assert ties <= _boundary_values(wx, wphi), ties
