@@ -2,7 +2,9 @@
 oracle's records and of Algorithms 1 and 2 on the CPU, and the GPU's
 compress / add / scale, decompress, dots and products, the tunable rate and
 the mixed-precision transform, a persistent batch and the predicted-slope
-input against the oracle on the same random inputs.
+input against the oracle on the same random inputs, and the product's other
+forms (compressed output, grouped, allocation-free) against the standalone
+product.
 
 Inputs are drawn per example from a structure (Gaussian, a single non-zero
 per block, constant blocks, affine ramps, huge or tiny magnitudes, mixed
@@ -258,3 +260,35 @@ def test_gpu_batch_and_predicted_input_match_the_oracle(m, c):
     np.testing.assert_array_equal(p.cpu().numpy(), wpsi)
     ties = compare_compressed(g.to_host(), (w.f, w.s, w.phi, w.codes), wx, wphi, f"predicted {m}")
     assert ties <= _boundary_values(wx, wphi), ties
+
+
+@pytest.mark.gpu
+@GPU
+@given(matrices, st.integers(1, 3), st.sampled_from(["fp64", "fp32", "bf16x3"]))
+def test_gpu_product_forms_agree(m, bn, prec):
+    """The product's other forms on the same structures, bit for bit: the
+    compressed-output product is the compression of the dense product, and
+    (binary64) a grouped launch and the allocation-free call equal the
+    standalone product."""
+    import torch
+    import paper_2202_13007_amd as blaz
+    A = make_matrix(*m)
+    B = make_matrix(m[0], m[1] ^ 0x1D1D, m[3], bn)
+    x, y = blaz.compress(torch.from_numpy(A).cuda()), blaz.compress(torch.from_numpy(B).cuda())
+    Bd = torch.from_numpy(B).cuda()
+    for b in (y, Bd):
+        dense = blaz.matmul(x, b, prec=prec)
+        got = blaz.matmul_compressed(x, b, prec=prec)
+        assert_same_compressed(got.to_host(), blaz.compress(dense).to_host(), f"matmul_compressed {prec} {m}")
+        if prec == "fp64":
+            st_out = torch.empty_like(dense)
+            blaz.matmul_static(x, b, out=st_out)
+            assert torch.equal(st_out, dense), f"matmul_static {m}"
+    if prec == "fp64":
+        outs = [torch.empty((A.shape[0], B.shape[1]), dtype=torch.float64, device="cuda") for _ in range(2)]
+        grp = blaz.MatmulGroup()
+        grp.add(x, y, outs[0])
+        grp.add(x, Bd, outs[1])
+        grp.plan().run()
+        assert torch.equal(outs[0], blaz.matmul(x, y)), f"group, compressed B {m}"
+        assert torch.equal(outs[1], blaz.matmul(x, Bd)), f"group, dense B {m}"
