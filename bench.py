@@ -943,12 +943,14 @@ def main():
                         "GBps_fp64_equiv": round(bytes_equiv[base] / ms / 1e6, 1),
                         "hbm_frac": round(bytes_actual[base] / ms / 1e6 / HBM_PEAK_GBS, 4)}
 
-    # The same operations on dense binary64 on this GPU (harness only).
+    # The same operations on dense binary64 on this GPU, and a plain read of
+    # the field (harness only).
     C = torch.empty_like(dA)
     plain = {}
     for name, fn, nbytes in (("add", lambda: torch.add(dA, dB, out=C), 24 * n2),
                              ("scale", lambda: torch.mul(dA, 1.7, out=C), 16 * n2),
-                             ("copy", lambda: C.copy_(dA), 16 * n2)):
+                             ("copy", lambda: C.copy_(dA), 16 * n2),
+                             ("sum", lambda: torch.sum(dA), 8 * n2)):
         for _ in range(3):
             fn()
         torch.cuda.synchronize()
@@ -987,7 +989,10 @@ def main():
     roofline = {"kernel": "compress_f64_kernel", "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "copy_2GiB_GBps": round(copy_gbs, 1),
-                "frac_vs_copy": round(achieved / copy_gbs, 4)}
+                "frac_vs_copy": round(achieved / copy_gbs, 4),
+                # a plain streaming read of the same field (torch.sum), for context
+                "sum_read_GBps": plain["sum"]["GBps"],
+                "frac_vs_sum_read": round(achieved / plain["sum"]["GBps"], 4)}
 
     result = {
         "metric": "blaz compress+add GB/s (FP64-equiv) vs plain; matmul TFLOP/s; p99 latency",
