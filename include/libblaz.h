@@ -52,7 +52,9 @@ typedef enum {
     BLAZ_ERR_MISMATCH = -3,    /* operand shapes do not agree                         */
     BLAZ_ERR_ALIGN = -4,       /* a pointer is not aligned to its element type         */
     BLAZ_ERR_ARG = -5,         /* another invalid argument (count < 0 or a dot count
-                                  above 2^27 - 8, bad enum, overlap)                   */
+                                  above 2^27 - 8, bad enum, overlap, an array or
+                                  operand whose extent passes the top of the address
+                                  space)                                             */
     BLAZ_ERR_UNSUPPORTED = -6, /* a valid request this build does not implement        */
     BLAZ_ERR_WORKSPACE = -7,   /* workspace missing or smaller than required           */
     BLAZ_ERR_HIP = -8,         /* the HIP runtime reported an error                    */

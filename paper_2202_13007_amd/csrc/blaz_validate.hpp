@@ -44,19 +44,6 @@ inline int lines_of(const blaz_matrix& m) { return m.lines == 0 ? 2 : (int)m.lin
 inline bool valid_lines(int64_t lines) { return lines >= 0 && lines <= 8; }
 inline int64_t code_stride(int lines) { return 4 * ((16 * lines - lines * lines + 3) / 4); }
 
-// A descriptor is valid if its shape and kept lines are and, when it holds
-// blocks, its four arrays are present and aligned.
-inline blaz_status check_matrix(const blaz_matrix* m)
-{
-    if (!m) return BLAZ_ERR_NULL;
-    if (!valid_lines(m->lines)) return BLAZ_ERR_ARG;
-    if (blaz_status st = check_shape(m->rows, m->cols)) return st;
-    if (nblocks(*m) == 0) return BLAZ_OK;
-    if (!m->f || !m->s || !m->phi || !m->codes) return BLAZ_ERR_NULL;
-    if (!aligned(m->f, 8) || !aligned(m->s, 8) || !aligned(m->codes, 4)) return BLAZ_ERR_ALIGN;
-    return BLAZ_OK;
-}
-
 struct Range {
     uintptr_t lo, hi;
 };
@@ -65,7 +52,10 @@ inline Range span(const void* p, int64_t bytes)
     const auto a = reinterpret_cast<uintptr_t>(p);
     return {a, a + (uintptr_t)(bytes > 0 ? bytes : 0)};
 }
-inline bool overlap(Range a, Range b) { return a.lo < b.hi && b.lo < a.hi; }
+// A range whose end passes the top of the address space (no allocation can
+// hold it) counts as overlapping everything, so that the call is refused.
+inline bool wraps(Range r) { return r.hi < r.lo; }
+inline bool overlap(Range a, Range b) { return wraps(a) || wraps(b) || (a.lo < b.hi && b.lo < a.hi); }
 
 // The byte ranges of a compressed matrix's four arrays.
 inline void ranges(const blaz_matrix& m, Range r[4])
@@ -75,6 +65,24 @@ inline void ranges(const blaz_matrix& m, Range r[4])
     r[1] = span(m.s, 8 * n);
     r[2] = span(m.phi, n);
     r[3] = span(m.codes, code_stride(lines_of(m)) * n);
+}
+
+// A descriptor is valid if its shape and kept lines are and, when it holds
+// blocks, its four arrays are present, aligned and end below the top of the
+// address space.
+inline blaz_status check_matrix(const blaz_matrix* m)
+{
+    if (!m) return BLAZ_ERR_NULL;
+    if (!valid_lines(m->lines)) return BLAZ_ERR_ARG;
+    if (blaz_status st = check_shape(m->rows, m->cols)) return st;
+    if (nblocks(*m) == 0) return BLAZ_OK;
+    if (!m->f || !m->s || !m->phi || !m->codes) return BLAZ_ERR_NULL;
+    if (!aligned(m->f, 8) || !aligned(m->s, 8) || !aligned(m->codes, 4)) return BLAZ_ERR_ALIGN;
+    Range r[4];
+    ranges(*m, r);
+    for (auto& x : r)
+        if (wraps(x)) return BLAZ_ERR_ARG;
+    return BLAZ_OK;
 }
 
 inline bool overlaps_matrix(Range a, const blaz_matrix& m)

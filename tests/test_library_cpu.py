@@ -401,3 +401,19 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=300, cwd=root)
     assert r.returncode == 2, (r.returncode, r.stdout[-500:], r.stderr[-500:])
     assert "one GPU only" in r.stdout + r.stderr
+
+
+def test_extents_past_the_top_of_the_address_space_are_refused(L):
+    """An array or dense operand whose byte extent would pass 2^64 cannot be
+    an allocation: it is refused as an invalid argument (BLAZ_ERR_ARG)
+    before anything is enqueued, also where it would otherwise look
+    disjoint from the other operands."""
+    from paper_2202_13007_amd._lib import BlazMatrixC
+    top = 1 << 64
+    high = BlazMatrixC(8, 16, top - 64, top - 32, top - 8, top - 4)  # 2 blocks: every array wraps
+    low = mat(8, 16, 1 << 30)
+    assert L.blaz_scale(B(high), 2.0, B(low), None) == -5
+    assert L.blaz_add(B(low), B(low), B(high), None) == -5
+    # a dense operand ending past the top (8 x 16 doubles from 2^64 - 512)
+    assert L.blaz_decompress(B(low), ctypes.c_void_p(top - 512), 16, None) == -5
+    assert L.blaz_compress(ctypes.c_void_p(top - 512), 16, B(low), 0, None, None) == -5

@@ -13,6 +13,7 @@ from hypothesis import strategies as st
 
 BLAZ_OK, BLAZ_ERR_HIP = 0, -8
 MAX_BLOCKS = (1 << 32) - 256
+TOP = 1 << 64  # addresses are unsigned 64-bit; an extent reaching TOP wraps
 SETTINGS = settings(max_examples=500, deadline=None, database=None, suppress_health_check=[HealthCheck.too_slow])
 
 
@@ -53,7 +54,9 @@ class Desc:
         f, s, phi, codes = self.ptrs
         if not (f and s and phi and codes):
             return False
-        return f % 8 == 0 and s % 8 == 0 and codes % 4 == 0
+        if not (f % 8 == 0 and s % 8 == 0 and codes % 4 == 0):
+            return False
+        return not any(wraps(r) for r in self.ranges())
 
     def ranges(self):
         n = self.nblk()
@@ -67,10 +70,19 @@ class Desc:
         return BlazMatrixC(self.rows, self.cols, f, s, phi, codes, self.lines)
 
 
+def wraps(r):
+    return r[1] > r[0] and r[1] >= TOP
+
+
+def overlap(r, q):
+    """Byte ranges [lo, hi) that overlap; a wrapping range overlaps everything."""
+    return wraps(r) or wraps(q) or (r[0] < q[1] and q[0] < r[1])
+
+
 def same_or_disjoint(z, x):
     if z.ptrs == x.ptrs:
         return True
-    return not any(a < d and c < b for a, b in z.ranges() for c, d in x.ranges())
+    return not any(overlap(r, q) for r in z.ranges() for q in x.ranges())
 
 
 SIDES = st.sampled_from([0, 8, 16, 24, 64, 8, 16, 24, 64, 7, -8, 8 << 22])
@@ -163,3 +175,71 @@ def test_null_descriptors_are_refused(L):
     x = Desc(8, 8, 0, 1 << 30, (1 << 30) + 64, (1 << 30) + 128, (1 << 30) + 192).c()
     assert L.blaz_add(None, ctypes.byref(x), ctypes.byref(x), None) not in (BLAZ_OK, BLAZ_ERR_HIP)
     assert L.blaz_scale(ctypes.byref(x), ctypes.c_double(1.0), None, None) not in (BLAZ_OK, BLAZ_ERR_HIP)
+
+
+def dense_span(base, rows, cols, lda):
+    return (base, base + (((rows - 1) * lda + cols) * 8 if rows > 0 else 0))
+
+
+def overlaps_desc(r, d):
+    return any(overlap(r, q) for q in d.ranges())
+
+
+@st.composite
+def dense_args(draw):
+    """A descriptor, a dense operand placed apart from it, over its arrays,
+    ending on its first element, running past 2^64, misaligned or NULL, a
+    leading dimension that may be short, and for compression an optional Psi
+    buffer placed apart, over either, or misaligned."""
+    m = draw(descriptor())
+    cols = max(m.cols, 0)
+    lda = cols + draw(st.sampled_from([0, 0, 2, 8, -8, -1]))
+    place = draw(st.sampled_from(["apart", "apart", "apart", "apart", "over", "tail", "top", "misaligned", "null"]))
+    base = (1 << 44) + (1 << 20) * draw(st.integers(0, 3))
+    rows = max(m.rows, 0)
+    extent = ((rows - 1) * lda + cols) * 8 if rows > 0 else 0
+    f = m.ptrs[0] or base
+    # "tail": only the operand's last element lies on the descriptor's f array
+    # "top": the operand starts below 2^64 and its extent passes it
+    A = {"apart": base, "over": (m.ptrs[3] or base) - 8, "tail": (f - extent + 8) % TOP,
+         "top": TOP - 8 * (extent // 16 + 1), "misaligned": base + 4, "null": None}[place]
+    pplace = draw(st.sampled_from(["none", "none", "none", "apart", "over_a", "over_m", "misaligned"]))
+    pbase = (1 << 46) + (1 << 20) * draw(st.integers(0, 3))
+    psi = {"none": None, "apart": pbase, "over_a": A, "over_m": m.ptrs[0], "misaligned": pbase + 8}[pplace]
+    prec = draw(st.sampled_from([0, 0, 0, 1, 2, 3, -1]))
+    return m, A, lda, psi, prec
+
+
+@SETTINGS
+@given(dense_args())
+def test_compress_accepts_exactly_what_the_rules_allow(L, args):
+    m, A, lda, psi, prec = args
+    ok = m.valid() and prec in (0, 1, 2)
+    lines = 2 if m.lines == 0 else m.lines
+    if ok and lines != 2 and (prec != 0 or psi is not None):
+        ok = False
+    n = m.nblk() if ok else 0
+    if ok and n:
+        ok = (A is not None and lda >= m.cols and A % 8 == 0 and (psi is None or psi % 16 == 0))
+        if ok:
+            ra = dense_span(A, m.rows, m.cols, lda)
+            ok = not overlaps_desc(ra, m)
+            if ok and psi is not None:
+                rp = (psi, psi + 64 * n)
+                ok = not overlap(rp, ra) and not overlaps_desc(rp, m)
+    want = expect(ok, n)
+    cm = m.c()
+    check(L.blaz_compress(ctypes.c_void_p(A), lda, ctypes.byref(cm), prec, ctypes.c_void_p(psi), None), want,
+          f"compress prec {prec}")
+
+
+@SETTINGS
+@given(dense_args())
+def test_decompress_accepts_exactly_what_the_rules_allow(L, args):
+    m, A, lda, _, _ = args
+    ok = m.valid()
+    n = m.nblk() if ok else 0
+    if ok and n:
+        ok = A is not None and lda >= m.cols and A % 8 == 0 and not overlaps_desc(dense_span(A, m.rows, m.cols, lda), m)
+    cm = m.c()
+    check(L.blaz_decompress(ctypes.byref(cm), ctypes.c_void_p(A), lda, None), expect(ok, n), "decompress")
