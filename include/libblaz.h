@@ -219,7 +219,8 @@ size_t blaz_matmul_workspace_bytes(int64_t m, int64_t n, int64_t k, int b_compre
  * prec selects the contraction arithmetic (FP64, FP32, or BF16x3 with FP32
  * accumulation); the output is binary64 in every case.  workspace must hold
  * blaz_matmul_workspace_bytes() bytes, 256-byte aligned.  C must not overlap
- * the inputs or the workspace. */
+ * the inputs or the workspace, and the workspace must not overlap the inputs
+ * (BLAZ_ERR_ARG). */
 blaz_status blaz_matmul(const blaz_matrix *a, const blaz_matrix *b, const double *bdense, int64_t n,
                         int64_t ldb, double *c, int64_t ldc, blaz_precision prec, void *workspace,
                         size_t ws_bytes, hipStream_t stream);

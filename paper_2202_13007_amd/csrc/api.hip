@@ -244,6 +244,13 @@ static blaz_status matmul_impl(const blaz_matrix* a, const blaz_matrix* b, const
         (bdense && overlap(rc, span(bdense, dense_span(k, n, ldb)))) ||
         (k > 0 && overlap(rc, span(workspace, (int64_t)need))))
         return BLAZ_ERR_ARG;
+    // the rebuilds write the workspace while the inputs are read
+    if (k > 0) {
+        const Range rw = span(workspace, (int64_t)need);
+        if (overlaps_matrix(rw, *a) || (b && overlaps_matrix(rw, *b)) ||
+            (bdense && overlap(rw, span(bdense, dense_span(k, n, ldb)))))
+            return BLAZ_ERR_ARG;
+    }
     // k == 0: the product is the zero matrix; the contraction kernel with an
     // empty K loop writes exactly that and reads nothing.
     if (tile == 0) tile = default_gemm_tile(m, n);

@@ -266,6 +266,12 @@ def test_matmul_validation(L):
     assert L.blaz_matmul(B(a), None, 0x500008, 8, 8, C, 8, 0, ws, need, None) == -4   # B not 16-aligned
     assert L.blaz_matmul(B(a), B(b), None, 8, 8, ws, 8, 0, ws, need, None) == -5      # C overlaps ws
     assert L.blaz_matmul(B(a), B(b), None, 8, 8, C, 8, 5, ws, need, None) == -5       # bad precision
+    # the workspace, which the rebuilds write while the inputs are read, must
+    # not overlap them: A's record, B's record, a dense B
+    assert L.blaz_matmul(B(a), B(b), None, 8, 8, C, 8, 0, 0x100000, need, None) == -5
+    assert L.blaz_matmul(B(a), B(b), None, 8, 8, C, 8, 0, 0x200000, need, None) == -5
+    need_d = L.blaz_matmul_workspace_bytes(16, 8, 24, 0, 1)
+    assert L.blaz_matmul(B(a), None, 0x500000, 8, 8, C, 8, 1, 0x500000, need_d, None) == -5
 
 
 def test_matmul_compressed_validation(L):

@@ -243,3 +243,118 @@ def test_decompress_accepts_exactly_what_the_rules_allow(L, args):
         ok = A is not None and lda >= m.cols and A % 8 == 0 and not overlaps_desc(dense_span(A, m.rows, m.cols, lda), m)
     cm = m.c()
     check(L.blaz_decompress(ctypes.byref(cm), ctypes.c_void_p(A), lda, None), expect(ok, n), "decompress")
+
+
+MATMUL_FAULTS = [None] * 8 + ["tile", "prec", "both", "neither", "bshape", "n", "cnull", "calign", "ldc",
+                              "ldb", "ldbodd", "balign", "wsnull", "wsshort", "wsalign", "c_a", "c_bd", "c_ws",
+                              "ws_a", "ws_b", "ws_bd"]
+
+
+@st.composite
+def matmul_args(draw):
+    """A valid product (compressed A of at least one block, B compressed or
+    dense, C and the workspace apart from each other) with at most one
+    fault: a bad tile or precision, both or neither form of B, B's shape,
+    n, C or the workspace NULL, misaligned, short or over another operand,
+    or a short or odd leading dimension."""
+    rows, cols = draw(st.sampled_from([8, 16, 24])), draw(st.sampled_from([8, 16, 24]))
+    a = Desc(rows, cols, draw(st.sampled_from([0, 2, 1, 3])), *[(1 << 36) + i * (1 << 20) for i in range(4)])
+    m, k = rows, cols
+    n = draw(st.sampled_from([8, 16, 24]))
+    dense = draw(st.booleans())
+    b = None if dense else Desc(k, n, draw(st.sampled_from([0, 2, 3])), *[(1 << 38) + i * (1 << 20) for i in range(4)])
+    bdense = (1 << 42) if dense else None
+    ldb, ldc = n + draw(st.sampled_from([0, 2])), n + draw(st.sampled_from([0, 8]))
+    c, ws, prec, tile, short = 1 << 43, 1 << 45, draw(st.sampled_from([0, 1, 2])), draw(st.sampled_from([0, 64, 128])), 0
+    fault = draw(st.sampled_from(MATMUL_FAULTS))
+    if fault == "tile":
+        tile = 32
+    elif fault == "prec":
+        prec = 7
+    elif fault == "both":
+        b, bdense = b or Desc(k, n, 0, *[(1 << 38) + i * (1 << 20) for i in range(4)]), bdense or (1 << 42)
+    elif fault == "neither":
+        b = bdense = None
+    elif fault == "bshape" and b is not None:
+        b = Desc(k + 8, n, b.lines, *b.ptrs)
+    elif fault == "n":
+        n += 4
+    elif fault == "cnull":
+        c = None
+    elif fault == "calign":
+        c += 4
+    elif fault == "ldc":
+        ldc = n - 8
+    elif fault == "ldb":
+        ldb = n - 2
+    elif fault == "ldbodd":
+        ldb = n + 1
+    elif fault == "balign" and bdense is not None:
+        bdense += 8
+    elif fault == "wsnull":
+        ws = None
+    elif fault == "wsshort":
+        short = 8
+    elif fault == "wsalign":
+        ws += 128
+    elif fault == "c_a":
+        c = a.ptrs[1]
+    elif fault == "c_bd" and bdense is not None:
+        c = bdense + 8 * n
+    elif fault == "c_ws":
+        c = ws + 64
+    elif fault == "ws_a":
+        ws = a.ptrs[0]
+    elif fault == "ws_b" and b is not None:
+        ws = b.ptrs[3]
+    elif fault == "ws_bd" and bdense is not None:
+        ws = bdense
+    return a, b, bdense, n, ldb, c, ldc, prec, ws, short, tile
+
+
+def matmul_model(L, a, b, bdense, n, ldb, c, ldc, prec, ws, tile, ws_bytes):
+    """Whether the header's rules accept the call, and whether it launches."""
+    if tile not in (0, 64, 128) or not a.valid() or prec not in (0, 1, 2):
+        return False, False
+    m, k = a.rows, a.cols
+    if b is not None and bdense is not None:
+        return False, False
+    if b is None and bdense is None and k > 0:
+        return False, False
+    if b is not None and (not b.valid() or b.rows != k or b.cols != n):
+        return False, False
+    if n < 0 or n % 8:
+        return False, False
+    if m == 0 or n == 0:
+        return True, False
+    if not c or ldc < n or c % 8:
+        return False, False
+    if b is None and k > 0 and (ldb < n or bdense % 16 or ldb % 2):
+        return False, False
+    need = L.blaz_matmul_workspace_bytes(m, n, k, int(b is not None), prec)
+    if k > 0 and (not ws or ws_bytes < need or ws % 256):
+        return False, False
+    rc = dense_span(c, m, n, ldc)
+    rb = dense_span(bdense, k, n, ldb) if bdense is not None else None
+    rw = (ws, ws + need) if k > 0 else None
+    ins = [q for q in a.ranges()] + (b.ranges() if b is not None else []) + ([rb] if rb else [])
+    if any(overlap(rc, q) for q in ins) or (rw and overlap(rc, rw)):
+        return False, False
+    if rw and any(overlap(rw, q) for q in ins):
+        return False, False
+    return True, True
+
+
+@SETTINGS
+@given(matmul_args())
+def test_matmul_accepts_exactly_what_the_rules_allow(L, args):
+    a, b, bdense, n, ldb, c, ldc, prec, ws, short, tile = args
+    need = L.blaz_matmul_workspace_bytes(max(a.rows, 0), n, max(a.cols, 0), int(b is not None), prec if prec in (0, 1, 2) else 0)
+    ws_bytes = max(need - short, 0)
+    ok, launches = matmul_model(L, a, b, bdense, n, ldb, c, ldc, prec, ws, tile, ws_bytes)
+    ca = a.c()
+    cb = b.c() if b is not None else None
+    st_ = L.blaz_matmul_tiled(ctypes.byref(ca), ctypes.byref(cb) if cb is not None else None, ctypes.c_void_p(bdense),
+                              n, ldb, ctypes.c_void_p(c), ldc, prec, ctypes.c_void_p(ws), ws_bytes, tile, None)
+    want = (BLAZ_ERR_HIP if launches else BLAZ_OK) if ok else None
+    check(st_, want, f"matmul form {'c' if b else ''}{'d' if bdense else ''} prec {prec} tile {tile}")
