@@ -191,7 +191,9 @@ blaz_status blaz_scale(const blaz_matrix *x, double c, const blaz_matrix *z, hip
  * (and the columns 8J..8J+7 of Y in order) rebuild each block once for the 8;
  * every query gets the same bits either way.  A call takes at most
  * 2^27 - 8 queries (32 lanes each in one dispatch of at most 2^32 - 1
- * work-items); more is BLAZ_ERR_ARG. */
+ * work-items); more is BLAZ_ERR_ARG.  out (count doubles, 8-byte aligned;
+ * xrow and ycol 8-byte aligned) must not overlap x, y, xrow or ycol
+ * (BLAZ_ERR_ARG). */
 blaz_status blaz_dot(const blaz_matrix *x, const int64_t *xrow, const blaz_matrix *y, const int64_t *ycol,
                      int64_t count, double *out, hipStream_t stream);
 
@@ -199,7 +201,8 @@ blaz_status blaz_dot(const blaz_matrix *x, const int64_t *xrow, const blaz_matri
  * out[q] = sum_k X[xrow[q], k] * v[q*ldv + k].  ldv = 0 uses one vector for
  * every q; otherwise ldv >= x->cols.  v is 16-byte aligned and, when
  * ldv != 0, ldv is even.  An index outside X yields NaN.  At most 2^27 - 8
- * queries, as for blaz_dot. */
+ * queries, as for blaz_dot.  out must not overlap x, xrow or the vectors
+ * (BLAZ_ERR_ARG). */
 blaz_status blaz_dot_dense(const blaz_matrix *x, const int64_t *xrow, const double *v, int64_t ldv,
                            int64_t count, double *out, hipStream_t stream);
 

@@ -200,7 +200,10 @@ inline blaz_status validate_dot(const blaz_matrix* x, const int64_t* xrow, const
     if (count == 0) return BLAZ_OK;
     if (!xrow || !ycol || !out) return BLAZ_ERR_NULL;
     if (!aligned(xrow, 8) || !aligned(ycol, 8) || !aligned(out, 8)) return BLAZ_ERR_ALIGN;
-    if (overlaps_matrix(span(out, 8 * count), *x) || overlaps_matrix(span(out, 8 * count), *y)) return BLAZ_ERR_ARG;
+    const Range ro = span(out, 8 * count);
+    if (overlaps_matrix(ro, *x) || overlaps_matrix(ro, *y)) return BLAZ_ERR_ARG;
+    // out is written while other queries still read their indexes
+    if (overlap(ro, span(xrow, 8 * count)) || overlap(ro, span(ycol, 8 * count))) return BLAZ_ERR_ARG;
     *empty = false;
     return BLAZ_OK;
 }
@@ -217,7 +220,11 @@ inline blaz_status validate_dot_dense(const blaz_matrix* x, const int64_t* xrow,
     if (count == 0) return BLAZ_OK;
     if (!xrow || !v || !out) return BLAZ_ERR_NULL;
     if (!aligned(xrow, 8) || !aligned(out, 8) || !aligned(v, 16) || ldv % 2 != 0) return BLAZ_ERR_ALIGN;
-    if (overlaps_matrix(span(out, 8 * count), *x)) return BLAZ_ERR_ARG;
+    const Range ro = span(out, 8 * count);
+    if (overlaps_matrix(ro, *x)) return BLAZ_ERR_ARG;
+    // out is written while other queries still read their indexes and vectors
+    const Range rv = span(v, ldv == 0 ? 8 * x->cols : dense_span(count, x->cols, ldv));
+    if (overlap(ro, span(xrow, 8 * count)) || overlap(ro, rv)) return BLAZ_ERR_ARG;
     *empty = false;
     return BLAZ_OK;
 }

@@ -89,13 +89,15 @@ int main()
     blaz_matrix huge = mat(8 * 257, 8 * ((int64_t(1) << 24) - 1), uintptr_t(1) << 44);
     EXPECT(validate_scale(&huge, &huge, &empty), BLAZ_ERR_SHAPE);
 
-    // dots: count limits
+    // dots: count limits (the output far from the index arrays, which it must
+    // not overlap even at the largest count)
     const int64_t* idx = fake<const int64_t>(0x700000);
-    EXPECT(validate_dot(&x, idx, &y, idx, kMaxDots, fake<const double>(0x800000), &empty), BLAZ_OK);
-    EXPECT(validate_dot(&x, idx, &y, idx, kMaxDots + 1, fake<const double>(0x800000), &empty), BLAZ_ERR_ARG);
-    EXPECT(validate_dot(&x, idx, &y, idx, -1, fake<const double>(0x800000), &empty), BLAZ_ERR_ARG);
-    EXPECT(validate_dot(&x, idx, &w, idx, 4, fake<const double>(0x800000), &empty), BLAZ_OK);
-    EXPECT(validate_dot(&w, idx, &x, idx, 4, fake<const double>(0x800000), &empty), BLAZ_ERR_MISMATCH);
+    const double* far_out = fake<const double>(uintptr_t(1) << 40);
+    EXPECT(validate_dot(&x, idx, &y, idx, kMaxDots, far_out, &empty), BLAZ_OK);
+    EXPECT(validate_dot(&x, idx, &y, idx, kMaxDots + 1, far_out, &empty), BLAZ_ERR_ARG);
+    EXPECT(validate_dot(&x, idx, &y, idx, -1, far_out, &empty), BLAZ_ERR_ARG);
+    EXPECT(validate_dot(&x, idx, &w, idx, 4, far_out, &empty), BLAZ_OK);
+    EXPECT(validate_dot(&w, idx, &x, idx, 4, far_out, &empty), BLAZ_ERR_MISMATCH);
     EXPECT(validate_dot_dense(&x, idx, fake<const double>(0x900000), 16, 4, fake<const double>(0x800000), &empty),
            BLAZ_OK);
     EXPECT(validate_dot_dense(&x, idx, fake<const double>(0x900000), big, 4, fake<const double>(0x800000), &empty),
@@ -103,6 +105,11 @@ int main()
     EXPECT(validate_dot_dense(&x, idx, fake<const double>(0x900000), 17, 4, fake<const double>(0x800000), &empty),
            BLAZ_ERR_ALIGN);
     EXPECT(validate_dot_dense(&x, idx, fake<const double>(0x900000), 0, kMaxDots + 1, fake<const double>(0x800000),
+                              &empty),
+           BLAZ_ERR_ARG);
+    // the output may not overlap the index arrays or the vectors
+    EXPECT(validate_dot(&x, idx, &y, idx, 4, fake<const double>(0x700008), &empty), BLAZ_ERR_ARG);
+    EXPECT(validate_dot_dense(&x, idx, fake<const double>(0x900000), 16, 4, fake<const double>(0x900000 + 8 * 60),
                               &empty),
            BLAZ_ERR_ARG);
     if (failures) return 1;

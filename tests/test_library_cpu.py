@@ -249,6 +249,12 @@ def test_dot_validation(L):
     assert L.blaz_dot_dense(B(x), idx, 0x500000, 23, 4, out, None) == -2  # ldv < cols
     assert L.blaz_dot_dense(B(x), idx, 0x500000, 25, 4, out, None) == -4  # odd ldv
     assert L.blaz_dot_dense(B(x), idx, 0x500000, -2, 4, out, None) == -5
+    # out is written while the other queries read their indexes and vectors
+    assert L.blaz_dot(B(x), idx, B(y), idx, 4, idx + 8, None) == -5          # out over xrow
+    assert L.blaz_dot(B(x), idx, B(y), out - 16, 4, out, None) == -5         # out over ycol
+    assert L.blaz_dot_dense(B(x), idx, out, 0, 4, out + 64, None) == -5      # out over the shared vector
+    assert L.blaz_dot_dense(B(x), idx, out, 24, 4, out + 8 * 80, None) == -5  # over the last vector
+    assert L.blaz_dot_dense(B(x), out + 24, 0x500000, 0, 4, out, None) == -5  # out over xrow
 
 
 def test_matmul_validation(L):

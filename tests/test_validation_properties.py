@@ -358,3 +358,87 @@ def test_matmul_accepts_exactly_what_the_rules_allow(L, args):
                               n, ldb, ctypes.c_void_p(c), ldc, prec, ctypes.c_void_p(ws), ws_bytes, tile, None)
     want = (BLAZ_ERR_HIP if launches else BLAZ_OK) if ok else None
     check(st_, want, f"matmul form {'c' if b else ''}{'d' if bdense else ''} prec {prec} tile {tile}")
+
+
+DOT_FAULTS = [None] * 6 + ["cols", "lines", "count", "xnull", "ynull", "onull", "xalign", "oalign", "o_x", "o_y",
+                           "o_xrow", "o_ycol", "valign", "ldv", "ldvodd", "o_v"]
+
+
+@st.composite
+def dot_args(draw):
+    """Valid compressed-pair and dense-vector dot calls with at most one
+    fault: mismatched shapes or rates, a bad count, an index, output or
+    vector array NULL, misaligned or overlapping the output, a short or
+    odd ldv."""
+    rows, cols, n = (draw(st.sampled_from([8, 16, 24])) for _ in range(3))
+    x = Desc(rows, cols, 0, *[(1 << 36) + i * (1 << 20) for i in range(4)])
+    y = Desc(cols, n, 0, *[(1 << 38) + i * (1 << 20) for i in range(4)])
+    count = draw(st.sampled_from([0, 1, 4, 9]))
+    xrow, ycol, out, v = 1 << 40, (1 << 40) + (1 << 20), 1 << 42, 1 << 44
+    ldv = draw(st.sampled_from([0, cols, cols + 2]))
+    fault = draw(st.sampled_from(DOT_FAULTS))
+    if fault == "cols":
+        y = Desc(cols + 8, n, 0, *y.ptrs)
+    elif fault == "lines":
+        x = Desc(rows, cols, 3, *x.ptrs)
+    elif fault == "count":
+        count = -1
+    elif fault == "xnull":
+        xrow = None
+    elif fault == "ynull":
+        ycol = None
+    elif fault == "onull":
+        out = None
+    elif fault == "xalign":
+        xrow += 4
+    elif fault == "oalign":
+        out += 4
+    elif fault == "o_x":
+        out = x.ptrs[2]
+    elif fault == "o_y":
+        out = y.ptrs[0] + 8
+    elif fault == "o_xrow":
+        out = xrow + 8
+    elif fault == "o_ycol":
+        out = ycol - 8
+    elif fault == "valign":
+        v += 8
+    elif fault == "ldv":
+        ldv = cols - 2
+    elif fault == "ldvodd":
+        ldv = cols + 1
+    elif fault == "o_v":
+        out = v + 8 * (ldv * max(count - 1, 0) + cols) - 8
+    return x, y, count, xrow, ycol, out, v, ldv
+
+
+def rng8(p, count):
+    return (p, p + 8 * count) if p else (0, 0)
+
+
+@SETTINGS
+@given(dot_args())
+def test_dot_and_dot_dense_accept_exactly_what_the_rules_allow(L, args):
+    x, y, count, xrow, ycol, out, v, ldv = args
+    i64 = ctypes.c_void_p
+    # compressed pairs
+    ok = x.cols == y.rows and x.lines in (0, 2) and y.lines in (0, 2) and 0 <= count
+    if ok and count:
+        ok = all(p and p % 8 == 0 for p in (xrow, ycol, out))
+        if ok:
+            ro = rng8(out, count)
+            ok = not (overlaps_desc(ro, x) or overlaps_desc(ro, y) or overlap(ro, rng8(xrow, count))
+                      or overlap(ro, rng8(ycol, count)))
+    cx, cy = x.c(), y.c()
+    check(L.blaz_dot(ctypes.byref(cx), i64(xrow), ctypes.byref(cy), i64(ycol), count, i64(out), None),
+          expect(ok, count if ok else 0), "dot")
+    # dense vectors
+    ok = x.lines in (0, 2) and 0 <= count and ldv >= 0 and (ldv == 0 or ldv >= x.cols)
+    if ok and count:
+        ok = all(p and p % 8 == 0 for p in (xrow, out)) and v and v % 16 == 0 and ldv % 2 == 0
+        if ok:
+            ro = rng8(out, count)
+            rv = (v, v + (8 * x.cols if ldv == 0 else ((count - 1) * ldv + x.cols) * 8))
+            ok = not (overlaps_desc(ro, x) or overlap(ro, rng8(xrow, count)) or overlap(ro, rv))
+    check(L.blaz_dot_dense(ctypes.byref(cx), i64(xrow), i64(v), ldv, count, i64(out), None),
+          expect(ok, count if ok else 0), "dot_dense")
