@@ -408,7 +408,8 @@ blaz_status blaz_batch_run_resident(const void *plan_dev, int64_t capacity, blaz
  * enqueues the launches (no memset, copy or allocation, so a run can be
  * captured in a HIP graph; the plan and workspace may be reused by later
  * runs on the same stream).  The products of a group run concurrently: no
- * product may write another's operands or output.
+ * product may write another's operands or output (the plan call refuses such
+ * a group with BLAZ_ERR_ARG; products may share operands).
  * ------------------------------------------------------------------------- */
 typedef struct blaz_matmul_item {
     blaz_matrix a;          /* A, m x k, compressed (two kept lines)                */

@@ -110,6 +110,28 @@ def test_plan_rejects_workspace_overlapping_an_output():
     assert st == -5
 
 
+def test_plan_rejects_an_output_over_another_products_operands_or_output():
+    """The products run concurrently: one product's C over another's A, B
+    (compressed or dense) or C is refused, naming the later product; products
+    sharing an operand are fine."""
+    ws = dict(ws=0x10000000, ws_bytes=1 << 30)
+    base = products()
+    for target in (0x1000000 + 8, 0x2000000, 0x5000000 + 64, 0x6000000 + 8):  # A0, B0, dense B1, C1
+        items = products()
+        items.append(item(fake_matrix(8, 8, 0xA000000), bdense=0xB000000, n=8, ldb=8, c=target, ldc=8))
+        st, info = plan(items, **ws)
+        assert st == -5 and info.rebuild_jobs == len(items) - 1, (hex(target), st, info.rebuild_jobs)
+    # a later product reading the first product's output is refused as well
+    items = products()
+    items.append(item(fake_matrix(8, 8, 0xA000000), bdense=0x3000000, n=8, ldb=8, c=0xC000000, ldc=8))
+    st, info = plan(items, **ws)
+    assert st == -5 and info.rebuild_jobs == len(items) - 1
+    # shared operands: the same A and dense B in two products with their own outputs
+    items = products()
+    items.append(item(base[1].a, bdense=0x5000000, n=64, ldb=64, c=0xD000000, ldc=64, tile=128))
+    assert plan(items, **ws)[0] == 0
+
+
 # --------------------------------------------------------------------------
 # GPU: every product against the oracle and against blaz_matmul alone
 # --------------------------------------------------------------------------
