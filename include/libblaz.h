@@ -349,7 +349,9 @@ size_t blaz_batch_plan_bytes(int64_t n_items);
  * *n_plan is the number of planned items and *total_chunks the length of the
  * work queue.  On failure *n_plan holds the index of the first invalid item
  * and nothing is written to device memory (nothing is, in any case: this is
- * a host-only function). */
+ * a host-only function).  Items that would read or write another item's
+ * output are refused with BLAZ_ERR_ARG, *n_plan naming the later of the two;
+ * items may share inputs. */
 blaz_status blaz_batch_plan(const blaz_batch_item *items, int64_t n_items, void *plan, size_t plan_bytes,
                             int64_t *n_plan, int64_t *total_chunks);
 

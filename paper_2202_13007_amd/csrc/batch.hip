@@ -282,6 +282,58 @@ BLAZ_API blaz_status blaz_batch_plan(const blaz_batch_item* items, int64_t n_ite
         chunks += n;
         out[np++] = d;
     }
+    // The items run concurrently: no item may read or write another item's
+    // output (inputs may be shared).
+    std::vector<Tagged> writes, reads;
+    for (int64_t i = 0; i < n_items; ++i) {
+        const blaz_batch_item& it = items[i];
+        switch (it.op) {
+            case BLAZ_OP_COMPRESS:
+                if (nblocks(it.x) == 0) break;
+                push_matrix(writes, it.x, i);
+                reads.push_back({span(it.dense, dense_span(it.x.rows, it.x.cols, it.ld)), i});
+                break;
+            case BLAZ_OP_DECOMPRESS:
+                if (nblocks(it.x) == 0) break;
+                writes.push_back({span(it.dense, dense_span(it.x.rows, it.x.cols, it.ld)), i});
+                push_matrix(reads, it.x, i);
+                break;
+            case BLAZ_OP_ADD:
+            case BLAZ_OP_SUB:
+                if (nblocks(it.x) == 0) break;
+                push_matrix(writes, it.z, i);
+                push_matrix(reads, it.x, i);
+                push_matrix(reads, it.y, i);
+                break;
+            case BLAZ_OP_SCALE:
+                if (nblocks(it.x) == 0) break;
+                push_matrix(writes, it.z, i);
+                push_matrix(reads, it.x, i);
+                break;
+            case BLAZ_OP_DOT:
+                if (it.count == 0) break;
+                writes.push_back({span(it.out, 8 * it.count), i});
+                push_matrix(reads, it.x, i);
+                push_matrix(reads, it.y, i);
+                reads.push_back({span(it.xrow, 8 * it.count), i});
+                reads.push_back({span(it.ycol, 8 * it.count), i});
+                break;
+            default:  // BLAZ_OP_DOT_DENSE
+                if (it.count == 0) break;
+                writes.push_back({span(it.out, 8 * it.count), i});
+                push_matrix(reads, it.x, i);
+                reads.push_back({span(it.xrow, 8 * it.count), i});
+                reads.push_back({span(it.dense, it.ld == 0 ? 8 * it.x.cols : dense_span(it.count, it.x.cols, it.ld)),
+                                 i});
+                break;
+        }
+    }
+    const int64_t bad = cross_item_conflict(writes, reads);
+    if (bad >= 0) {
+        *n_plan = bad;
+        *total_chunks = 0;
+        return BLAZ_ERR_ARG;
+    }
     *n_plan = np;
     *total_chunks = chunks;
     return BLAZ_OK;

@@ -3,7 +3,9 @@
 // them touches device memory or calls the HIP runtime.
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
+#include <vector>
 
 #include "libblaz.h"
 
@@ -121,6 +123,40 @@ inline blaz_status check_dense(int64_t rows, int64_t cols, int64_t ld)
 }
 
 inline blaz_status hip_status(hipError_t e) { return e == hipSuccess ? BLAZ_OK : BLAZ_ERR_HIP; }
+
+// Work that runs concurrently (the items of a batch, the products of a
+// group): no item's output may overlap another item's output or inputs,
+// while inputs may be shared.  writes and reads are byte ranges tagged with
+// their item.  The writes, sorted by address, must be disjoint; then a read
+// can only meet the last write that starts below its end.  Returns the
+// larger item index of a conflicting pair, or -1.
+struct Tagged {
+    Range r;
+    int64_t item;
+};
+inline int64_t cross_item_conflict(std::vector<Tagged>& writes, const std::vector<Tagged>& reads)
+{
+    std::sort(writes.begin(), writes.end(), [](const Tagged& x, const Tagged& y) { return x.r.lo < y.r.lo; });
+    for (size_t q = 1; q < writes.size(); ++q)
+        if (overlap(writes[q - 1].r, writes[q].r)) return std::max(writes[q - 1].item, writes[q].item);
+    for (const Tagged& rd : reads) {
+        if (rd.r.hi == rd.r.lo) continue;
+        auto after = std::lower_bound(writes.begin(), writes.end(), rd.r.hi,
+                                      [](const Tagged& w, uintptr_t hi) { return w.r.lo < hi; });
+        if (after == writes.begin()) continue;
+        const Tagged& w = *(after - 1);
+        if (w.item != rd.item && overlap(w.r, rd.r)) return std::max(w.item, rd.item);
+    }
+    return -1;
+}
+
+// The four arrays of a compressed matrix, tagged.
+inline void push_matrix(std::vector<Tagged>& v, const blaz_matrix& m, int64_t item)
+{
+    Range r[4];
+    ranges(m, r);
+    for (const Range& x : r) v.push_back({x, item});
+}
 
 inline size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

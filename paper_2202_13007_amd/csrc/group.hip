@@ -9,9 +9,7 @@
 // block and every tile, so each product is bit for bit blaz_matmul's.
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
 #include <cstring>
-#include <vector>
 
 #include "blaz_codec.hpp"
 #include "blaz_internal.hpp"
@@ -184,48 +182,25 @@ BLAZ_API blaz_status blaz_matmul_group_plan(const blaz_matmul_item* items, int64
         }
     }
 
-    // The products run concurrently, so no product's output may overlap
-    // another product's operands or output (operands may be shared).  The
-    // outputs, sorted by address, must be disjoint; then each operand array
-    // can overlap at most the last output that starts below its end.
+    // The products run concurrently: no product's output may overlap another
+    // product's operands or output (operands may be shared).
     {
-        struct Tagged {
-            Range r;
-            int64_t item;
-        };
         std::vector<Tagged> writes, reads;
         for (int64_t i = 0; i < n_items; ++i) {
             const blaz_matmul_item& it = items[i];
             const int64_t m = it.a.rows, k = it.a.cols, n = it.n;
             if (m == 0 || n == 0) continue;
             writes.push_back({span(it.c, dense_span(m, n, it.ldc)), i});
-            Range ra[4];
-            ranges(it.a, ra);
-            for (const Range& r : ra) reads.push_back({r, i});
-            if (it.b.rows != 0 || it.b.cols != 0) {
-                Range rb[4];
-                ranges(it.b, rb);
-                for (const Range& r : rb) reads.push_back({r, i});
-            } else if (it.bdense && k > 0) {
+            push_matrix(reads, it.a, i);
+            if (it.b.rows != 0 || it.b.cols != 0)
+                push_matrix(reads, it.b, i);
+            else if (it.bdense && k > 0)
                 reads.push_back({span(it.bdense, dense_span(k, n, it.ldb)), i});
-            }
         }
-        std::sort(writes.begin(), writes.end(), [](const Tagged& x, const Tagged& y) { return x.r.lo < y.r.lo; });
-        for (size_t q = 1; q < writes.size(); ++q)
-            if (overlap(writes[q - 1].r, writes[q].r)) {
-                info->rebuild_jobs = std::max(writes[q - 1].item, writes[q].item);
-                return BLAZ_ERR_ARG;
-            }
-        for (const Tagged& rd : reads) {
-            if (rd.r.hi == rd.r.lo) continue;
-            auto after = std::lower_bound(writes.begin(), writes.end(), rd.r.hi,
-                                          [](const Tagged& w, uintptr_t hi) { return w.r.lo < hi; });
-            if (after == writes.begin()) continue;
-            const Tagged& w = *(after - 1);
-            if (w.item != rd.item && overlap(w.r, rd.r)) {
-                info->rebuild_jobs = std::max(w.item, rd.item);
-                return BLAZ_ERR_ARG;
-            }
+        const int64_t bad = cross_item_conflict(writes, reads);
+        if (bad >= 0) {
+            info->rebuild_jobs = bad;
+            return BLAZ_ERR_ARG;
         }
     }
 

@@ -174,6 +174,29 @@ def test_plan_rejects_partial_overlap():
     assert st == -5 and n_plan == 0
 
 
+def test_plan_rejects_items_that_touch_another_items_output():
+    """The items of a batch run concurrently: an item writing another's
+    output, or reading it, is refused with the later item's index; items
+    sharing inputs are planned."""
+    x, y = fake_matrix(8, 64, 0x2000000), fake_matrix(8, 64, 0x3000000)
+    z, w = fake_matrix(8, 64, 0x4000000), fake_matrix(8, 64, 0x5000000)
+    first = item("add", x=x, y=y, z=z)
+    cases = [
+        item("scale", x=y, z=z, c=2.0),                                              # same output
+        item("scale", x=z, z=w, c=2.0),                                              # reads the output
+        item("decompress", x=fake_matrix(8, 8, 0x6000000), dense=0x4000000 + 64, ld=8),  # writes over it
+        item("dot", x=x, y=fake_matrix(64, 8, 0x7000000), xrow=0x4000000, ycol=0x7100000, count=4,
+             out=0x7200000),                                                         # indexes in it
+    ]
+    for later in cases:
+        st, n_plan, _ = plan([first, later])
+        assert st == -5 and n_plan == 1, (later.op, st, n_plan)
+    shared = [first, item("sub", x=x, y=y, z=w), item("dot", x=x, y=fake_matrix(64, 8, 0x7000000), xrow=0x7100000,
+                                                      ycol=0x7100000, count=4, out=0x7200000)]
+    st, n_plan, total = plan(shared)
+    assert st == 0 and n_plan == 3
+
+
 # --------------------------------------------------------------------------
 # GPU: batched results equal the standalone calls
 # --------------------------------------------------------------------------
