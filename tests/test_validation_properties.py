@@ -442,3 +442,85 @@ def test_dot_and_dot_dense_accept_exactly_what_the_rules_allow(L, args):
             ok = not (overlaps_desc(ro, x) or overlap(ro, rng8(xrow, count)) or overlap(ro, rv))
     check(L.blaz_dot_dense(ctypes.byref(cx), i64(xrow), i64(v), ldv, count, i64(out), None),
           expect(ok, count if ok else 0), "dot_dense")
+
+
+# Batches: items over a small pool of operands, so that items meet each other
+# often; the rule (no item reads or writes another item's output, inputs may
+# be shared) is checked by brute force over the pairs.
+POOL_X = [(1 << 40) + i * (1 << 20) for i in range(4)]      # compressed 8 x 64 records
+POOL_D = [(1 << 42) + i * (1 << 20) for i in range(2)]      # dense 8 x 64, ld 64
+POOL_I = [(1 << 44) + i * (1 << 20) for i in range(2)]      # index arrays
+POOL_O = [(1 << 45) + i * (1 << 20) for i in range(2)]      # dot outputs
+Y_DOT = (1 << 46)                                            # a read-only 64 x 8 record
+
+
+def pool_desc(base, rows=8, cols=64):
+    nb = (rows // 8) * (cols // 8)
+    return Desc(rows, cols, 0, base, base + 8 * nb + 64, base + 16 * nb + 128, base + 17 * nb + 256)
+
+
+@st.composite
+def batch_items(draw):
+    ops = []
+    for _ in range(draw(st.integers(1, 5))):
+        op = draw(st.sampled_from(["add", "scale", "compress", "decompress", "dot"]))
+        if op == "add":
+            ops.append(("add", dict(x=draw(st.sampled_from(POOL_X)), y=draw(st.sampled_from(POOL_X)),
+                                    z=draw(st.sampled_from(POOL_X)))))
+        elif op == "scale":
+            ops.append(("scale", dict(x=draw(st.sampled_from(POOL_X)), z=draw(st.sampled_from(POOL_X)))))
+        elif op in ("compress", "decompress"):
+            ops.append((op, dict(x=draw(st.sampled_from(POOL_X)), dense=draw(st.sampled_from(POOL_D)))))
+        else:
+            ops.append(("dot", dict(x=draw(st.sampled_from(POOL_X)), xrow=draw(st.sampled_from(POOL_I)),
+                                    ycol=draw(st.sampled_from(POOL_I)), out=draw(st.sampled_from(POOL_O)))))
+    return ops
+
+
+def batch_rw(op, a):
+    """(writes, reads) of an item as sets of pool addresses."""
+    if op == "add":
+        return {a["z"]}, {a["x"], a["y"]}
+    if op == "scale":
+        return {a["z"]}, {a["x"]}
+    if op == "compress":
+        return {a["x"]}, {a["dense"]}
+    if op == "decompress":
+        return {a["dense"]}, {a["x"]}
+    return {a["out"]}, {a["x"], a["xrow"], a["ycol"], Y_DOT}
+
+
+@SETTINGS
+@given(batch_items())
+def test_batch_plan_refuses_exactly_the_items_that_touch_another_items_output(L, ops):
+    from paper_2202_13007_amd import _lib
+    conflicts = set()
+    for j in range(len(ops)):
+        wj, rj = batch_rw(*ops[j])
+        for i in range(j):
+            wi, ri = batch_rw(*ops[i])
+            if wi & wj or wi & rj or ri & wj:
+                conflicts.add(j)
+    arr = (_lib.BatchItemC * len(ops))()
+    for it, (op, a) in zip(arr, ops):
+        it.op = _lib.OPS[op]
+        if op in ("add", "scale", "compress", "decompress", "dot"):
+            it.x = pool_desc(a["x"]).c()
+        if op == "add":
+            it.y, it.z = pool_desc(a["y"]).c(), pool_desc(a["z"]).c()
+        elif op == "scale":
+            it.z, it.c = pool_desc(a["z"]).c(), 1.5
+        elif op in ("compress", "decompress"):
+            it.dense, it.ld = a["dense"], 64
+        else:
+            it.y = pool_desc(Y_DOT, 64, 8).c()
+            it.xrow, it.ycol, it.out, it.count = a["xrow"], a["ycol"], a["out"], 4
+    nbytes = L.blaz_batch_plan_bytes(len(ops))
+    buf = (ctypes.c_uint8 * nbytes)()
+    n_plan, total = ctypes.c_int64(), ctypes.c_int64()
+    st_ = L.blaz_batch_plan(ctypes.cast(arr, ctypes.c_void_p), len(ops), ctypes.cast(buf, ctypes.c_void_p), nbytes,
+                            ctypes.byref(n_plan), ctypes.byref(total))
+    if conflicts:
+        assert st_ == -5 and n_plan.value in conflicts, (ops, st_, n_plan.value, conflicts)
+    else:
+        assert st_ == BLAZ_OK and n_plan.value == len(ops), (ops, st_, n_plan.value)
