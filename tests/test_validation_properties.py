@@ -524,3 +524,54 @@ def test_batch_plan_refuses_exactly_the_items_that_touch_another_items_output(L,
         assert st_ == -5 and n_plan.value in conflicts, (ops, st_, n_plan.value, conflicts)
     else:
         assert st_ == BLAZ_OK and n_plan.value == len(ops), (ops, st_, n_plan.value)
+
+
+# Grouped products over a small pool: A (8 x 64 records), B compressed
+# (64 x 8 records) or dense (64 x 8, ld 8), C (8 x 8, ld 8) from a pool that
+# also holds the dense B regions, so that outputs meet other products'
+# operands and outputs.
+POOL_A = POOL_X[:3]
+POOL_B = [(1 << 47) + i * (1 << 20) for i in range(2)]
+POOL_BD = [(1 << 48) + i * (1 << 20) for i in range(2)]
+POOL_C = [(1 << 49) + i * (1 << 20) for i in range(3)] + POOL_BD
+
+
+@st.composite
+def group_items(draw):
+    items = []
+    for _ in range(draw(st.integers(1, 5))):
+        a = draw(st.sampled_from(POOL_A))
+        if draw(st.booleans()):
+            b, bd = draw(st.sampled_from(POOL_B)), None
+        else:
+            b, bd = None, draw(st.sampled_from(POOL_BD))
+        c = draw(st.sampled_from([p for p in POOL_C if p != bd]))  # never over its own operands
+        items.append((a, b, bd, c))
+    return items
+
+
+@SETTINGS
+@given(group_items())
+def test_group_plan_refuses_exactly_the_products_that_touch_another_products_output(L, items):
+    from paper_2202_13007_amd import _lib
+    conflicts = set()
+    for j, (aj, bj, dj, cj) in enumerate(items):
+        for i in range(j):
+            ai, bi, di, ci = items[i]
+            if ci == cj or ci in (aj, bj, dj) or cj in (ai, bi, di):
+                conflicts.add(j)
+    arr = (_lib.MatmulItemC * len(items))()
+    for it, (a, b, bd, c) in zip(arr, items):
+        it.a = pool_desc(a).c()
+        it.b = pool_desc(b, 64, 8).c() if b is not None else _lib.BlazMatrixC(0, 0, None, None, None, None, 0)
+        it.bdense = bd
+        it.n, it.ldb, it.c, it.ldc, it.tile, it.reserved = 8, 8, c, 8, 64, 0
+    nbytes = L.blaz_matmul_group_plan_bytes(len(items))
+    buf = (ctypes.c_uint8 * nbytes)()
+    info = _lib.MatmulGroupInfoC()
+    st_ = L.blaz_matmul_group_plan(ctypes.cast(arr, ctypes.c_void_p), len(items), ctypes.c_void_p(1 << 50), 1 << 30,
+                                   ctypes.cast(buf, ctypes.c_void_p), nbytes, ctypes.byref(info))
+    if conflicts:
+        assert st_ == -5 and info.rebuild_jobs in conflicts, (items, st_, info.rebuild_jobs, conflicts)
+    else:
+        assert st_ == BLAZ_OK, (items, st_, info.rebuild_jobs)
