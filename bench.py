@@ -279,7 +279,13 @@ def matmul_leg(blaz, torch, workload_inputs):
     # operands: the MFMA work rate a single BF16 GEMM reaches on this part
     aB, bB = Ad.to(torch.bfloat16).contiguous(), dB.to(torch.bfloat16).contiguous()
     runs.append(("vendor_bf16", lambda: torch.mm(aB, bB, out_dtype=torch.float32)))
-    peaks = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3, "plain": 78.6, "vendor_bf16": 2500.0}
+    # and its FP32 GEMM (no reduced-precision inner products)
+    tf32 = torch.backends.cuda.matmul.allow_tf32
+    torch.backends.cuda.matmul.allow_tf32 = False
+    aF, bF = Ad.float(), dB.float()
+    runs.append(("vendor_fp32", lambda: torch.mm(aF, bF)))
+    peaks = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3, "plain": 78.6, "vendor_bf16": 2500.0,
+             "vendor_fp32": 157.3}
     # three interleaved rounds of 5 back-to-back launches per variant, median
     # round: the clock drifts with the power draw of FP64 matrix work, so a
     # fixed order would favour whichever variant runs in the better state
@@ -326,7 +332,11 @@ def matmul_leg(blaz, torch, workload_inputs):
     legs["vendor_bf16"]["what"] = ("one BF16 x BF16 -> FP32 product of the rounded operands by the vendor library "
                                    "(torch.mm): the MFMA work rate of a plain BF16 GEMM, for reference")
     legs["bf16x3"]["mfma_work_vs_vendor_bf16"] = round(3 * legs["bf16x3"]["TFLOPs"] / legs["vendor_bf16"]["TFLOPs"], 4)
-    del outs, exact, ws, aB, bB
+    legs["vendor_fp32"]["what"] = "the vendor library's FP32 GEMM (torch.mm, TF32 off) of the same operands in FP32"
+    legs["fp32"]["vs_vendor_fp32"] = round(legs["fp32"]["TFLOPs"] / legs["vendor_fp32"]["TFLOPs"], 4)
+    legs["fp64"]["vs_vendor_fp64"] = round(legs["fp64"]["TFLOPs"] / legs["plain"]["TFLOPs"], 4)
+    torch.backends.cuda.matmul.allow_tf32 = tf32
+    del outs, exact, ws, aB, bB, aF, bF
     return {"legs": legs, "method_rel_err": float(f"{method:.3e}"),
             "note": "TFLOPs count 2 n^3 useful flops; times include decompressing A and preparing B",
             "dots": dot_leg(blaz, torch, g, Ad, dB, torch.from_numpy(Vm).cuda())}
