@@ -55,7 +55,7 @@ typedef enum {
                                   above 2^27 - 8, bad enum, overlap, an array or
                                   operand whose extent passes the top of the address
                                   space)                                             */
-    BLAZ_ERR_UNSUPPORTED = -6, /* a valid request this build does not implement        */
+    BLAZ_ERR_UNSUPPORTED = -6, /* a valid request the library does not implement       */
     BLAZ_ERR_WORKSPACE = -7,   /* workspace missing or smaller than required           */
     BLAZ_ERR_HIP = -8,         /* the HIP runtime reported an error                    */
     BLAZ_ERR_TOO_LARGE = -9    /* blaz_matmul_static: the product's workspace exceeds

@@ -436,7 +436,7 @@ BLAZ_API const char* blaz_status_string(blaz_status status)
         case BLAZ_ERR_MISMATCH: return "operand shapes do not agree";
         case BLAZ_ERR_ALIGN: return "a pointer or leading dimension is not suitably aligned";
         case BLAZ_ERR_ARG: return "invalid argument (count, enum value, or overlapping buffers)";
-        case BLAZ_ERR_UNSUPPORTED: return "request not supported by this build";
+        case BLAZ_ERR_UNSUPPORTED: return "request not supported by the library";
         case BLAZ_ERR_WORKSPACE: return "workspace missing or too small";
         case BLAZ_ERR_HIP: return "the HIP runtime reported an error";
         case BLAZ_ERR_TOO_LARGE:
