@@ -210,10 +210,8 @@ def dense_args(draw):
     return m, A, lda, psi, prec
 
 
-@SETTINGS
-@given(dense_args())
-def test_compress_accepts_exactly_what_the_rules_allow(L, args):
-    m, A, lda, psi, prec = args
+def compress_model(m, A, lda, psi, prec):
+    """Whether blaz_compress's rules accept the call, and its block count."""
     ok = m.valid() and prec in (0, 1, 2)
     lines = 2 if m.lines == 0 else m.lines
     if ok and lines != 2 and (prec != 0 or psi is not None):
@@ -227,10 +225,22 @@ def test_compress_accepts_exactly_what_the_rules_allow(L, args):
             if ok and psi is not None:
                 rp = (psi, psi + 64 * n)
                 ok = not overlap(rp, ra) and not overlaps_desc(rp, m)
-    want = expect(ok, n)
+    return ok, n
+
+
+@SETTINGS
+@given(dense_args())
+def test_compress_accepts_exactly_what_the_rules_allow(L, args):
+    m, A, lda, psi, prec = args
+    ok, n = compress_model(m, A, lda, psi, prec)
     cm = m.c()
-    check(L.blaz_compress(ctypes.c_void_p(A), lda, ctypes.byref(cm), prec, ctypes.c_void_p(psi), None), want,
-          f"compress prec {prec}")
+    check(L.blaz_compress(ctypes.c_void_p(A), lda, ctypes.byref(cm), prec, ctypes.c_void_p(psi), None),
+          expect(ok, n if ok else 0), f"compress prec {prec}")
+    # the predicted-slope input: the binary64 rules, two kept lines only
+    ok, n = compress_model(m, A, lda, psi, 0)
+    ok = ok and m.valid() and (2 if m.lines == 0 else m.lines) == 2
+    check(L.blaz_compress_predicted(ctypes.c_void_p(A), lda, ctypes.byref(cm), ctypes.c_void_p(psi), None),
+          expect(ok, n if ok else 0), "compress_predicted")
 
 
 @SETTINGS
