@@ -585,3 +585,43 @@ def test_group_plan_refuses_exactly_the_products_that_touch_another_products_out
         assert st_ == -5 and info.rebuild_jobs in conflicts, (items, st_, info.rebuild_jobs, conflicts)
     else:
         assert st_ == BLAZ_OK, (items, st_, info.rebuild_jobs)
+
+
+@SETTINGS
+@given(matmul_args(), st.sampled_from(["apart", "apart", "apart", "over_a", "over_b", "over_ws", "shape", "lines3"]))
+def test_matmul_compressed_accepts_exactly_what_the_rules_allow(L, args, cplace):
+    """The product recompressed: the operands and workspace drawn as for
+    blaz_matmul_tiled, the output a descriptor placed apart, over A, over B
+    (compressed or dense) or over the workspace, or of the wrong shape."""
+    a, b, bdense, n, ldb, _, _, prec, ws, short, tile = args
+    m, k = a.rows, a.cols
+    cbase = {"over_a": a.ptrs[2], "over_b": (b.ptrs[0] if b is not None else bdense),
+             "over_ws": (ws + 512) if ws else None}.get(cplace) or (1 << 51)
+    c = Desc(m + (8 if cplace == "shape" else 0), n, 3 if cplace == "lines3" else 0,
+             cbase, cbase + 8 * (1 << 16), cbase + 16 * (1 << 16), cbase + 17 * (1 << 16))
+    p = prec if prec in (0, 1, 2) else 0
+    need = L.blaz_matmul_compressed_workspace_bytes(m, n, k, int(b is not None), p)
+    ws_bytes = max(need - short, 0)
+    ok = tile in (0, 64, 128) and a.valid() and c.valid() and prec in (0, 1, 2)
+    ok = ok and not (b is not None and bdense is not None) and not (b is None and bdense is None and k > 0)
+    if ok and b is not None:
+        ok = b.valid() and b.rows == k and b.cols == n
+    ok = ok and n >= 0 and n % 8 == 0 and c.rows == m and c.cols == n
+    launches = ok and m > 0 and n > 0
+    if launches:
+        if b is None and k > 0:
+            ok = ldb >= n and bdense % 16 == 0 and ldb % 2 == 0
+        ok = ok and ws is not None and ws_bytes >= need and ws % 256 == 0
+        if ok:
+            rw = (ws, ws + need)
+            ins = a.ranges() + (b.ranges() if b is not None else []) + \
+                ([dense_span(bdense, k, n, ldb)] if bdense is not None else [])
+            ok = not overlaps_desc(rw, c) and not any(overlap(rw, q) for q in ins) and \
+                not any(overlap(r, q) for r in c.ranges() for q in ins)
+        launches = ok
+    ca, cc = a.c(), c.c()
+    cb = b.c() if b is not None else None
+    st_ = L.blaz_matmul_compressed(ctypes.byref(ca), ctypes.byref(cb) if cb is not None else None,
+                                   ctypes.c_void_p(bdense), n, ldb, ctypes.byref(cc), prec, ctypes.c_void_p(ws),
+                                   ws_bytes, tile, None)
+    check(st_, (BLAZ_ERR_HIP if launches else BLAZ_OK) if ok else None, f"matmul_compressed {cplace}")
