@@ -44,7 +44,9 @@ def make_matrix(structure, seed, br, bc):
     return np.cumsum(rng.standard_normal((r, c)), axis=1) * np.where((np.arange(c) // 8) % 2, -1.0, 1.0)
 
 
-matrices = st.tuples(st.sampled_from(STRUCTURES), st.integers(0, 2 ** 32 - 1), st.integers(1, 3), st.integers(1, 3))
+# 1..9 blocks per side: up to 81 blocks, more than one 64-block wave with a
+# ragged last one
+matrices = st.tuples(st.sampled_from(STRUCTURES), st.integers(0, 2 ** 32 - 1), st.integers(1, 9), st.integers(1, 9))
 CPU = settings(max_examples=60, deadline=None, database=None, suppress_health_check=[HealthCheck.too_slow])
 
 
