@@ -625,3 +625,17 @@ def test_matmul_compressed_accepts_exactly_what_the_rules_allow(L, args, cplace)
                                    ctypes.c_void_p(bdense), n, ldb, ctypes.byref(cc), prec, ctypes.c_void_p(ws),
                                    ws_bytes, tile, None)
     check(st_, (BLAZ_ERR_HIP if launches else BLAZ_OK) if ok else None, f"matmul_compressed {cplace}")
+
+
+@SETTINGS
+@given(descriptor(), st.sampled_from(["apart", "apart", "over", "misaligned", "null"]))
+def test_diagnose_accepts_exactly_what_the_rules_allow(L, x, where):
+    """blaz_diagnose: a valid record and, when it holds blocks, four 8-byte
+    aligned counters apart from it."""
+    cnt = {"apart": 1 << 50, "over": x.ptrs[1], "misaligned": (1 << 50) + 4, "null": None}[where]
+    ok = x.valid()
+    n = x.nblk() if ok else 0
+    if ok and n:
+        ok = bool(cnt) and cnt % 8 == 0 and not overlaps_desc((cnt, cnt + 32), x)
+    cx = x.c()
+    check(L.blaz_diagnose(ctypes.byref(cx), ctypes.c_void_p(cnt), None), expect(ok, n if ok else 0), "diagnose")
