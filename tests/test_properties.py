@@ -9,6 +9,8 @@ product.
 Inputs are drawn per example from a structure (Gaussian, a single non-zero
 per block, constant blocks, affine ramps, huge or tiny magnitudes, mixed
 signs of slope) and a seed; hypothesis shrinks over those two choices."""
+import os
+
 import numpy as np
 import pytest
 from hypothesis import HealthCheck, example, given, settings
@@ -47,7 +49,10 @@ def make_matrix(structure, seed, br, bc):
 # 1..9 blocks per side: up to 81 blocks, more than one 64-block wave with a
 # ragged last one
 matrices = st.tuples(st.sampled_from(STRUCTURES), st.integers(0, 2 ** 32 - 1), st.integers(1, 9), st.integers(1, 9))
-CPU = settings(max_examples=60, deadline=None, database=None, suppress_health_check=[HealthCheck.too_slow])
+# Derandomized (the same draws on every run) unless BLAZ_PROPERTY_EXPLORE is
+# set, which draws afresh.
+CPU = settings(max_examples=60, deadline=None, database=None, suppress_health_check=[HealthCheck.too_slow],
+               derandomize=not os.environ.get("BLAZ_PROPERTY_EXPLORE"))
 
 
 @CPU
@@ -113,9 +118,8 @@ def _boundary_values(code_x, phi_x):
         return int((near_integer(code_x) & (code_x != 0)).sum() + near_integer(phi_x).sum())
 
 
-# The GPU draws are derandomized (the same 40 examples on every run) so that
-# a GPU run is reproducible; the CPU properties above draw afresh each time.
-GPU = settings(max_examples=40, deadline=None, database=None, derandomize=True,
+# The GPU draws are derandomized too (the same 40 examples on every run).
+GPU = settings(max_examples=40, deadline=None, database=None, derandomize=not os.environ.get("BLAZ_PROPERTY_EXPLORE"),
                suppress_health_check=[HealthCheck.too_slow])
 
 

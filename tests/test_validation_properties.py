@@ -6,6 +6,7 @@ there are no blocks); a call they reject must return another error before
 anything is enqueued.  The addresses are fake and never dereferenced, so
 the tests are skipped where a GPU is present."""
 import ctypes
+import os
 
 import pytest
 from hypothesis import HealthCheck, given, settings
@@ -14,7 +15,10 @@ from hypothesis import strategies as st
 BLAZ_OK, BLAZ_ERR_HIP = 0, -8
 MAX_BLOCKS = (1 << 32) - 256
 TOP = 1 << 64  # addresses are unsigned 64-bit; an extent reaching TOP wraps
-SETTINGS = settings(max_examples=500, deadline=None, database=None, suppress_health_check=[HealthCheck.too_slow])
+# Derandomized (the same draws on every run) unless BLAZ_PROPERTY_EXPLORE is
+# set, which draws afresh.
+SETTINGS = settings(max_examples=500, deadline=None, database=None, suppress_health_check=[HealthCheck.too_slow],
+                    derandomize=not os.environ.get("BLAZ_PROPERTY_EXPLORE"))
 
 
 @pytest.fixture(scope="module")
