@@ -12,7 +12,8 @@
 // workgroups pops chunk indices from an atomic counter, finds the item by
 // binary search and runs the same device body as the standalone kernel, until
 // the counter passes the end of the queue.  Every wave reaches that exit, so
-// the grid always drains.
+// the grid always drains.  Chunks of different items run at the same time, so
+// the plan refuses items that read or write another item's output.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
